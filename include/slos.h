@@ -1,0 +1,205 @@
+/*
+ * slos.h -- C ABI of the MI355X (gfx950) strong-simulation library.
+ *
+ * The library computes, for n photons in m modes of a linear-optical
+ * interferometer with unitary U, every output Fock amplitude
+ *
+ *     a_t = Perm(U[R(t), C(s)]) / sqrt(prod_i s_i! prod_j t_j!)
+ *
+ * (arXiv 2602.11092, Sec. II-A-1: output probabilities are permanents of
+ * sub-matrices of U up to normalisation; the Fock space has C(m+n-1, n)
+ * states), by the photon-by-photon recursion of Sec. II-A-2/II-A-3: starting
+ * from one photon, the k-photon state is built from the (k-1)-photon state
+ * through a transition graph that depends only on (m, k), while only the
+ * coefficients taken from U change between calls.  The graph is built once
+ * per plan (Sec. II-A-3, "prebuilding the sparse transition graph once").
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Complex numbers are interleaved float pairs (re, im), i.e. the memory
+ *   layout of complex64 / float2.  Pointers typed `float*` that hold complex
+ *   data say so in their comment.
+ * - U is row-major [B][m][m] with U[b][j][i] = amplitude for a photon entering
+ *   mode i to leave in mode j (a single photon in mode i gives p_j = |U[j][i]|^2).
+ * - Fock basis order: lexicographic order of the sorted list of occupied
+ *   modes; |n,0,...,0> has rank 0, |0,...,0,n> rank C(m+n-1,n)-1.
+ *   slos_fock_unrank / slos_fock_rank are the reference for this order.
+ * - Batches may mix photon numbers.  Sample b's outputs occupy
+ *   out[off_b .. off_b + C(m+n_b-1, n_b)) with off_b the exclusive prefix sum
+ *   of the per-sample Fock dimensions (slos_batch_out_offsets).
+ * - Gradients follow the convention G = dL/dRe + i dL/dIm of a real loss L
+ *   (the one PyTorch uses).  Backward calls OVERWRITE their gradient outputs.
+ * - Ownership: the caller allocates every device buffer passed to a compute
+ *   call (inputs, outputs, workspace).  The library allocates device memory
+ *   only in slos_plan_create and slos_batch_create, and frees it in the
+ *   matching destroy call.
+ * - Compute calls are asynchronous and ordered on `stream` (a hipStream_t
+ *   passed as void*; NULL = the default stream).  They neither synchronise
+ *   nor allocate, so they may be captured into a HIP graph.  The caller keeps
+ *   inputs alive and does not read outputs until the stream has reached them.
+ * - Errors: every call returns SLOS_OK (0) or a negative status.  Argument
+ *   errors are detected on the host before anything is enqueued, so a failed
+ *   call leaves all buffers untouched.  slos_last_error() gives a message for
+ *   the calling thread's most recent failure.
+ * - Thread safety: plans and batches are read-only after creation and may be
+ *   used from several host threads and streams at once, provided each
+ *   concurrent call has its own workspace.
+ */
+#ifndef SLOS_H
+#define SLOS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SLOS_OK 0
+#define SLOS_EINVAL (-1)        /* bad argument (null pointer, bad size, bad occupation) */
+#define SLOS_ENOMEM (-2)        /* device or host allocation failed (create calls only) */
+#define SLOS_EHIP (-3)          /* a HIP runtime call or kernel launch failed */
+#define SLOS_EWORKSPACE (-4)    /* workspace pointer null or smaller than required */
+#define SLOS_EUNSUPPORTED (-5)  /* valid request outside what this plan/build supports */
+
+/* Limits of this build. */
+#define SLOS_MAX_MODES 32
+#define SLOS_MAX_PHOTONS 16
+
+/* Operation codes for slos_workspace_bytes / slos_batch_set_config. */
+#define SLOS_OP_AMPLITUDES 0
+#define SLOS_OP_PROBS 1
+#define SLOS_OP_AMPLITUDES_BACKWARD 2
+#define SLOS_OP_PROBS_BACKWARD 3
+
+/* Plan flags. */
+#define SLOS_PLAN_DEFAULT 0
+#define SLOS_PLAN_FORWARD_ONLY 1  /* skip the successor tables; backward calls return SLOS_EUNSUPPORTED */
+
+/* Kernel variants for slos_batch_set_config. */
+#define SLOS_VARIANT_AUTO 0    /* library heuristic (or the last value set) */
+#define SLOS_VARIANT_FUSED 1   /* one persistent launch; each workgroup keeps a sample's photon layers in LDS */
+#define SLOS_VARIANT_LAYERED 2 /* one launch per photon layer; layers kept in the workspace (any size) */
+
+typedef struct slos_plan_s* slos_plan_t;
+typedef struct slos_batch_s* slos_batch_t;
+
+/* ---- Fock-space combinatorics (host only, no device work) ---------------- */
+
+/* C(m+n-1, n), the dimension of the n-photon Fock space over m modes
+ * (Sec. II-A-1).  Returns -1 if m < 1, n < 0 or the value overflows int64. */
+int64_t slos_fock_dim(int m, int n);
+
+/* Occupation vector (occ[0..m-1], host) of the state of the given rank in
+ * the basis order above.  Returns SLOS_EINVAL for a bad m, n, rank or NULL. */
+int slos_fock_unrank(int m, int n, int64_t rank, int32_t* occ);
+
+/* Rank of an occupation vector (host, m entries summing to n); -1 if invalid. */
+int64_t slos_fock_rank(int m, int n, const int32_t* occ);
+
+/* Message for the calling thread's most recent failed call ("" if none). */
+const char* slos_last_error(void);
+
+/* ---- Plans: transition graph for (m, n <= n_max) ------------------------- */
+
+/* Builds, once, the transition graph of Sec. II-A-3 for every photon layer
+ * k = 1..n_max over m modes and uploads it to the current HIP device:
+ * predecessor lists (which (k-1)-photon states feed each k-photon state, and
+ * through which output mode), successor tables (the reverse map, for the
+ * backward pass), and sqrt(prod_j t_j!) per state.  Synchronous; allocates.
+ * m in [1, SLOS_MAX_MODES], n_max in [1, SLOS_MAX_PHOTONS].
+ * Returns SLOS_EINVAL, SLOS_ENOMEM, SLOS_EHIP or SLOS_OK (*out set). */
+int slos_plan_create(int m, int n_max, int flags, slos_plan_t* out);
+int slos_plan_destroy(slos_plan_t plan);  /* NULL is accepted; waits for the device */
+
+/* ---- Batches: the input states of one call's samples --------------------- */
+
+/* Describes B samples with input occupation vectors occ_host[b*m .. b*m+m-1]
+ * (host memory, each entry >= 0, sum n_b in [0, n_max]).  Validates them,
+ * derives per-sample photon lists, normalisation 1/sqrt(prod s!), output
+ * offsets and a longest-first work order, and uploads them (synchronous,
+ * allocates).  The batch keeps a reference to `plan`; destroy the batch first. */
+int slos_batch_create(slos_plan_t plan, int B, const int32_t* occ_host, slos_batch_t* out);
+int slos_batch_destroy(slos_batch_t batch);
+
+/* Total number of outputs (sum of the per-sample Fock dimensions), or -1. */
+int64_t slos_batch_out_len(slos_batch_t batch);
+
+/* Writes the B+1 output offsets into off_host (host memory). */
+int slos_batch_out_offsets(slos_batch_t batch, int64_t* off_host);
+
+/* Device workspace needed by `op` on this batch with its current
+ * configuration (0 is possible).  *bytes receives the size. */
+int slos_workspace_bytes(slos_batch_t batch, int op, size_t* bytes);
+
+/* Chooses the kernel variant and workgroup size used for `op` on this batch
+ * (the autotuner's hook).  block = 0 keeps the library's choice.  Returns
+ * SLOS_EUNSUPPORTED if the variant cannot run this batch (the fused variant
+ * needs a sample's photon layers to fit in LDS). */
+int slos_batch_set_config(slos_batch_t batch, int op, int variant, int block);
+
+/* Reads back the configuration in use for `op` (variant, block). */
+int slos_batch_get_config(slos_batch_t batch, int op, int* variant, int* block);
+
+/* ---- Forward: amplitudes and probabilities (Sec. II-A-1/2/3, Sec. II-B) --- */
+
+/* amps (device, complex, [out_len]) <- a_t for every sample and output state.
+ * U (device, complex, [B][m][m]).  ws: device workspace of at least
+ * slos_workspace_bytes(batch, SLOS_OP_AMPLITUDES) bytes (may be NULL if 0). */
+int fock_amplitudes(slos_batch_t batch, const float* U, float* amps,
+                    void* ws, size_t ws_bytes, void* stream);
+
+/* probs (device, float, [out_len]) <- |a_t|^2 (no renormalisation). */
+int fock_probs(slos_batch_t batch, const float* U, float* probs,
+               void* ws, size_t ws_bytes, void* stream);
+
+/* ---- Backward (adjoint of the recursion; intermediate photon layers are
+ *      recomputed, not stored, so calls are stateless) --------------------- */
+
+/* grad_U (device, complex, [B][m][m]) <- dL/dU given grad_amps = dL/da
+ * (device, complex, [out_len]).  Columns of U that carry no input photon get
+ * zero gradient. */
+int fock_amplitudes_backward(slos_batch_t batch, const float* U, const float* grad_amps,
+                             float* grad_U, void* ws, size_t ws_bytes, void* stream);
+
+/* grad_U (device, complex, [B][m][m]) <- dL/dU given grad_probs = dL/dp
+ * (device, float, [out_len]). */
+int fock_probs_backward(slos_batch_t batch, const float* U, const float* grad_probs,
+                        float* grad_U, void* ws, size_t ws_bytes, void* stream);
+
+/* ---- Interferometer mesh U(x, theta) (Sec. II-A-3, Sec. II-C-1) ---------- */
+/*
+ * Rectangular mesh of m(m-1)/2 Mach-Zehnder interferometers.  Column
+ * c = 0..m-1 holds MZIs on mode pairs (k, k+1), k = c mod 2, c mod 2 + 2, ...,
+ * k <= m-2.  MZI(theta, phi) = BS . PS(theta) . BS . PS(phi) with
+ * BS = (1/sqrt2)[[1, i], [i, 1]] and PS(a) = diag(exp(i a), 1) on the upper
+ * mode.  theta (device, float, [m(m-1)]) holds (theta_q, phi_q) per MZI,
+ * MZIs ordered column-major, top-down.  The mesh is split after column
+ * m/2 - 1 into W1 (columns < m/2) and W2, and the angle-encoding layer sits
+ * between them (Sec. II-C-1, U(x, theta) = W2 S(x) W1):
+ *
+ *     U_b = W2 diag(exp(i * enc_scale * x[b][:])) W1,
+ *
+ * or U = W2 W1 (B must be 1) when x is NULL.
+ */
+
+/* Workspace for the mesh calls (both directions). */
+int mesh_workspace_bytes(int m, int B, size_t* bytes);
+
+/* U (device, complex, [B][m][m]) <- U(x_b, theta).  x: device [B][m] or NULL. */
+int mesh_to_unitary(int m, int B, const float* theta, const float* x, float enc_scale,
+                    float* U, void* ws, size_t ws_bytes, void* stream);
+
+/* grad_theta (device, float, [m(m-1)]) and grad_x (device, float, [B][m],
+ * may be NULL; must be NULL when x is NULL) <- gradients of a real loss given
+ * grad_U (device, complex, [B][m][m]).  The reduction over the batch is done
+ * in a fixed order (bitwise reproducible). */
+int mesh_to_unitary_backward(int m, int B, const float* theta, const float* x, float enc_scale,
+                             const float* grad_U, float* grad_theta, float* grad_x,
+                             void* ws, size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SLOS_H */
