@@ -51,6 +51,10 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#ifndef SLOS_API
+#define SLOS_API __attribute__((visibility("default")))
+#endif
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -88,17 +92,29 @@ typedef struct slos_batch_s* slos_batch_t;
 
 /* C(m+n-1, n), the dimension of the n-photon Fock space over m modes
  * (Sec. II-A-1).  Returns -1 if m < 1, n < 0 or the value overflows int64. */
-int64_t slos_fock_dim(int m, int n);
+SLOS_API int64_t slos_fock_dim(int m, int n);
 
 /* Occupation vector (occ[0..m-1], host) of the state of the given rank in
  * the basis order above.  Returns SLOS_EINVAL for a bad m, n, rank or NULL. */
-int slos_fock_unrank(int m, int n, int64_t rank, int32_t* occ);
+SLOS_API int slos_fock_unrank(int m, int n, int64_t rank, int32_t* occ);
 
 /* Rank of an occupation vector (host, m entries summing to n); -1 if invalid. */
-int64_t slos_fock_rank(int m, int n, const int32_t* occ);
+SLOS_API int64_t slos_fock_rank(int m, int n, const int32_t* occ);
+
+/* Host copy of the transition graph of photon layer k (1 <= k <= 16) over m
+ * modes, the tables a plan uploads (host only, no device work; for
+ * inspection and tests).  Each output may be NULL.  Sizes, N_k = C(m+k-1,k):
+ *   pred   [k][N_k]      (rank of t - e_j in layer k-1) << 5 | j for the p-th
+ *                        entry of t's sorted mode list; -1 where that entry
+ *                        repeats the previous one;
+ *   succ   [m][N_{k-1}]  rank in layer k of t' + e_j;
+ *   nrm    [N_k]         sqrt(prod_j t_j!);
+ *   minoff [m+1]         first rank of layer k whose smallest occupied mode is >= c.
+ * Returns SLOS_EINVAL for bad m or k, SLOS_EUNSUPPORTED if N_k >= 2^26. */
+SLOS_API int slos_transition_tables(int m, int k, int32_t* pred, int32_t* succ, float* nrm, int32_t* minoff);
 
 /* Message for the calling thread's most recent failed call ("" if none). */
-const char* slos_last_error(void);
+SLOS_API const char* slos_last_error(void);
 
 /* ---- Plans: transition graph for (m, n <= n_max) ------------------------- */
 
@@ -109,8 +125,8 @@ const char* slos_last_error(void);
  * backward pass), and sqrt(prod_j t_j!) per state.  Synchronous; allocates.
  * m in [1, SLOS_MAX_MODES], n_max in [1, SLOS_MAX_PHOTONS].
  * Returns SLOS_EINVAL, SLOS_ENOMEM, SLOS_EHIP or SLOS_OK (*out set). */
-int slos_plan_create(int m, int n_max, int flags, slos_plan_t* out);
-int slos_plan_destroy(slos_plan_t plan);  /* NULL is accepted; waits for the device */
+SLOS_API int slos_plan_create(int m, int n_max, int flags, slos_plan_t* out);
+SLOS_API int slos_plan_destroy(slos_plan_t plan);  /* NULL is accepted; waits for the device */
 
 /* ---- Batches: the input states of one call's samples --------------------- */
 
@@ -119,38 +135,38 @@ int slos_plan_destroy(slos_plan_t plan);  /* NULL is accepted; waits for the dev
  * derives per-sample photon lists, normalisation 1/sqrt(prod s!), output
  * offsets and a longest-first work order, and uploads them (synchronous,
  * allocates).  The batch keeps a reference to `plan`; destroy the batch first. */
-int slos_batch_create(slos_plan_t plan, int B, const int32_t* occ_host, slos_batch_t* out);
-int slos_batch_destroy(slos_batch_t batch);
+SLOS_API int slos_batch_create(slos_plan_t plan, int B, const int32_t* occ_host, slos_batch_t* out);
+SLOS_API int slos_batch_destroy(slos_batch_t batch);
 
 /* Total number of outputs (sum of the per-sample Fock dimensions), or -1. */
-int64_t slos_batch_out_len(slos_batch_t batch);
+SLOS_API int64_t slos_batch_out_len(slos_batch_t batch);
 
 /* Writes the B+1 output offsets into off_host (host memory). */
-int slos_batch_out_offsets(slos_batch_t batch, int64_t* off_host);
+SLOS_API int slos_batch_out_offsets(slos_batch_t batch, int64_t* off_host);
 
 /* Device workspace needed by `op` on this batch with its current
  * configuration (0 is possible).  *bytes receives the size. */
-int slos_workspace_bytes(slos_batch_t batch, int op, size_t* bytes);
+SLOS_API int slos_workspace_bytes(slos_batch_t batch, int op, size_t* bytes);
 
 /* Chooses the kernel variant and workgroup size used for `op` on this batch
  * (the autotuner's hook).  block = 0 keeps the library's choice.  Returns
  * SLOS_EUNSUPPORTED if the variant cannot run this batch (the fused variant
  * needs a sample's photon layers to fit in LDS). */
-int slos_batch_set_config(slos_batch_t batch, int op, int variant, int block);
+SLOS_API int slos_batch_set_config(slos_batch_t batch, int op, int variant, int block);
 
 /* Reads back the configuration in use for `op` (variant, block). */
-int slos_batch_get_config(slos_batch_t batch, int op, int* variant, int* block);
+SLOS_API int slos_batch_get_config(slos_batch_t batch, int op, int* variant, int* block);
 
 /* ---- Forward: amplitudes and probabilities (Sec. II-A-1/2/3, Sec. II-B) --- */
 
 /* amps (device, complex, [out_len]) <- a_t for every sample and output state.
  * U (device, complex, [B][m][m]).  ws: device workspace of at least
  * slos_workspace_bytes(batch, SLOS_OP_AMPLITUDES) bytes (may be NULL if 0). */
-int fock_amplitudes(slos_batch_t batch, const float* U, float* amps,
+SLOS_API int fock_amplitudes(slos_batch_t batch, const float* U, float* amps,
                     void* ws, size_t ws_bytes, void* stream);
 
 /* probs (device, float, [out_len]) <- |a_t|^2 (no renormalisation). */
-int fock_probs(slos_batch_t batch, const float* U, float* probs,
+SLOS_API int fock_probs(slos_batch_t batch, const float* U, float* probs,
                void* ws, size_t ws_bytes, void* stream);
 
 /* ---- Backward (adjoint of the recursion; intermediate photon layers are
@@ -159,12 +175,12 @@ int fock_probs(slos_batch_t batch, const float* U, float* probs,
 /* grad_U (device, complex, [B][m][m]) <- dL/dU given grad_amps = dL/da
  * (device, complex, [out_len]).  Columns of U that carry no input photon get
  * zero gradient. */
-int fock_amplitudes_backward(slos_batch_t batch, const float* U, const float* grad_amps,
+SLOS_API int fock_amplitudes_backward(slos_batch_t batch, const float* U, const float* grad_amps,
                              float* grad_U, void* ws, size_t ws_bytes, void* stream);
 
 /* grad_U (device, complex, [B][m][m]) <- dL/dU given grad_probs = dL/dp
  * (device, float, [out_len]). */
-int fock_probs_backward(slos_batch_t batch, const float* U, const float* grad_probs,
+SLOS_API int fock_probs_backward(slos_batch_t batch, const float* U, const float* grad_probs,
                         float* grad_U, void* ws, size_t ws_bytes, void* stream);
 
 /* ---- Interferometer mesh U(x, theta) (Sec. II-A-3, Sec. II-C-1) ---------- */
@@ -184,17 +200,17 @@ int fock_probs_backward(slos_batch_t batch, const float* U, const float* grad_pr
  */
 
 /* Workspace for the mesh calls (both directions). */
-int mesh_workspace_bytes(int m, int B, size_t* bytes);
+SLOS_API int mesh_workspace_bytes(int m, int B, size_t* bytes);
 
 /* U (device, complex, [B][m][m]) <- U(x_b, theta).  x: device [B][m] or NULL. */
-int mesh_to_unitary(int m, int B, const float* theta, const float* x, float enc_scale,
+SLOS_API int mesh_to_unitary(int m, int B, const float* theta, const float* x, float enc_scale,
                     float* U, void* ws, size_t ws_bytes, void* stream);
 
 /* grad_theta (device, float, [m(m-1)]) and grad_x (device, float, [B][m],
  * may be NULL; must be NULL when x is NULL) <- gradients of a real loss given
  * grad_U (device, complex, [B][m][m]).  The reduction over the batch is done
  * in a fixed order (bitwise reproducible). */
-int mesh_to_unitary_backward(int m, int B, const float* theta, const float* x, float enc_scale,
+SLOS_API int mesh_to_unitary_backward(int m, int B, const float* theta, const float* x, float enc_scale,
                              const float* grad_U, float* grad_theta, float* grad_x,
                              void* ws, size_t ws_bytes, void* stream);
 

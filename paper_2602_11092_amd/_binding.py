@@ -1,0 +1,362 @@
+"""ctypes binding of libslos_hip.so (the C ABI declared in include/slos.h).
+
+Argument marshalling only: every computation runs in the library's HIP
+kernels.  PyTorch tensors provide device memory and the current stream.  The
+library must be built (python -m paper_2602_11092_amd.build_lib); there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Tuple
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libslos_hip.so")
+
+SLOS_OK = 0
+SLOS_EINVAL = -1
+SLOS_ENOMEM = -2
+SLOS_EHIP = -3
+SLOS_EWORKSPACE = -4
+SLOS_EUNSUPPORTED = -5
+
+OP_AMPLITUDES = 0
+OP_PROBS = 1
+OP_AMPLITUDES_BACKWARD = 2
+OP_PROBS_BACKWARD = 3
+
+PLAN_DEFAULT = 0
+PLAN_FORWARD_ONLY = 1
+
+VARIANT_AUTO = 0
+VARIANT_FUSED = 1
+VARIANT_LAYERED = 2
+
+# every symbol the header declares, with (restype, argtypes)
+_c = ctypes
+_vp = _c.c_void_p
+SIGNATURES = {
+    "slos_fock_dim": (_c.c_int64, [_c.c_int, _c.c_int]),
+    "slos_fock_unrank": (_c.c_int, [_c.c_int, _c.c_int, _c.c_int64, _vp]),
+    "slos_fock_rank": (_c.c_int64, [_c.c_int, _c.c_int, _vp]),
+    "slos_last_error": (_c.c_char_p, []),
+    "slos_transition_tables": (_c.c_int, [_c.c_int, _c.c_int, _vp, _vp, _vp, _vp]),
+    "slos_plan_create": (_c.c_int, [_c.c_int, _c.c_int, _c.c_int, _c.POINTER(_vp)]),
+    "slos_plan_destroy": (_c.c_int, [_vp]),
+    "slos_batch_create": (_c.c_int, [_vp, _c.c_int, _vp, _c.POINTER(_vp)]),
+    "slos_batch_destroy": (_c.c_int, [_vp]),
+    "slos_batch_out_len": (_c.c_int64, [_vp]),
+    "slos_batch_out_offsets": (_c.c_int, [_vp, _vp]),
+    "slos_workspace_bytes": (_c.c_int, [_vp, _c.c_int, _c.POINTER(_c.c_size_t)]),
+    "slos_batch_set_config": (_c.c_int, [_vp, _c.c_int, _c.c_int, _c.c_int]),
+    "slos_batch_get_config": (_c.c_int, [_vp, _c.c_int, _c.POINTER(_c.c_int), _c.POINTER(_c.c_int)]),
+    "fock_amplitudes": (_c.c_int, [_vp, _vp, _vp, _vp, _c.c_size_t, _vp]),
+    "fock_probs": (_c.c_int, [_vp, _vp, _vp, _vp, _c.c_size_t, _vp]),
+    "fock_amplitudes_backward": (_c.c_int, [_vp, _vp, _vp, _vp, _vp, _c.c_size_t, _vp]),
+    "fock_probs_backward": (_c.c_int, [_vp, _vp, _vp, _vp, _vp, _c.c_size_t, _vp]),
+    "mesh_workspace_bytes": (_c.c_int, [_c.c_int, _c.c_int, _c.POINTER(_c.c_size_t)]),
+    "mesh_to_unitary": (_c.c_int, [_c.c_int, _c.c_int, _vp, _vp, _c.c_float, _vp, _vp, _c.c_size_t, _vp]),
+    "mesh_to_unitary_backward": (_c.c_int, [_c.c_int, _c.c_int, _vp, _vp, _c.c_float, _vp, _vp, _vp, _vp,
+                                            _c.c_size_t, _vp]),
+}
+
+_lib = None
+
+
+class SlosError(RuntimeError):
+    def __init__(self, fn: str, code: int, msg: str):
+        super().__init__("%s failed (%d): %s" % (fn, code, msg))
+        self.code = code
+
+
+def lib():
+    """Loads the built library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libslos_hip.so is not built; run `python -m paper_2602_11092_amd.build_lib`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(fn: str, rc: int):
+    if rc != SLOS_OK:
+        raise SlosError(fn, rc, lib().slos_last_error().decode())
+
+
+def _stream_ptr(dev: torch.device):
+    return ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _require(t: torch.Tensor, name: str, dtype, shape=None):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch.Tensor" % name)
+    if not t.is_cuda:
+        raise ValueError("%s must be a device (cuda) tensor" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError("%s must have shape %s, got %s" % (name, tuple(shape), tuple(t.shape)))
+
+
+# ------------------------------------------------------------------ combinatorics
+
+def slos_fock_dim(m: int, n: int) -> int:
+    return int(lib().slos_fock_dim(m, n))
+
+
+def slos_fock_unrank(m: int, n: int, rank: int) -> np.ndarray:
+    occ = np.zeros(m, dtype=np.int32)
+    _check("slos_fock_unrank", lib().slos_fock_unrank(m, n, rank, occ.ctypes.data_as(_vp)))
+    return occ
+
+
+def slos_fock_rank(m: int, n: int, occ) -> int:
+    o = np.ascontiguousarray(occ, dtype=np.int32)
+    return int(lib().slos_fock_rank(m, n, o.ctypes.data_as(_vp)))
+
+
+# ------------------------------------------------------------------ plan / batch
+
+class Plan:
+    """Transition graph for m modes and up to n_max photons (slos_plan_create)."""
+
+    def __init__(self, m: int, n_max: int, forward_only: bool = False):
+        h = _vp()
+        flags = PLAN_FORWARD_ONLY if forward_only else PLAN_DEFAULT
+        _check("slos_plan_create", lib().slos_plan_create(m, n_max, flags, ctypes.byref(h)))
+        self._h = h
+        self.m = m
+        self.n_max = n_max
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            lib().slos_plan_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Input states of B samples for one plan (slos_batch_create)."""
+
+    def __init__(self, plan: Plan, occ):
+        occ = np.ascontiguousarray(np.asarray(occ, dtype=np.int32).reshape(-1, plan.m))
+        h = _vp()
+        _check("slos_batch_create", lib().slos_batch_create(plan.handle, occ.shape[0], occ.ctypes.data_as(_vp),
+                                                            ctypes.byref(h)))
+        self._h = h
+        self.plan = plan  # keep the plan alive
+        self.m = plan.m
+        self.B = occ.shape[0]
+        self.occ = occ
+        self.n = occ.sum(axis=1)
+        self.out_len = int(lib().slos_batch_out_len(h))
+        off = np.zeros(self.B + 1, dtype=np.int64)
+        _check("slos_batch_out_offsets", lib().slos_batch_out_offsets(h, off.ctypes.data_as(_vp)))
+        self.offsets = off
+        self._ws = {}
+
+    @property
+    def handle(self):
+        return self._h
+
+    def workspace_bytes(self, op: int) -> int:
+        n = ctypes.c_size_t(0)
+        _check("slos_workspace_bytes", lib().slos_workspace_bytes(self._h, op, ctypes.byref(n)))
+        return int(n.value)
+
+    def set_config(self, op: int, variant: int, block: int = 0):
+        _check("slos_batch_set_config", lib().slos_batch_set_config(self._h, op, variant, block))
+        self._ws.pop(op, None)
+
+    def get_config(self, op: int) -> Tuple[int, int]:
+        v, b = ctypes.c_int(0), ctypes.c_int(0)
+        _check("slos_batch_get_config", lib().slos_batch_get_config(self._h, op, ctypes.byref(v), ctypes.byref(b)))
+        return int(v.value), int(b.value)
+
+    def workspace(self, op: int, device) -> Optional[torch.Tensor]:
+        """Device workspace for `op`, allocated once and reused."""
+        need = self.workspace_bytes(op)
+        if need == 0:
+            return None
+        ws = self._ws.get(op)
+        if ws is None or ws.numel() < need or ws.device != torch.device(device):
+            ws = torch.empty(need, dtype=torch.uint8, device=device)
+            self._ws[op] = ws
+        return ws
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            lib().slos_batch_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _ws_args(ws: Optional[torch.Tensor]):
+    if ws is None:
+        return ctypes.c_void_p(0), 0
+    return ctypes.c_void_p(ws.data_ptr()), ws.numel()
+
+
+# ------------------------------------------------------------------ forward / backward
+
+def fock_amplitudes(batch: Batch, U: torch.Tensor, out: Optional[torch.Tensor] = None,
+                    ws: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Amplitudes a_t of every sample, complex64 [out_len] (ragged per sample)."""
+    _require(U, "U", torch.complex64, (batch.B, batch.m, batch.m))
+    if out is None:
+        out = torch.empty(batch.out_len, dtype=torch.complex64, device=U.device)
+    _require(out, "out", torch.complex64, (batch.out_len,))
+    if ws is None:
+        ws = batch.workspace(OP_AMPLITUDES, U.device)
+    wp, wn = _ws_args(ws)
+    _check("fock_amplitudes", lib().fock_amplitudes(batch.handle, _ptr(U), _ptr(out), wp, wn, _stream_ptr(U.device)))
+    return out
+
+
+def fock_probs(batch: Batch, U: torch.Tensor, out: Optional[torch.Tensor] = None,
+               ws: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Probabilities |a_t|^2, float32 [out_len]."""
+    _require(U, "U", torch.complex64, (batch.B, batch.m, batch.m))
+    if out is None:
+        out = torch.empty(batch.out_len, dtype=torch.float32, device=U.device)
+    _require(out, "out", torch.float32, (batch.out_len,))
+    if ws is None:
+        ws = batch.workspace(OP_PROBS, U.device)
+    wp, wn = _ws_args(ws)
+    _check("fock_probs", lib().fock_probs(batch.handle, _ptr(U), _ptr(out), wp, wn, _stream_ptr(U.device)))
+    return out
+
+
+def fock_amplitudes_backward(batch: Batch, U: torch.Tensor, grad_amps: torch.Tensor,
+                             out: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None) -> torch.Tensor:
+    _require(U, "U", torch.complex64, (batch.B, batch.m, batch.m))
+    _require(grad_amps, "grad_amps", torch.complex64, (batch.out_len,))
+    if out is None:
+        out = torch.empty_like(U)
+    _require(out, "grad_U", torch.complex64, (batch.B, batch.m, batch.m))
+    if ws is None:
+        ws = batch.workspace(OP_AMPLITUDES_BACKWARD, U.device)
+    wp, wn = _ws_args(ws)
+    _check("fock_amplitudes_backward",
+           lib().fock_amplitudes_backward(batch.handle, _ptr(U), _ptr(grad_amps), _ptr(out), wp, wn,
+                                          _stream_ptr(U.device)))
+    return out
+
+
+def fock_probs_backward(batch: Batch, U: torch.Tensor, grad_probs: torch.Tensor,
+                        out: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None) -> torch.Tensor:
+    _require(U, "U", torch.complex64, (batch.B, batch.m, batch.m))
+    _require(grad_probs, "grad_probs", torch.float32, (batch.out_len,))
+    if out is None:
+        out = torch.empty_like(U)
+    _require(out, "grad_U", torch.complex64, (batch.B, batch.m, batch.m))
+    if ws is None:
+        ws = batch.workspace(OP_PROBS_BACKWARD, U.device)
+    wp, wn = _ws_args(ws)
+    _check("fock_probs_backward",
+           lib().fock_probs_backward(batch.handle, _ptr(U), _ptr(grad_probs), _ptr(out), wp, wn,
+                                     _stream_ptr(U.device)))
+    return out
+
+
+# ------------------------------------------------------------------ mesh
+
+_mesh_ws = {}
+
+
+def mesh_workspace(m: int, B: int, device) -> torch.Tensor:
+    n = ctypes.c_size_t(0)
+    _check("mesh_workspace_bytes", lib().mesh_workspace_bytes(m, B, ctypes.byref(n)))
+    key = (str(device),)
+    ws = _mesh_ws.get(key)
+    if ws is None or ws.numel() < n.value:
+        ws = torch.empty(int(n.value), dtype=torch.uint8, device=device)
+        _mesh_ws[key] = ws
+    return ws
+
+
+def mesh_to_unitary(theta: torch.Tensor, x: Optional[torch.Tensor], enc_scale: float, m: Optional[int] = None,
+                    out: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """U(x_b, theta) for every row of x (complex64 [B, m, m]); with x = None,
+    the plain mesh W2 W1 as [1, m, m]."""
+    if x is not None:
+        _require(x, "x", torch.float32)
+        B, m = x.shape
+    else:
+        if m is None:
+            raise ValueError("m is required when x is None")
+        B = 1
+    _require(theta, "theta", torch.float32, (m * (m - 1),))
+    if out is None:
+        out = torch.empty(B, m, m, dtype=torch.complex64, device=theta.device)
+    _require(out, "U", torch.complex64, (B, m, m))
+    if ws is None:
+        ws = mesh_workspace(m, B, theta.device)
+    _check("mesh_to_unitary", lib().mesh_to_unitary(m, B, _ptr(theta), _ptr(x), float(enc_scale), _ptr(out),
+                                                    _ptr(ws), ws.numel(), _stream_ptr(theta.device)))
+    return out
+
+
+def mesh_to_unitary_backward(theta: torch.Tensor, x: Optional[torch.Tensor], enc_scale: float,
+                             grad_U: torch.Tensor, need_grad_x: bool = True,
+                             ws: Optional[torch.Tensor] = None):
+    """(grad_theta [m(m-1)], grad_x [B, m] or None)."""
+    B, m = grad_U.shape[0], grad_U.shape[1]
+    _require(grad_U, "grad_U", torch.complex64, (B, m, m))
+    _require(theta, "theta", torch.float32, (m * (m - 1),))
+    if x is not None:
+        _require(x, "x", torch.float32, (B, m))
+    gt = torch.empty_like(theta)
+    gx = torch.empty(B, m, dtype=torch.float32, device=theta.device) if (x is not None and need_grad_x) else None
+    if ws is None:
+        ws = mesh_workspace(m, B, theta.device)
+    _check("mesh_to_unitary_backward",
+           lib().mesh_to_unitary_backward(m, B, _ptr(theta), _ptr(x), float(enc_scale), _ptr(grad_U), _ptr(gt),
+                                          _ptr(gx), _ptr(ws), ws.numel(), _stream_ptr(theta.device)))
+    return gt, gx
+
+
+def slos_transition_tables(m: int, k: int, want_succ: bool = True):
+    """Host copy of layer k's transition tables: (pred [k, N_k], succ [m, N_{k-1}]
+    or None, nrm [N_k], minoff [m+1])."""
+    Nk = slos_fock_dim(m, k)
+    Nkm1 = slos_fock_dim(m, k - 1)
+    pred = np.zeros((k, Nk), dtype=np.int32)
+    succ = np.zeros((m, Nkm1), dtype=np.int32) if want_succ else None
+    nrm = np.zeros(Nk, dtype=np.float32)
+    minoff = np.zeros(m + 1, dtype=np.int32)
+    _check("slos_transition_tables",
+           lib().slos_transition_tables(m, k, pred.ctypes.data_as(_vp),
+                                        succ.ctypes.data_as(_vp) if succ is not None else None,
+                                        nrm.ctypes.data_as(_vp), minoff.ctypes.data_as(_vp)))
+    return pred, succ, nrm, minoff

@@ -1,0 +1,86 @@
+"""torch.autograd.Function wrappers around the library's forward and
+adjoint kernels (the hand-written backward of Sec. II-A-3's differentiable
+simulation).  Gradients use PyTorch's convention dL/dRe + i dL/dIm, which is
+also the library's."""
+from __future__ import annotations
+
+import math
+from typing import Optional
+
+import torch
+
+from . import _binding as B
+
+
+class FockProbs(torch.autograd.Function):
+    """U [B, m, m] complex64 -> probabilities float32 [out_len]."""
+
+    @staticmethod
+    def forward(ctx, U: torch.Tensor, batch: B.Batch):
+        U = U.contiguous()
+        ctx.batch = batch
+        ctx.save_for_backward(U)
+        return B.fock_probs(batch, U)
+
+    @staticmethod
+    def backward(ctx, grad_p):
+        (U,) = ctx.saved_tensors
+        gU = B.fock_probs_backward(ctx.batch, U, grad_p.contiguous().to(torch.float32))
+        return gU, None
+
+
+class FockAmplitudes(torch.autograd.Function):
+    """U [B, m, m] complex64 -> amplitudes complex64 [out_len]."""
+
+    @staticmethod
+    def forward(ctx, U: torch.Tensor, batch: B.Batch):
+        U = U.contiguous()
+        ctx.batch = batch
+        ctx.save_for_backward(U)
+        return B.fock_amplitudes(batch, U)
+
+    @staticmethod
+    def backward(ctx, grad_a):
+        (U,) = ctx.saved_tensors
+        gU = B.fock_amplitudes_backward(ctx.batch, U, grad_a.contiguous().to(torch.complex64))
+        return gU, None
+
+
+class MeshToUnitary(torch.autograd.Function):
+    """theta [m(m-1)] float32 and features x [B, m] float32 (or None) ->
+    U [B, m, m] complex64."""
+
+    @staticmethod
+    def forward(ctx, theta: torch.Tensor, x: Optional[torch.Tensor], enc_scale: float, m: int):
+        theta = theta.contiguous()
+        xx = x.contiguous() if x is not None else None
+        ctx.enc_scale = enc_scale
+        ctx.has_x = x is not None
+        ctx.save_for_backward(theta, xx) if xx is not None else ctx.save_for_backward(theta)
+        return B.mesh_to_unitary(theta, xx, enc_scale, m=m)
+
+    @staticmethod
+    def backward(ctx, gU):
+        if ctx.has_x:
+            theta, x = ctx.saved_tensors
+        else:
+            (theta,) = ctx.saved_tensors
+            x = None
+        need_gx = ctx.has_x and ctx.needs_input_grad[1]
+        gt, gx = B.mesh_to_unitary_backward(theta, x, ctx.enc_scale, gU.contiguous(), need_grad_x=need_gx)
+        return gt, gx, None, None
+
+
+def fock_probs(U: torch.Tensor, batch: B.Batch) -> torch.Tensor:
+    return FockProbs.apply(U, batch)
+
+
+def fock_amplitudes(U: torch.Tensor, batch: B.Batch) -> torch.Tensor:
+    return FockAmplitudes.apply(U, batch)
+
+
+def mesh_to_unitary(theta: torch.Tensor, x: Optional[torch.Tensor], enc_scale: float = math.pi,
+                    m: Optional[int] = None) -> torch.Tensor:
+    if m is None:
+        m = x.shape[1]
+    return MeshToUnitary.apply(theta, x, enc_scale, m)

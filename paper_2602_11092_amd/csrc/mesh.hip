@@ -1,0 +1,324 @@
+// Interferometer mesh U(x, theta) of phase shifters and beam splitters
+// (arXiv 2602.11092, Sec. II-A-3: trainable phases define U(theta);
+// Sec. II-C-1: angle encoding U(x, theta) = W2 S(x) W1) and its adjoint.
+//
+// Rectangular mesh: column c holds MZIs on pairs (k, k+1), k = c mod 2 + 2p.
+// MZIs of one column touch disjoint pairs, so a column is applied to all
+// rows at once.  W1 = columns [0, m/2), W2 = the rest; both factors are built
+// by one workgroup (one half each), then every sample forms
+// U_b = W2 diag(exp(i enc x_b)) W1.  The adjoint reduces dL/dW1, dL/dW2 over
+// the batch in a fixed order, then sweeps the columns backwards, recovering
+// each column's input as T^H times its output (T unitary).
+#include "slos_internal.h"
+
+namespace slos {
+namespace {
+
+constexpr int kMeshSamplesPerBlock = 4;
+constexpr int kMeshMaxBlocks = 256;
+
+struct Mzi {
+    float2 t00, t01, t10, t11;
+};
+
+// MZI(theta, phi) = BS PS(theta) BS PS(phi), BS = (1/sqrt2)[[1,i],[i,1]],
+// PS(a) = diag(e^{ia}, 1):
+//   T = 1/2 [[ (e^{i th} - 1) e^{i ph},  i (e^{i th} + 1) ],
+//            [ i (e^{i th} + 1) e^{i ph}, 1 - e^{i th}     ]]
+__device__ __forceinline__ Mzi mzi(float th, float ph) {
+    float st, ct, sp, cp;
+    sincosf(th, &st, &ct);
+    sincosf(ph, &sp, &cp);
+    const float2 em1 = make_float2(0.5f * (ct - 1.f), 0.5f * st);  // (e^{i th} - 1)/2
+    const float2 ep1 = make_float2(0.5f * (ct + 1.f), 0.5f * st);  // (e^{i th} + 1)/2
+    const float2 iep1 = make_float2(-ep1.y, ep1.x);                // i (e^{i th} + 1)/2
+    const float2 eph = make_float2(cp, sp);
+    Mzi T;
+    T.t00 = make_float2(em1.x * eph.x - em1.y * eph.y, em1.x * eph.y + em1.y * eph.x);
+    T.t01 = iep1;
+    T.t10 = make_float2(iep1.x * eph.x - iep1.y * eph.y, iep1.x * eph.y + iep1.y * eph.x);
+    T.t11 = make_float2(-em1.x, -em1.y);
+    return T;
+}
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+
+__device__ __forceinline__ int col_start(int c, int m) { return ((c + 1) / 2) * (m / 2) + (c / 2) * ((m - 1) / 2); }
+
+// Builds W1 (half 0) and W2 (half 1) into Wout[2][m][m].  1024 threads:
+// half = tid / 512, pair slot = (tid % 512) / 32, column of W = tid % 32.
+__global__ __launch_bounds__(1024) void mesh_factors_kernel(int m, const float* __restrict__ theta,
+                                                            float2* __restrict__ Wout) {
+    __shared__ float2 W[2][32][33];
+    const int tid = threadIdx.x;
+    const int half = tid >> 9, pr = (tid >> 5) & 15, col = tid & 31;
+    for (int r = pr; r < 32; r += 16)
+        W[half][r][col] = make_float2((r == col) ? 1.f : 0.f, 0.f);
+    __syncthreads();
+    const int split = m / 2;
+    const int nsteps = max(split, m - split);
+    for (int s = 0; s < nsteps; ++s) {
+        const int c = half == 0 ? s : split + s;
+        const int cend = half == 0 ? split : m;
+        const int k = (c & 1) + 2 * pr;
+        if (c < cend && k <= m - 2 && col < m) {
+            const int q = col_start(c, m) + pr;
+            const Mzi T = mzi(theta[2 * q], theta[2 * q + 1]);
+            const float2 x0 = W[half][k][col], x1 = W[half][k + 1][col];
+            float2 y0 = cmul(T.t00, x0), y1 = cmul(T.t10, x0);
+            c_fma(y0, T.t01, x1);
+            c_fma(y1, T.t11, x1);
+            W[half][k][col] = y0;
+            W[half][k + 1][col] = y1;
+        }
+        __syncthreads();
+    }
+    for (int r = pr; r < m; r += 16)
+        if (col < m) Wout[((size_t)half * m + r) * m + col] = W[half][r][col];
+}
+
+// U_b = W2 diag(S_b) W1, one sample per block.
+__global__ __launch_bounds__(256) void mesh_apply_kernel(int m, const float2* __restrict__ Wf,
+                                                         const float* __restrict__ x, float enc,
+                                                         float2* __restrict__ U) {
+    __shared__ float2 W2[32][33];
+    __shared__ float2 A[32][33];  // diag(S) W1
+    const int b = blockIdx.x;
+    const int tid = threadIdx.x;
+    for (int q = tid; q < m * m; q += 256) {
+        const int r = q / m, c = q % m;
+        float2 s = make_float2(1.f, 0.f);
+        if (x) {
+            float sn, cs;
+            sincosf(enc * x[(size_t)b * m + r], &sn, &cs);
+            s = make_float2(cs, sn);
+        }
+        A[r][c] = cmul(s, Wf[(size_t)r * m + c]);
+        W2[r][c] = Wf[(size_t)m * m + q];
+    }
+    __syncthreads();
+    for (int q = tid; q < m * m; q += 256) {
+        const int j = q / m, i = q % m;
+        float2 acc = c_zero();
+        for (int k = 0; k < m; ++k) c_fma(acc, W2[j][k], A[k][i]);
+        U[(size_t)b * m * m + q] = acc;
+    }
+}
+
+// Per-block partial sums of dL/dW1 = sum_b conj(S_b) (W2^H G_b) and
+// dL/dW2 = sum_b (G_b W1^H) conj(S_b), plus dL/dx_b.
+__global__ __launch_bounds__(256) void mesh_bwd_samples_kernel(int m, int B, const float2* __restrict__ Wf,
+                                                               const float* __restrict__ x, float enc,
+                                                               const float2* __restrict__ gU,
+                                                               float* __restrict__ gx,
+                                                               float2* __restrict__ partial, int per_block) {
+    __shared__ float2 W1[32][33], W2[32][33], G[32][33], Y[32][33], V[32][33];
+    __shared__ float2 S[32];
+    const int tid = threadIdx.x;
+    for (int q = tid; q < m * m; q += 256) {
+        const int r = q / m, c = q % m;
+        W1[r][c] = Wf[q];
+        W2[r][c] = Wf[(size_t)m * m + q];
+    }
+    float2 pa[4], pb[4];
+    for (int e = 0; e < 4; ++e) pa[e] = pb[e] = c_zero();
+    const int b0 = blockIdx.x * per_block;
+    const int b1 = min(B, b0 + per_block);
+    for (int b = b0; b < b1; ++b) {
+        __syncthreads();
+        for (int q = tid; q < m * m; q += 256) G[q / m][q % m] = gU[(size_t)b * m * m + q];
+        if (tid < m) {
+            float2 s = make_float2(1.f, 0.f);
+            if (x) {
+                float sn, cs;
+                sincosf(enc * x[(size_t)b * m + tid], &sn, &cs);
+                s = make_float2(cs, sn);
+            }
+            S[tid] = s;
+        }
+        __syncthreads();
+        for (int q = tid; q < m * m; q += 256) {
+            const int r = q / m, c = q % m;
+            float2 y = c_zero(), v = c_zero();
+            for (int k = 0; k < m; ++k) {
+                c_fma_conj(y, W2[k][r], G[k][c]);       // (W2^H G)[r][c]
+                c_fma(v, G[r][k], cconj(W1[c][k]));     // (G W1^H)[r][c]
+            }
+            Y[r][c] = y;
+            V[r][c] = v;
+        }
+        __syncthreads();
+        if (gx && tid < m) {
+            float2 gs = c_zero();  // (W2^H G W1^H)[k][k]
+            for (int i = 0; i < m; ++i) c_fma(gs, Y[tid][i], cconj(W1[tid][i]));
+            const float2 z = cmul(cconj(gs), S[tid]);
+            gx[(size_t)b * m + tid] = -enc * z.y;
+        }
+        for (int e = 0; e < 4; ++e) {
+            const int q = tid + e * 256;
+            if (q < m * m) {
+                const int r = q / m, c = q % m;
+                c_fma(pa[e], cconj(S[r]), Y[r][c]);
+                c_fma(pb[e], V[r][c], cconj(S[c]));
+            }
+        }
+    }
+    for (int e = 0; e < 4; ++e) {
+        const int q = tid + e * 256;
+        if (q < m * m) {
+            partial[((size_t)blockIdx.x * 2 + 0) * m * m + q] = pa[e];
+            partial[((size_t)blockIdx.x * 2 + 1) * m * m + q] = pb[e];
+        }
+    }
+}
+
+// Fixed-order sum of the partials, then the reverse column sweeps of both
+// factors.  Thread layout as in mesh_factors_kernel.
+__global__ __launch_bounds__(1024) void mesh_bwd_final_kernel(int m, const float* __restrict__ theta,
+                                                              const float2* __restrict__ Wf,
+                                                              const float2* __restrict__ partial, int nblk,
+                                                              float* __restrict__ gtheta) {
+    __shared__ float2 X[2][32][33], G[2][32][33];
+    const int tid = threadIdx.x;
+    const int half = tid >> 9, pr = (tid >> 5) & 15, col = tid & 31;
+    for (int r = pr; r < m; r += 16) {
+        if (col < m) {
+            const int q = r * m + col;
+            float2 s = c_zero();
+            for (int blk = 0; blk < nblk; ++blk) s = c_add(s, partial[((size_t)blk * 2 + half) * m * m + q]);
+            G[half][r][col] = s;
+            X[half][r][col] = Wf[(size_t)half * m * m + q];
+        }
+    }
+    __syncthreads();
+    const int split = m / 2;
+    const int nsteps = max(split, m - split);
+    for (int s = nsteps - 1; s >= 0; --s) {
+        const int c = half == 0 ? s : split + s;
+        const int cend = half == 0 ? split : m;
+        const int k = (c & 1) + 2 * pr;
+        if (c < cend && k <= m - 2) {  // uniform over the 32 lanes of this pair slot
+            const int q = col_start(c, m) + pr;
+            const float th = theta[2 * q], ph = theta[2 * q + 1];
+            const Mzi T = mzi(th, ph);
+            float2 r0 = c_zero(), r1 = c_zero(), g0 = c_zero(), g1 = c_zero();
+            if (col < m) {
+                const float2 x0 = X[half][k][col], x1 = X[half][k + 1][col];
+                c_fma_conj(r0, T.t00, x0);  // (T^H X) row 0
+                c_fma_conj(r0, T.t10, x1);
+                c_fma_conj(r1, T.t01, x0);  // row 1
+                c_fma_conj(r1, T.t11, x1);
+                g0 = G[half][k][col];
+                g1 = G[half][k + 1][col];
+            }
+            // G_T[a][b] = sum_col g_a conj(r_b)
+            float2 p[4] = {cmul(g0, cconj(r0)), cmul(g0, cconj(r1)), cmul(g1, cconj(r0)), cmul(g1, cconj(r1))};
+            for (int e = 0; e < 4; ++e) {
+#pragma unroll
+                for (int o = 16; o > 0; o >>= 1) {
+                    p[e].x += __shfl_xor(p[e].x, o, 32);
+                    p[e].y += __shfl_xor(p[e].y, o, 32);
+                }
+            }
+            if (col == 0) {
+                float st, ct, sp, cp;
+                sincosf(th, &st, &ct);
+                sincosf(ph, &sp, &cp);
+                const float2 eth = make_float2(ct, st);
+                const float2 etp = cmul(eth, make_float2(cp, sp));
+                // dT/dtheta = 1/2 [[ i e^{i(th+ph)}, -e^{i th} ], [ -e^{i(th+ph)}, -i e^{i th} ]]
+                const float2 d00 = make_float2(-0.5f * etp.y, 0.5f * etp.x);
+                const float2 d01 = make_float2(-0.5f * eth.x, -0.5f * eth.y);
+                const float2 d10 = make_float2(-0.5f * etp.x, -0.5f * etp.y);
+                const float2 d11 = make_float2(0.5f * eth.y, -0.5f * eth.x);
+                float gth = 0.f;
+                gth += p[0].x * d00.x + p[0].y * d00.y;
+                gth += p[1].x * d01.x + p[1].y * d01.y;
+                gth += p[2].x * d10.x + p[2].y * d10.y;
+                gth += p[3].x * d11.x + p[3].y * d11.y;
+                // dT/dphi = [[ i t00, 0 ], [ i t10, 0 ]]
+                const float2 e00 = make_float2(-T.t00.y, T.t00.x);
+                const float2 e10 = make_float2(-T.t10.y, T.t10.x);
+                float gph = p[0].x * e00.x + p[0].y * e00.y + p[2].x * e10.x + p[2].y * e10.y;
+                gtheta[2 * q] = gth;
+                gtheta[2 * q + 1] = gph;
+            }
+            if (col < m) {
+                X[half][k][col] = r0;
+                X[half][k + 1][col] = r1;
+                float2 h0 = c_zero(), h1 = c_zero();
+                c_fma_conj(h0, T.t00, g0);
+                c_fma_conj(h0, T.t10, g1);
+                c_fma_conj(h1, T.t01, g0);
+                c_fma_conj(h1, T.t11, g1);
+                G[half][k][col] = h0;
+                G[half][k + 1][col] = h1;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+int mesh_blocks(int B) { return std::max(1, std::min(kMeshMaxBlocks, (B + kMeshSamplesPerBlock - 1) / kMeshSamplesPerBlock)); }
+
+size_t mesh_ws(int m, int B) {
+    const size_t mm = (size_t)m * m * sizeof(float2);
+    return 2 * mm + (size_t)mesh_blocks(B) * 2 * mm;
+}
+
+}  // namespace
+}  // namespace slos
+
+using namespace slos;
+
+extern "C" int mesh_workspace_bytes(int m, int B, size_t* bytes) {
+    if (!bytes) return fail(SLOS_EINVAL, "mesh_workspace_bytes: bytes is NULL");
+    if (m < 2 || m > kMaxModes || B < 0) return fail(SLOS_EINVAL, "mesh_workspace_bytes: bad m or B");
+    *bytes = mesh_ws(m, std::max(B, 1));
+    return SLOS_OK;
+}
+
+extern "C" int mesh_to_unitary(int m, int B, const float* theta, const float* x, float enc_scale, float* U,
+                               void* ws, size_t ws_bytes, void* stream) {
+    if (m < 2 || m > kMaxModes) return fail(SLOS_EINVAL, "mesh_to_unitary: m must be in [2, 32]");
+    if (B < 0) return fail(SLOS_EINVAL, "mesh_to_unitary: B < 0");
+    if (!x && B != 1) return fail(SLOS_EINVAL, "mesh_to_unitary: B must be 1 when x is NULL");
+    if (B == 0) return SLOS_OK;
+    if (!theta || !U) return fail(SLOS_EINVAL, "mesh_to_unitary: NULL pointer");
+    if (!ws || ws_bytes < mesh_ws(m, B)) return fail(SLOS_EWORKSPACE, "mesh_to_unitary: workspace too small");
+    hipStream_t s = (hipStream_t)stream;
+    float2* Wf = (float2*)ws;
+    hipLaunchKernelGGL(mesh_factors_kernel, dim3(1), dim3(1024), 0, s, m, theta, Wf);
+    hipLaunchKernelGGL(mesh_apply_kernel, dim3(B), dim3(256), 0, s, m, (const float2*)Wf, x, enc_scale, (float2*)U);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(SLOS_EHIP, std::string("mesh_to_unitary launch: ") + hipGetErrorString(e));
+    return SLOS_OK;
+}
+
+extern "C" int mesh_to_unitary_backward(int m, int B, const float* theta, const float* x, float enc_scale,
+                                        const float* grad_U, float* grad_theta, float* grad_x, void* ws,
+                                        size_t ws_bytes, void* stream) {
+    if (m < 2 || m > kMaxModes) return fail(SLOS_EINVAL, "mesh_to_unitary_backward: m must be in [2, 32]");
+    if (B < 1) return fail(SLOS_EINVAL, "mesh_to_unitary_backward: B < 1");
+    if (!x && B != 1) return fail(SLOS_EINVAL, "mesh_to_unitary_backward: B must be 1 when x is NULL");
+    if (!x && grad_x) return fail(SLOS_EINVAL, "mesh_to_unitary_backward: grad_x must be NULL when x is NULL");
+    if (!theta || !grad_U || !grad_theta) return fail(SLOS_EINVAL, "mesh_to_unitary_backward: NULL pointer");
+    if (!ws || ws_bytes < mesh_ws(m, B)) return fail(SLOS_EWORKSPACE, "mesh_to_unitary_backward: workspace too small");
+    hipStream_t s = (hipStream_t)stream;
+    float2* Wf = (float2*)ws;
+    float2* partial = Wf + 2 * (size_t)m * m;
+    const int nblk = mesh_blocks(B);
+    const int per_block = (B + nblk - 1) / nblk;
+    float* gx = (x && grad_x) ? grad_x : nullptr;
+    hipLaunchKernelGGL(mesh_factors_kernel, dim3(1), dim3(1024), 0, s, m, theta, Wf);
+    hipLaunchKernelGGL(mesh_bwd_samples_kernel, dim3(nblk), dim3(256), 0, s, m, B, (const float2*)Wf, x, enc_scale,
+                       (const float2*)grad_U, gx, partial, per_block);
+    hipLaunchKernelGGL(mesh_bwd_final_kernel, dim3(1), dim3(1024), 0, s, m, theta, (const float2*)Wf,
+                       (const float2*)partial, nblk, grad_theta);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(SLOS_EHIP, std::string("mesh_to_unitary_backward launch: ") + hipGetErrorString(e));
+    return SLOS_OK;
+}

@@ -1,0 +1,529 @@
+// Host side of the strong-simulation library: Fock-basis combinatorics, the
+// transition graph of every photon layer (built once per plan, Sec. II-A-3
+// of arXiv 2602.11092), batch descriptors, and the C ABI entry points that
+// validate arguments and dispatch to the fused or layered kernels.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <thread>
+
+#include "slos_internal.h"
+
+namespace slos {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+int fail(int code, const std::string& msg) {
+    g_last_error = msg;
+    return code;
+}
+
+namespace {
+
+// C(a, b) in int64, -1 on overflow or invalid input.
+int64_t binom(int64_t a, int64_t b) {
+    if (b < 0 || a < 0 || b > a) return 0;
+    if (b > a - b) b = a - b;
+    __int128 r = 1;
+    for (int64_t i = 1; i <= b; ++i) {
+        r = r * (a - b + i) / i;
+        if (r > (__int128)INT64_MAX) return -1;
+    }
+    return (int64_t)r;
+}
+
+// Counting helper for the basis order (sorted mode lists in lexicographic
+// order).  below[r][c] = number of sorted lists of length r whose first entry
+// is < c and all entries lie in [0, m): the rank offset contributed by a
+// position holding c when r more entries follow it, measured from 0.
+struct Counter {
+    int m = 0;
+    int K = 0;
+    std::vector<std::vector<int64_t>> below;  // [r][c], r = 0..K, c = 0..m
+
+    Counter(int m_, int K_) : m(m_), K(K_), below(K_ + 1, std::vector<int64_t>(m_ + 1, 0)) {
+        for (int r = 0; r <= K; ++r) {
+            int64_t acc = 0;
+            for (int c = 0; c <= m; ++c) {
+                below[r][c] = acc;
+                if (c < m) acc += count_from(c, r);
+            }
+        }
+    }
+    // number of sorted lists of length r with entries in [c, m)
+    int64_t count_from(int c, int r) const {
+        if (r == 0) return 1;
+        return binom((int64_t)(m - c) + r - 1, r);
+    }
+    // rank of sorted list L[0..len) skipping index `skip` (-1: none)
+    int64_t rank(const int* L, int len, int skip = -1) const {
+        const int K2 = (skip >= 0) ? len - 1 : len;
+        int64_t r = 0;
+        int prev = 0;
+        int pos = 0;
+        for (int q = 0; q < len; ++q) {
+            if (q == skip) continue;
+            const int rem = K2 - pos - 1;
+            r += below[rem][L[q]] - below[rem][prev];
+            prev = L[q];
+            ++pos;
+        }
+        return r;
+    }
+    void unrank(int64_t r, int len, int* L) const {
+        int lo = 0;
+        for (int pos = 0; pos < len; ++pos) {
+            const int rem = len - pos - 1;
+            int j = lo;
+            while (true) {
+                const int64_t blk = count_from(j, rem);
+                if (r < blk) break;
+                r -= blk;
+                ++j;
+            }
+            L[pos] = j;
+            lo = j;
+        }
+    }
+};
+
+// next sorted list in lexicographic order; false after the last one
+bool next_list(int* L, int len, int m) {
+    int q = len - 1;
+    while (q >= 0 && L[q] == m - 1) --q;
+    if (q < 0) return false;
+    ++L[q];
+    for (int r = q + 1; r < len; ++r) L[r] = L[q];
+    return true;
+}
+
+template <class F>
+void parallel_ranges(int64_t total, F&& body) {
+    unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    if (total < 20000) hw = 1;
+    std::vector<std::thread> th;
+    const int64_t step = (total + hw - 1) / hw;
+    for (unsigned w = 0; w < hw; ++w) {
+        const int64_t lo = (int64_t)w * step, hi = std::min(total, lo + step);
+        if (lo >= hi) break;
+        th.emplace_back([=, &body] { body(lo, hi); });
+    }
+    for (auto& t : th) t.join();
+}
+
+struct HostLayer {
+    std::vector<int32_t> pred, succ, minoff;
+    std::vector<float> nrm;
+};
+
+// Transition graph of layer k (k >= 1): predecessor entries for every
+// k-photon state, successor ranks for every (k-1)-photon state and output
+// mode, sqrt(prod t!) and the smallest-mode block offsets.
+void build_layer(int m, int k, const Counter& Ck, const Counter& Ckm1, int64_t Nk, int64_t Nkm1,
+                 bool want_succ, HostLayer& H) {
+    H.pred.assign((size_t)k * Nk, -1);
+    H.nrm.assign(Nk, 1.f);
+    parallel_ranges(Nk, [&](int64_t lo, int64_t hi) {
+        int L[kMaxPhotons];
+        Ck.unrank(lo, k, L);
+        for (int64_t t = lo; t < hi; ++t) {
+            double f = 1.0;
+            int run = 1;
+            for (int p = 0; p < k; ++p) {
+                if (p > 0 && L[p] == L[p - 1]) {
+                    ++run;
+                    f *= run;
+                } else {
+                    run = 1;
+                    const int64_t r = Ckm1.rank(L, k, p);
+                    H.pred[(size_t)p * Nk + t] = (int32_t)((r << kModeBits) | L[p]);
+                }
+            }
+            H.nrm[t] = (float)std::sqrt(f);
+            next_list(L, k, m);
+        }
+    });
+    if (want_succ) {
+        H.succ.assign((size_t)m * Nkm1, 0);
+        parallel_ranges(Nkm1, [&](int64_t lo, int64_t hi) {
+            int L[kMaxPhotons + 1], T[kMaxPhotons + 1];
+            if (k - 1 > 0) Ckm1.unrank(lo, k - 1, L);
+            for (int64_t t = lo; t < hi; ++t) {
+                for (int j = 0; j < m; ++j) {
+                    // insert j into the sorted list
+                    int q = 0, o = 0;
+                    bool done = false;
+                    for (int p = 0; p < k - 1; ++p) {
+                        if (!done && j < L[p]) { T[o++] = j; done = true; }
+                        T[o++] = L[p];
+                        ++q;
+                    }
+                    if (!done) T[o++] = j;
+                    H.succ[(size_t)j * Nkm1 + t] = (int32_t)Ck.rank(T, k);
+                }
+                if (k - 1 > 0) next_list(L, k - 1, m);
+            }
+        });
+    }
+    H.minoff.assign(m + 1, 0);
+    for (int c = 0; c <= m; ++c) H.minoff[c] = (int32_t)Ck.below[k - 1][c];
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+}  // namespace slos
+
+using namespace slos;
+
+// ===================================================================== ABI
+
+extern "C" const char* slos_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" int64_t slos_fock_dim(int m, int n) {
+    if (m < 1 || n < 0) return -1;
+    return binom((int64_t)m + n - 1, n);
+}
+
+extern "C" int slos_fock_unrank(int m, int n, int64_t rank, int32_t* occ) {
+    if (!occ) return fail(SLOS_EINVAL, "slos_fock_unrank: occ is NULL");
+    if (m < 1 || m > kMaxModes || n < 0 || n > 64) return fail(SLOS_EINVAL, "slos_fock_unrank: bad m or n");
+    const int64_t N = slos_fock_dim(m, n);
+    if (N < 0 || rank < 0 || rank >= N) return fail(SLOS_EINVAL, "slos_fock_unrank: rank out of range");
+    Counter C(m, n);
+    std::vector<int> L(n > 0 ? n : 1);
+    C.unrank(rank, n, L.data());
+    for (int j = 0; j < m; ++j) occ[j] = 0;
+    for (int p = 0; p < n; ++p) occ[L[p]] += 1;
+    return SLOS_OK;
+}
+
+extern "C" int64_t slos_fock_rank(int m, int n, const int32_t* occ) {
+    if (!occ || m < 1 || m > kMaxModes || n < 0 || n > 64) return -1;
+    std::vector<int> L;
+    for (int j = 0; j < m; ++j) {
+        if (occ[j] < 0) return -1;
+        for (int q = 0; q < occ[j]; ++q) L.push_back(j);
+    }
+    if ((int)L.size() != n) return -1;
+    Counter C(m, n);
+    return C.rank(L.data(), n);
+}
+
+extern "C" int slos_transition_tables(int m, int k, int32_t* pred, int32_t* succ, float* nrm, int32_t* minoff) {
+    if (m < 1 || m > kMaxModes) return fail(SLOS_EINVAL, "slos_transition_tables: m must be in [1, 32]");
+    if (k < 1 || k > kMaxPhotons) return fail(SLOS_EINVAL, "slos_transition_tables: k must be in [1, 16]");
+    const int64_t Nk = slos_fock_dim(m, k), Nkm1 = slos_fock_dim(m, k - 1);
+    if (Nk < 0 || Nk >= ((int64_t)1 << (31 - kModeBits)))
+        return fail(SLOS_EUNSUPPORTED, "slos_transition_tables: layer too large for 32-bit tables");
+    Counter Ck(m, k), Ckm1(m, k - 1);
+    HostLayer H;
+    build_layer(m, k, Ck, Ckm1, Nk, Nkm1, succ != nullptr, H);
+    if (pred) std::memcpy(pred, H.pred.data(), H.pred.size() * 4);
+    if (succ) std::memcpy(succ, H.succ.data(), H.succ.size() * 4);
+    if (nrm) std::memcpy(nrm, H.nrm.data(), H.nrm.size() * 4);
+    if (minoff) std::memcpy(minoff, H.minoff.data(), H.minoff.size() * 4);
+    return SLOS_OK;
+}
+
+extern "C" int slos_plan_create(int m, int n_max, int flags, slos_plan_t* out) {
+    if (!out) return fail(SLOS_EINVAL, "slos_plan_create: out is NULL");
+    *out = nullptr;
+    if (m < 1 || m > kMaxModes) return fail(SLOS_EINVAL, "slos_plan_create: m must be in [1, 32]");
+    if (n_max < 1 || n_max > kMaxPhotons) return fail(SLOS_EINVAL, "slos_plan_create: n_max must be in [1, 16]");
+    if (flags & ~SLOS_PLAN_FORWARD_ONLY) return fail(SLOS_EINVAL, "slos_plan_create: unknown flags");
+    const int64_t Ntop = slos_fock_dim(m, n_max);
+    if (Ntop < 0 || Ntop >= ((int64_t)1 << (31 - kModeBits)))
+        return fail(SLOS_EUNSUPPORTED, "slos_plan_create: Fock space too large for 32-bit tables");
+
+    auto* P = new slos_plan_s();
+    P->m = m;
+    P->n_max = n_max;
+    P->flags = flags;
+    P->N.resize(n_max + 1);
+    for (int k = 0; k <= n_max; ++k) P->N[k] = slos_fock_dim(m, k);
+
+    if (hipGetDevice(&P->device) != hipSuccess) {
+        delete P;
+        return fail(SLOS_EHIP, "slos_plan_create: no HIP device");
+    }
+    int cu = 0, lds = 0;
+    hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, P->device);
+    hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, P->device);
+    P->num_cu = cu;
+    P->max_lds = (size_t)lds;
+
+    const bool want_succ = !(flags & SLOS_PLAN_FORWARD_ONLY);
+    std::vector<HostLayer> H(n_max + 1);
+    std::vector<Counter> C;
+    C.reserve(n_max + 1);
+    for (int k = 0; k <= n_max; ++k) C.emplace_back(m, k);
+    for (int k = 1; k <= n_max; ++k)
+        build_layer(m, k, C[k], C[k - 1], P->N[k], P->N[k - 1], want_succ, H[k]);
+
+    // one device allocation for every table
+    size_t total = align256(sizeof(LayerDev) * (n_max + 1));
+    std::vector<size_t> o_pred(n_max + 1), o_succ(n_max + 1), o_nrm(n_max + 1), o_min(n_max + 1);
+    for (int k = 1; k <= n_max; ++k) {
+        o_pred[k] = total; total += align256(H[k].pred.size() * 4);
+        o_succ[k] = total; total += align256(H[k].succ.size() * 4);
+        o_nrm[k] = total;  total += align256(H[k].nrm.size() * 4);
+        o_min[k] = total;  total += align256(H[k].minoff.size() * 4);
+    }
+    if (hipMalloc(&P->dmem, total) != hipSuccess) {
+        delete P;
+        return fail(SLOS_ENOMEM, "slos_plan_create: hipMalloc of the transition tables failed");
+    }
+    char* base = (char*)P->dmem;
+    P->layers.assign(n_max + 1, LayerDev{});
+    P->layers[0].N = 1;
+    P->layers[0].cum = 0;
+    hipError_t e = hipSuccess;
+    for (int k = 1; k <= n_max && e == hipSuccess; ++k) {
+        LayerDev& L = P->layers[k];
+        L.N = P->N[k];
+        L.cum = P->layers[k - 1].cum + P->N[k - 1];
+        L.pred = (const int32_t*)(base + o_pred[k]);
+        L.succ = want_succ ? (const int32_t*)(base + o_succ[k]) : nullptr;
+        L.nrm = (const float*)(base + o_nrm[k]);
+        L.minoff = (const int32_t*)(base + o_min[k]);
+        e = hipMemcpy(base + o_pred[k], H[k].pred.data(), H[k].pred.size() * 4, hipMemcpyHostToDevice);
+        if (e == hipSuccess && want_succ)
+            e = hipMemcpy(base + o_succ[k], H[k].succ.data(), H[k].succ.size() * 4, hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(base + o_nrm[k], H[k].nrm.data(), H[k].nrm.size() * 4, hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(base + o_min[k], H[k].minoff.data(), H[k].minoff.size() * 4, hipMemcpyHostToDevice);
+    }
+    P->d_layers = (LayerDev*)base;
+    if (e == hipSuccess)
+        e = hipMemcpy(P->d_layers, P->layers.data(), sizeof(LayerDev) * (n_max + 1), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        hipFree(P->dmem);
+        delete P;
+        return fail(SLOS_EHIP, std::string("slos_plan_create: upload failed: ") + hipGetErrorString(e));
+    }
+    *out = P;
+    return SLOS_OK;
+}
+
+extern "C" int slos_plan_destroy(slos_plan_t plan) {
+    if (!plan) return SLOS_OK;
+    hipDeviceSynchronize();
+    if (plan->dmem) hipFree(plan->dmem);
+    delete plan;
+    return SLOS_OK;
+}
+
+extern "C" int slos_batch_create(slos_plan_t plan, int B, const int32_t* occ_host, slos_batch_t* out) {
+    if (!out) return fail(SLOS_EINVAL, "slos_batch_create: out is NULL");
+    *out = nullptr;
+    if (!plan) return fail(SLOS_EINVAL, "slos_batch_create: plan is NULL");
+    if (B < 0) return fail(SLOS_EINVAL, "slos_batch_create: B < 0");
+    if (B > 0 && !occ_host) return fail(SLOS_EINVAL, "slos_batch_create: occ_host is NULL");
+    const int m = plan->m;
+    auto* Bt = new slos_batch_s();
+    Bt->plan = plan;
+    Bt->B = B;
+    Bt->n_host.resize(B);
+    Bt->off_host.assign(B + 1, 0);
+    std::vector<int32_t> modes((size_t)std::max(B, 1) * kMaxPhotons, 0);
+    std::vector<float> innorm(std::max(B, 1), 1.f);
+    for (int b = 0; b < B; ++b) {
+        int n = 0;
+        double f = 1.0;
+        for (int i = 0; i < m; ++i) {
+            const int32_t s = occ_host[(size_t)b * m + i];
+            if (s < 0) { delete Bt; return fail(SLOS_EINVAL, "slos_batch_create: negative occupation"); }
+            if (n + s > plan->n_max) {
+                delete Bt;
+                return fail(SLOS_EUNSUPPORTED, "slos_batch_create: a sample has more photons than the plan's n_max");
+            }
+            for (int q = 0; q < s; ++q) {
+                modes[(size_t)b * kMaxPhotons + n + q] = i;
+                f *= (q + 1);
+            }
+            n += s;
+        }
+        Bt->n_host[b] = n;
+        innorm[b] = (float)(1.0 / std::sqrt(f));
+        Bt->off_host[b + 1] = Bt->off_host[b] + plan->N[n];
+        Bt->n_max = std::max(Bt->n_max, n);
+    }
+    std::vector<int32_t> order(B);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return Bt->n_host[a] > Bt->n_host[b]; });
+
+    const size_t Bs = std::max(B, 1);
+    size_t o_n = 0, o_modes = align256(Bs * 4), o_off = o_modes + align256(Bs * kMaxPhotons * 4);
+    size_t o_in = o_off + align256((Bs + 1) * 8), o_ord = o_in + align256(Bs * 4);
+    size_t total = o_ord + align256(Bs * 4);
+    if (hipMalloc(&Bt->dmem, total) != hipSuccess) {
+        delete Bt;
+        return fail(SLOS_ENOMEM, "slos_batch_create: hipMalloc failed");
+    }
+    char* base = (char*)Bt->dmem;
+    hipError_t e = hipSuccess;
+    if (B > 0) {
+        e = hipMemcpy(base + o_n, Bt->n_host.data(), B * 4, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(base + o_modes, modes.data(), (size_t)B * kMaxPhotons * 4, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(base + o_in, innorm.data(), B * 4, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(base + o_ord, order.data(), B * 4, hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess) e = hipMemcpy(base + o_off, Bt->off_host.data(), (B + 1) * 8, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        hipFree(Bt->dmem);
+        delete Bt;
+        return fail(SLOS_EHIP, "slos_batch_create: upload failed");
+    }
+    Bt->dev.B = B;
+    Bt->dev.n_max = Bt->n_max;
+    Bt->dev.n = (const int32_t*)(base + o_n);
+    Bt->dev.modes = (const int32_t*)(base + o_modes);
+    Bt->dev.off = (const int64_t*)(base + o_off);
+    Bt->dev.innorm = (const float*)(base + o_in);
+    Bt->dev.order = (const int32_t*)(base + o_ord);
+    *out = Bt;
+    return SLOS_OK;
+}
+
+extern "C" int slos_batch_destroy(slos_batch_t batch) {
+    if (!batch) return SLOS_OK;
+    hipDeviceSynchronize();
+    if (batch->dmem) hipFree(batch->dmem);
+    delete batch;
+    return SLOS_OK;
+}
+
+extern "C" int64_t slos_batch_out_len(slos_batch_t batch) {
+    if (!batch) return -1;
+    return batch->off_host[batch->B];
+}
+
+extern "C" int slos_batch_out_offsets(slos_batch_t batch, int64_t* off_host) {
+    if (!batch || !off_host) return fail(SLOS_EINVAL, "slos_batch_out_offsets: NULL argument");
+    std::memcpy(off_host, batch->off_host.data(), (batch->B + 1) * sizeof(int64_t));
+    return SLOS_OK;
+}
+
+namespace {
+
+bool op_valid(int op) { return op >= SLOS_OP_AMPLITUDES && op <= SLOS_OP_PROBS_BACKWARD; }
+bool op_backward(int op) { return op >= SLOS_OP_AMPLITUDES_BACKWARD; }
+
+// Resolves AUTO and the default block size for one op.
+int resolve(const slos_batch_s& Bt, int op, int* variant, int* block) {
+    const slos_plan_s& P = *Bt.plan;
+    const bool bwd = op_backward(op);
+    Config c = Bt.cfg[op];
+    int v = c.variant;
+    if (v == SLOS_VARIANT_AUTO) {
+        const int blk = fused_default_block(P, Bt.n_max, bwd);
+        const bool ok = bwd ? fused_bwd_supported(P, Bt.n_max, blk, nullptr)
+                            : fused_fwd_supported(P, Bt.n_max, blk, nullptr);
+        v = ok ? SLOS_VARIANT_FUSED : SLOS_VARIANT_LAYERED;
+    }
+    int blk = c.block;
+    if (blk == 0)
+        blk = (v == SLOS_VARIANT_FUSED) ? fused_default_block(P, Bt.n_max, bwd) : layered_default_block(Bt);
+    *variant = v;
+    *block = blk;
+    return SLOS_OK;
+}
+
+}  // namespace
+
+extern "C" int slos_workspace_bytes(slos_batch_t batch, int op, size_t* bytes) {
+    if (!batch || !bytes) return fail(SLOS_EINVAL, "slos_workspace_bytes: NULL argument");
+    if (!op_valid(op)) return fail(SLOS_EINVAL, "slos_workspace_bytes: bad op");
+    int v, blk;
+    resolve(*batch, op, &v, &blk);
+    *bytes = (v == SLOS_VARIANT_FUSED) ? 0 : layered_ws_bytes(*batch, op_backward(op));
+    return SLOS_OK;
+}
+
+extern "C" int slos_batch_set_config(slos_batch_t batch, int op, int variant, int block) {
+    if (!batch) return fail(SLOS_EINVAL, "slos_batch_set_config: batch is NULL");
+    if (!op_valid(op)) return fail(SLOS_EINVAL, "slos_batch_set_config: bad op");
+    if (variant < SLOS_VARIANT_AUTO || variant > SLOS_VARIANT_LAYERED)
+        return fail(SLOS_EINVAL, "slos_batch_set_config: bad variant");
+    if (block != 0 && block != 64 && block != 128 && block != 256 && block != 512 && block != 1024)
+        return fail(SLOS_EINVAL, "slos_batch_set_config: block must be 0, 64, 128, 256, 512 or 1024");
+    const bool bwd = op_backward(op);
+    if (variant == SLOS_VARIANT_FUSED) {
+        std::string why;
+        const int blk = block ? block : fused_default_block(*batch->plan, batch->n_max, bwd);
+        const bool ok = bwd ? fused_bwd_supported(*batch->plan, batch->n_max, blk, &why)
+                            : fused_fwd_supported(*batch->plan, batch->n_max, blk, &why);
+        if (!ok) return fail(SLOS_EUNSUPPORTED, "slos_batch_set_config: fused variant unavailable: " + why);
+    }
+    batch->cfg[op].variant = variant;
+    batch->cfg[op].block = block;
+    return SLOS_OK;
+}
+
+extern "C" int slos_batch_get_config(slos_batch_t batch, int op, int* variant, int* block) {
+    if (!batch || !variant || !block) return fail(SLOS_EINVAL, "slos_batch_get_config: NULL argument");
+    if (!op_valid(op)) return fail(SLOS_EINVAL, "slos_batch_get_config: bad op");
+    return resolve(*batch, op, variant, block);
+}
+
+namespace {
+
+int run(slos_batch_t batch, int op, const float* U, const void* gin, void* out, void* ws, size_t ws_bytes,
+        void* stream) {
+    static const char* names[4] = {"fock_amplitudes", "fock_probs", "fock_amplitudes_backward",
+                                   "fock_probs_backward"};
+    const std::string nm = names[op];
+    if (!batch) return fail(SLOS_EINVAL, nm + ": batch is NULL");
+    if (batch->B == 0) return SLOS_OK;
+    if (!U) return fail(SLOS_EINVAL, nm + ": U is NULL");
+    if (!out) return fail(SLOS_EINVAL, nm + ": output pointer is NULL");
+    const bool bwd = op_backward(op);
+    if (bwd && !gin) return fail(SLOS_EINVAL, nm + ": gradient input is NULL");
+    if (bwd && (batch->plan->flags & SLOS_PLAN_FORWARD_ONLY))
+        return fail(SLOS_EUNSUPPORTED, nm + ": plan was created forward-only");
+    int v, blk;
+    resolve(*batch, op, &v, &blk);
+    const bool probs = (op == SLOS_OP_PROBS || op == SLOS_OP_PROBS_BACKWARD);
+    hipStream_t s = (hipStream_t)stream;
+    int rc;
+    if (v == SLOS_VARIANT_FUSED) {
+        rc = bwd ? launch_fused_bwd(*batch, blk, (const float2*)U, gin, probs, (float2*)out, s)
+                 : launch_fused_fwd(*batch, blk, (const float2*)U, out, probs, s);
+    } else {
+        const size_t need = layered_ws_bytes(*batch, bwd);
+        if (need > 0 && (!ws || ws_bytes < need))
+            return fail(SLOS_EWORKSPACE, nm + ": workspace missing or too small (need " + std::to_string(need) +
+                                             " bytes)");
+        rc = bwd ? launch_layered_bwd(*batch, blk, (const float2*)U, gin, probs, (float2*)out, ws, s)
+                 : launch_layered_fwd(*batch, blk, (const float2*)U, out, probs, ws, s);
+    }
+    return rc;
+}
+
+}  // namespace
+
+extern "C" int fock_amplitudes(slos_batch_t batch, const float* U, float* amps, void* ws, size_t ws_bytes,
+                               void* stream) {
+    return run(batch, SLOS_OP_AMPLITUDES, U, nullptr, amps, ws, ws_bytes, stream);
+}
+
+extern "C" int fock_probs(slos_batch_t batch, const float* U, float* probs, void* ws, size_t ws_bytes,
+                          void* stream) {
+    return run(batch, SLOS_OP_PROBS, U, nullptr, probs, ws, ws_bytes, stream);
+}
+
+extern "C" int fock_amplitudes_backward(slos_batch_t batch, const float* U, const float* grad_amps,
+                                        float* grad_U, void* ws, size_t ws_bytes, void* stream) {
+    return run(batch, SLOS_OP_AMPLITUDES_BACKWARD, U, grad_amps, grad_U, ws, ws_bytes, stream);
+}
+
+extern "C" int fock_probs_backward(slos_batch_t batch, const float* U, const float* grad_probs, float* grad_U,
+                                   void* ws, size_t ws_bytes, void* stream) {
+    return run(batch, SLOS_OP_PROBS_BACKWARD, U, grad_probs, grad_U, ws, ws_bytes, stream);
+}

@@ -1,0 +1,145 @@
+"""Host-side checks of the GPU library (CPU only): the shared library loads
+and exports every symbol include/slos.h declares, the basis order and the
+transition tables agree with an independent enumeration, and argument errors
+come back as status codes before any device work."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2602_11092_amd import _binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    text = open(os.path.join(ROOT, "include", "slos.h")).read()
+    return sorted(set(re.findall(r"SLOS_API\s+[\w\s\*]+?\b(\w+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = _declared_symbols()
+    assert len(names) >= 20
+    lib = B.lib()
+    for n in names:
+        assert hasattr(lib, n), n
+    # and the binding declares a signature for each of them
+    assert sorted(B.SIGNATURES) == names
+
+
+@pytest.mark.parametrize("m,n", [(1, 1), (2, 3), (6, 3), (16, 6), (20, 5), (24, 8), (32, 16)])
+def test_fock_dim(m, n):
+    assert B.slos_fock_dim(m, n) == math.comb(m + n - 1, n)
+
+
+def test_fock_dim_invalid():
+    assert B.slos_fock_dim(0, 2) == -1
+    assert B.slos_fock_dim(3, -1) == -1
+
+
+@pytest.mark.parametrize("m,n", [(3, 3), (5, 2), (6, 3), (4, 5)])
+def test_rank_unrank_match_oracle_order(m, n):
+    basis = O.fock_basis(m, n)
+    for r, t in enumerate(basis):
+        assert (B.slos_fock_unrank(m, n, r) == t).all()
+        assert B.slos_fock_rank(m, n, t) == r
+
+
+def test_rank_unrank_large_sample():
+    m, n = 24, 8
+    rng = np.random.default_rng(0)
+    for r in rng.integers(0, math.comb(m + n - 1, n), 200):
+        occ = B.slos_fock_unrank(m, n, int(r))
+        assert occ.sum() == n
+        assert B.slos_fock_rank(m, n, occ) == r
+        assert (occ == O.fock_unrank(m, n, int(r))).all()
+
+
+@pytest.mark.parametrize("m,k", [(1, 3), (2, 2), (3, 3), (5, 3), (6, 4), (4, 1)])
+def test_transition_tables_against_enumeration(m, k):
+    pred, succ, nrm, minoff = B.slos_transition_tables(m, k)
+    layer = O.fock_basis(m, k)
+    prev = O.fock_basis(m, k - 1)
+    for r, t in enumerate(layer):
+        modes = [j for j in range(m) for _ in range(int(t[j]))]
+        seen = set()
+        for p in range(k):
+            e = int(pred[p, r])
+            if p > 0 and modes[p] == modes[p - 1]:
+                assert e == -1
+                continue
+            j = e & 31
+            assert j == modes[p]
+            tm = t.copy()
+            tm[j] -= 1
+            assert (e >> 5) == O.fock_rank(m, k - 1, tm)
+            seen.add(j)
+        assert seen == {j for j in range(m) if t[j] > 0}
+        assert abs(nrm[r] - math.sqrt(np.prod([math.factorial(int(v)) for v in t]))) <= 1e-6 * nrm[r]
+    for r, t in enumerate(prev):
+        for j in range(m):
+            tp = t.copy()
+            tp[j] += 1
+            assert succ[j, r] == O.fock_rank(m, k, tp)
+    for c in range(m + 1):
+        first = next((r for r, t in enumerate(layer) if min(j for j in range(m) if t[j] > 0) >= c), len(layer))
+        assert minoff[c] == first
+
+
+def test_transition_table_edge_counts():
+    # every (k-1)-photon state has m successors, so layer k has m * N_{k-1} edges
+    for m, k in [(5, 3), (7, 4), (20, 3)]:
+        pred, _, _, _ = B.slos_transition_tables(m, k, want_succ=False)
+        assert int((pred >= 0).sum()) == m * math.comb(m + k - 2, k - 1)
+
+
+def test_argument_errors_without_device():
+    L = B.lib()
+    h = ctypes.c_void_p()
+    assert L.slos_plan_create(0, 3, 0, ctypes.byref(h)) == B.SLOS_EINVAL
+    assert L.slos_plan_create(33, 3, 0, ctypes.byref(h)) == B.SLOS_EINVAL
+    assert L.slos_plan_create(6, 0, 0, ctypes.byref(h)) == B.SLOS_EINVAL
+    assert L.slos_plan_create(6, 17, 0, ctypes.byref(h)) == B.SLOS_EINVAL
+    assert L.slos_plan_create(6, 3, 8, ctypes.byref(h)) == B.SLOS_EINVAL
+    assert L.slos_plan_create(6, 3, 0, None) == B.SLOS_EINVAL
+    assert b"m must be" in L.slos_last_error() or len(L.slos_last_error()) > 0
+    occ = np.zeros(6, np.int32)
+    assert L.slos_fock_unrank(6, 3, 56, occ.ctypes.data_as(ctypes.c_void_p)) == B.SLOS_EINVAL
+    assert L.slos_fock_unrank(6, 3, -1, occ.ctypes.data_as(ctypes.c_void_p)) == B.SLOS_EINVAL
+    assert L.slos_fock_unrank(6, 3, 0, None) == B.SLOS_EINVAL
+    bad = np.array([1, 1, 0, 0, 0, -1], np.int32)
+    assert L.slos_fock_rank(6, 1, bad.ctypes.data_as(ctypes.c_void_p)) == -1
+    assert L.slos_transition_tables(6, 0, None, None, None, None) == B.SLOS_EINVAL
+    assert L.slos_transition_tables(40, 2, None, None, None, None) == B.SLOS_EINVAL
+    # compute calls with a NULL batch / bad sizes return before touching the device
+    assert L.fock_probs(None, None, None, None, 0, None) == B.SLOS_EINVAL
+    assert L.fock_amplitudes(None, None, None, None, 0, None) == B.SLOS_EINVAL
+    assert L.fock_probs_backward(None, None, None, None, None, 0, None) == B.SLOS_EINVAL
+    assert L.fock_amplitudes_backward(None, None, None, None, None, 0, None) == B.SLOS_EINVAL
+    assert L.slos_batch_create(None, 1, None, ctypes.byref(h)) == B.SLOS_EINVAL
+    n = ctypes.c_size_t()
+    assert L.mesh_workspace_bytes(1, 4, ctypes.byref(n)) == B.SLOS_EINVAL
+    assert L.mesh_workspace_bytes(20, 512, ctypes.byref(n)) == B.SLOS_OK and n.value > 0
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: every call below fails validation first
+    assert L.mesh_to_unitary(40, 1, fake, None, 1.0, fake, fake, 1 << 20, None) == B.SLOS_EINVAL
+    assert L.mesh_to_unitary(6, 3, fake, None, 1.0, fake, fake, 1 << 20, None) == B.SLOS_EINVAL  # x NULL needs B = 1
+    assert L.mesh_to_unitary(6, 1, fake, fake, 1.0, fake, fake, 8, None) == B.SLOS_EWORKSPACE
+    assert L.mesh_to_unitary(6, 1, fake, fake, 1.0, fake, None, 1 << 20, None) == B.SLOS_EWORKSPACE
+    assert L.mesh_to_unitary_backward(6, 1, fake, None, 1.0, fake, fake, fake, fake, 1 << 20, None) == B.SLOS_EINVAL
+    assert L.mesh_to_unitary_backward(6, 0, fake, fake, 1.0, fake, fake, None, fake, 1 << 20, None) == B.SLOS_EINVAL
+
+
+def test_plan_without_device_fails_cleanly():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            pytest.skip("a device is present")
+    except Exception:
+        pass
+    h = ctypes.c_void_p()
+    assert B.lib().slos_plan_create(6, 3, 0, ctypes.byref(h)) == B.SLOS_EHIP
+    assert not h.value
