@@ -1,0 +1,345 @@
+#!/usr/bin/env python3
+"""Benchmark of the strong-simulation hot path on one MI355X.
+
+One step = mesh -> U (per-sample angle encoding), fused Fock-space forward to
+probabilities, fused adjoint to dL/dU, mesh adjoint to dL/dtheta and dL/dx,
+for the 512-sample m=20, n=5 workload (Fock dimension 42504, input photons in
+modes 0,4,8,12,16).  dL/dp comes from the workload's linear readout and mean
+cross-entropy, evaluated once before timing; the readout itself is timed
+separately (train_step_ms) since it is ordinary PyTorch, not this path.
+
+Prints ONE JSON line.  Usage:
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-plain]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Fock amplitudes/sec, batched fwd+bwd (m=20,n=5); % of HBM peak; max |Δp|"
+HBM_PEAK_GBS = 8000.0
+# FP32 FMA on the vector ALUs without packed (dual) FP32 math, which this
+# build keeps disabled: 256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz.
+ALU_PEAK_TFLOPS = 78.6
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="clements_m20_n5_b512")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--eager", action="store_true", help="launch the step eagerly instead of replaying a HIP graph")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 1 GiB device copy (counter calibration under rocprofv3 --pmc)")
+    return ap.parse_args()
+
+
+def time_region(fn, iters, stream):
+    import torch
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(iters):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / iters  # ms
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the work shards by samples with one all-reduce of dL/dtheta; see the design notes). "
+              "Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2602_11092_amd import _binding as B
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    wl = W.make(args.workload)
+    m, Bn = wl.m, wl.B
+    n = int(wl.n.max())
+    assert (wl.n == n).all() and wl.theta is not None
+    N = math.comb(m + n - 1, n)
+
+    # ---- inputs resident in HBM
+    theta = torch.from_numpy(wl.theta).to(dev)
+    x = torch.from_numpy(wl.x).to(dev)
+    Wr = torch.from_numpy(wl.readout_W).to(dev)
+    br = torch.from_numpy(wl.readout_b).to(dev)
+    labels = torch.from_numpy(wl.labels).to(dev)
+    t0 = time.time()
+    plan = B.Plan(m, n)
+    batch = B.Batch(plan, wl.occ)
+    log("plan+batch %.2fs, out_len %d, fwd cfg %s, bwd cfg %s" % (
+        time.time() - t0, batch.out_len, batch.get_config(B.OP_PROBS), batch.get_config(B.OP_PROBS_BACKWARD)))
+
+    U = torch.empty(Bn, m, m, dtype=torch.complex64, device=dev)
+    p = torch.empty(batch.out_len, dtype=torch.float32, device=dev)
+    gU = torch.empty_like(U)
+    gt = torch.empty_like(theta)
+    gx = torch.empty_like(x)
+    mws = B.mesh_workspace(m, Bn, dev)
+    fws = batch.workspace(B.OP_PROBS, dev)
+    bws = batch.workspace(B.OP_PROBS_BACKWARD, dev)
+
+    # dL/dp from the readout + cross-entropy of the workload (once)
+    B.mesh_to_unitary(theta, x, wl.enc_scale, out=U, ws=mws)
+    B.fock_probs(batch, U, out=p, ws=fws)
+    pv = p.detach().clone().view(Bn, N).requires_grad_(True)
+    loss = torch.nn.functional.cross_entropy(pv @ Wr.t() + br, labels)
+    (gp,) = torch.autograd.grad(loss, pv)
+    gp = gp.contiguous().view(-1)
+    torch.cuda.synchronize()
+
+    def step():
+        B.mesh_to_unitary(theta, x, wl.enc_scale, out=U, ws=mws)
+        B.fock_probs(batch, U, out=p, ws=fws)
+        B.fock_probs_backward(batch, U, gp, out=gU, ws=bws)
+        B.mesh_to_unitary_backward(theta, x, wl.enc_scale, gU, ws=mws, out_theta=gt, out_x=gx)
+
+    step()
+    torch.cuda.synchronize()
+    if args.eager:
+        run = step
+    else:
+        side = torch.cuda.Stream()
+        side.wait_stream(stream)
+        with torch.cuda.stream(side):
+            step()
+        stream.wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            step()
+        run = graph.replay
+    for _ in range(args.warmup):
+        run()
+    torch.cuda.synchronize()
+    # ---- timed region: exactly K steps between two synchronisations
+    t_start = time.perf_counter()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        run()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall_ms = (time.perf_counter() - t_start) * 1e3
+    ms_per_step = e0.elapsed_time(e1) / args.steps
+    amps_per_step = Bn * N
+    value = amps_per_step / (ms_per_step * 1e-3)
+    log("step %.4f ms (wall %.4f ms/step), %.3e amps/s" % (ms_per_step, wall_ms / args.steps, value))
+
+    # ---- per-kernel averages (HIP events on the launch stream)
+    kiters = max(20, min(200, args.steps))
+    k_fwd = time_region(lambda: B.fock_probs(batch, U, out=p, ws=fws), kiters, stream)
+    k_bwd = time_region(lambda: B.fock_probs_backward(batch, U, gp, out=gU, ws=bws), kiters, stream)
+    k_mesh = time_region(lambda: B.mesh_to_unitary(theta, x, wl.enc_scale, out=U, ws=mws), kiters, stream)
+    k_meshb = time_region(lambda: B.mesh_to_unitary_backward(theta, x, wl.enc_scale, gU, ws=mws, out_theta=gt,
+                                                             out_x=gx), kiters, stream)
+    kernels_us = {"fock_probs": k_fwd * 1e3, "fock_probs_backward": k_bwd * 1e3,
+                  "mesh_to_unitary": k_mesh * 1e3, "mesh_to_unitary_backward": k_meshb * 1e3}
+    log("kernels (us): %s" % json.dumps({k: round(v, 2) for k, v in kernels_us.items()}))
+
+    # algorithmic traffic per sample: U in (8 m^2) and p out (4 N) forward;
+    # U in, dL/dp in (4 N) and dL/dU out (8 m^2) backward
+    u_bytes = 8 * m * m
+    fwd_bytes = Bn * (u_bytes + 4 * N)
+    bwd_bytes = Bn * (u_bytes + 4 * N + u_bytes)
+    step_bytes = fwd_bytes + bwd_bytes + 2 * Bn * (4 * m + u_bytes)  # + mesh in/out
+    # complex multiply-adds per sample: forward = every edge of every layer
+    # once (n * N); adjoint = recompute layers 1..n-1, recompute the last
+    # layer, two per edge in the last layer's pull and the lower pulls
+    edges_top = m * math.comb(m + n - 2, n - 1)
+    edges_all = n * N
+    edges_low = edges_all - edges_top
+    cmac_fwd = edges_all
+    cmac_bwd = edges_low + edges_top + 2 * edges_top + 2 * edges_low
+    flop_bwd = 8.0 * cmac_bwd * Bn
+    flop_fwd = 8.0 * cmac_fwd * Bn
+    dominant = "fock_probs_backward" if k_bwd >= k_fwd else "fock_probs"
+    if dominant == "fock_probs_backward":
+        dur, flops, nbytes = k_bwd, flop_bwd, bwd_bytes
+    else:
+        dur, flops, nbytes = k_fwd, flop_fwd, fwd_bytes
+    alu_tflops = flops / (dur * 1e-3) / 1e12
+    hbm_gbs = nbytes / (dur * 1e-3) / 1e9
+    roofline = {"kernel": dominant, "bound": "alu", "achieved": round(alu_tflops, 3), "peak": ALU_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(alu_tflops / ALU_PEAK_TFLOPS, 4), "traffic": None,
+                "hbm_gbs": round(hbm_gbs, 1), "hbm_frac": round(hbm_gbs / HBM_PEAK_GBS, 4),
+                "algorithmic_bytes": nbytes, "algorithmic_flop": flops, "avg_us": round(dur * 1e3, 3)}
+    tr = load_traffic(dominant)
+    if tr is not None:
+        roofline["traffic"] = tr
+    hbm_frac_step = step_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS
+
+    # ---- readout + cross-entropy + its backward, for the full training step
+    def readout_step():
+        pv2 = p.view(Bn, N).detach().requires_grad_(True)
+        l2 = torch.nn.functional.cross_entropy(pv2 @ Wr.t() + br, labels)
+        (g2,) = torch.autograd.grad(l2, pv2)
+        gp.copy_(g2.view(-1))
+    readout_ms = time_region(readout_step, 20, stream)
+
+    # ---- unbatched per-sample plain path on the same GPU
+    plain = None
+    if not args.no_plain:
+        plain = plain_path(B, wl, theta, x, gp, plan, N, dev, stream, ms_per_step)
+
+    # ---- copy probe for counter calibration
+    if args.copy_probe:
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(wl, U, p, gp, N)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "Fock amplitudes/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "m": m, "n": n, "batch": Bn, "fock_dim": N,
+                   "pass": "mesh fwd + fock_probs + fock_probs_backward + mesh bwd",
+                   "launch": "eager" if args.eager else "hip_graph"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "hbm_frac_step": round(hbm_frac_step, 4),
+        "kernels_us": {k: round(v, 3) for k, v in kernels_us.items()},
+        "train_step_ms": round(ms_per_step + readout_ms, 4),
+        "readout_ms": round(readout_ms, 4),
+        "plain_path": plain,
+        "max_abs_dp": cpu.get("max_abs_dp") if cpu else None,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def plain_path(B, wl, theta, x, gp, plan, N, dev, stream, ms_batched):
+    """Per-sample calls (B = 1, one launch per photon layer, no graph) of the
+    same four entry points; returns the time for the whole batch."""
+    import numpy as np
+    import torch
+    m, Bn = wl.m, wl.B
+    batch1 = B.Batch(plan, wl.occ[:1])
+    batch1.set_config(B.OP_PROBS, B.VARIANT_LAYERED)
+    batch1.set_config(B.OP_PROBS_BACKWARD, B.VARIANT_LAYERED)
+    fws = batch1.workspace(B.OP_PROBS, dev)
+    bws = batch1.workspace(B.OP_PROBS_BACKWARD, dev)
+    mws = B.mesh_workspace(m, 1, dev)
+    U1 = torch.empty(1, m, m, dtype=torch.complex64, device=dev)
+    p1 = torch.empty(N, dtype=torch.float32, device=dev)
+    g1 = torch.empty_like(U1)
+    gt = torch.zeros_like(theta)
+    gt1 = torch.empty_like(theta)
+    gx1 = torch.empty(1, m, dtype=torch.float32, device=dev)
+
+    def one(b):
+        xb = x[b:b + 1]
+        B.mesh_to_unitary(theta, xb, wl.enc_scale, out=U1, ws=mws)
+        B.fock_probs(batch1, U1, out=p1, ws=fws)
+        B.fock_probs_backward(batch1, U1, gp[b * N:(b + 1) * N], out=g1, ws=bws)
+        B.mesh_to_unitary_backward(theta, xb, wl.enc_scale, g1, ws=mws, out_theta=gt1, out_x=gx1)
+        gt.add_(gt1)
+
+    for b in range(4):
+        one(b)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for b in range(Bn):
+        one(b)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    return {"ms_per_step": round(ms, 3), "speedup_of_batched_fused": round(ms / ms_batched, 1),
+            "variant": "layered, B=1 per call, eager"}
+
+
+def cpu_baseline(wl, U, p, gp, N):
+    """The FP64 oracle (Ryser permanents and minor permanents) timed on the
+    host for a bounded sample of the workload's samples."""
+    import numpy as np
+    from oracle import oracle as O
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
+    U64 = U.cpu().numpy().astype(np.complex128)
+    pn = p.cpu().numpy()
+    gpn = gp.cpu().numpy().astype(np.float64)
+    worst = 0.0
+
+    def one(b):
+        a = O.amplitudes(U64[b], wl.occ[b])
+        O.probs_grad(U64[b], wl.occ[b], gpn[b * N:(b + 1) * N])
+        return float(np.abs(np.abs(a) ** 2 - pn[b * N:(b + 1) * N]).max())
+
+    O.build(force=False)
+    t0 = time.perf_counter()
+    worst = max(worst, one(0))
+    t1 = time.perf_counter() - t0
+    S = int(max(1, min(wl.B - 1, 15.0 / max(t1, 1e-3))))
+    t0 = time.perf_counter()
+    for b in range(1, 1 + S):
+        worst = max(worst, one(b))
+    dt = time.perf_counter() - t0
+    return {"value": S * N / dt, "unit": "Fock amplitudes/s", "cores": threads, "kind": "oracle",
+            "sample": "%d of %d samples, forward amplitudes + minor-permanent gradient, FP64 Ryser, OpenMP" % (
+                S, wl.B),
+            "seconds": round(dt, 2), "max_abs_dp": worst}
+
+
+def load_traffic(kernel):
+    """HBM bytes per launch from the committed counter summary, if it was taken
+    on the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s.json" % kernel)
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+        if d.get("src_sha256") != sources_sha256():
+            return None
+        return d.get("bytes_per_launch")
+    except Exception:
+        return None
+
+
+def sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2602_11092_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()
+
+
+if __name__ == "__main__":
+    main()

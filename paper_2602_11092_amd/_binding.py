@@ -329,15 +329,20 @@ def mesh_to_unitary(theta: torch.Tensor, x: Optional[torch.Tensor], enc_scale: f
 
 def mesh_to_unitary_backward(theta: torch.Tensor, x: Optional[torch.Tensor], enc_scale: float,
                              grad_U: torch.Tensor, need_grad_x: bool = True,
-                             ws: Optional[torch.Tensor] = None):
+                             ws: Optional[torch.Tensor] = None, out_theta: Optional[torch.Tensor] = None,
+                             out_x: Optional[torch.Tensor] = None):
     """(grad_theta [m(m-1)], grad_x [B, m] or None)."""
     B, m = grad_U.shape[0], grad_U.shape[1]
     _require(grad_U, "grad_U", torch.complex64, (B, m, m))
     _require(theta, "theta", torch.float32, (m * (m - 1),))
     if x is not None:
         _require(x, "x", torch.float32, (B, m))
-    gt = torch.empty_like(theta)
-    gx = torch.empty(B, m, dtype=torch.float32, device=theta.device) if (x is not None and need_grad_x) else None
+    gt = out_theta if out_theta is not None else torch.empty_like(theta)
+    _require(gt, "grad_theta", torch.float32, (m * (m - 1),))
+    gx = None
+    if x is not None and need_grad_x:
+        gx = out_x if out_x is not None else torch.empty(B, m, dtype=torch.float32, device=theta.device)
+        _require(gx, "grad_x", torch.float32, (B, m))
     if ws is None:
         ws = mesh_workspace(m, B, theta.device)
     _check("mesh_to_unitary_backward",

@@ -4,18 +4,17 @@
 //
 // Rectangular mesh: column c holds MZIs on pairs (k, k+1), k = c mod 2 + 2p.
 // MZIs of one column touch disjoint pairs, so a column is applied to all
-// rows at once.  W1 = columns [0, m/2), W2 = the rest; both factors are built
-// by one workgroup (one half each), then every sample forms
-// U_b = W2 diag(exp(i enc x_b)) W1.  The adjoint reduces dL/dW1, dL/dW2 over
-// the batch in a fixed order, then sweeps the columns backwards, recovering
-// each column's input as T^H times its output (T unitary).
+// rows at once.  W1 = columns [0, m/2), W2 = the rest.  All 2x2 MZI matrices
+// are formed in parallel first; one workgroup then sweeps the columns of both
+// factors (one half each) and every sample forms U_b = W2 diag(e^{i enc x_b}) W1.
+// The adjoint computes each sample's contribution to dL/dW1 and dL/dW2 (and
+// dL/dx_b) in its own workgroup, sums them over the batch in a fixed order,
+// then sweeps the columns backwards, recovering each column's input as
+// T^H times its output (T unitary).
 #include "slos_internal.h"
 
 namespace slos {
 namespace {
-
-constexpr int kMeshSamplesPerBlock = 4;
-constexpr int kMeshMaxBlocks = 256;
 
 struct Mzi {
     float2 t00, t01, t10, t11;
@@ -46,17 +45,46 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
 }
 __device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
 
-__device__ __forceinline__ int col_start(int c, int m) { return ((c + 1) / 2) * (m / 2) + (c / 2) * ((m - 1) / 2); }
+__host__ __device__ __forceinline__ int col_start(int c, int m) {
+    return ((c + 1) / 2) * (m / 2) + (c / 2) * ((m - 1) / 2);
+}
+__host__ __device__ __forceinline__ int num_mzi(int m) { return m * (m - 1) / 2; }
 
-// Builds W1 (half 0) and W2 (half 1) into Wout[2][m][m].  1024 threads:
-// half = tid / 512, pair slot = (tid % 512) / 32, column of W = tid % 32.
+// Workspace layout (float2 units): W[2][m][m] | T[nmzi][4] | G[2][m][m] | partial[B][2][m][m]
+struct MeshWs {
+    float2* W;
+    Mzi* T;
+    float2* G;
+    float2* partial;
+};
+__host__ __device__ inline size_t mesh_ws_floats2(int m, int B) {
+    return (size_t)2 * m * m + (size_t)num_mzi(m) * 4 + (size_t)2 * m * m + (size_t)B * 2 * m * m;
+}
+__host__ __device__ inline MeshWs mesh_ws_split(void* ws, int m) {
+    MeshWs w;
+    w.W = (float2*)ws;
+    w.T = (Mzi*)(w.W + 2 * m * m);
+    w.G = (float2*)(w.T + num_mzi(m));
+    w.partial = w.G + 2 * m * m;
+    return w;
+}
+
+// Builds W1 (half 0) and W2 (half 1) into Wout[2][m][m] and stores every
+// MZI matrix in Tout.  1024 threads: half = tid / 512, pair slot =
+// (tid % 512) / 32, column of W = tid % 32.
 __global__ __launch_bounds__(1024) void mesh_factors_kernel(int m, const float* __restrict__ theta,
-                                                            float2* __restrict__ Wout) {
+                                                            float2* __restrict__ Wout, Mzi* __restrict__ Tout) {
     __shared__ float2 W[2][32][33];
+    __shared__ Mzi Ts[496];
     const int tid = threadIdx.x;
+    const int nm = num_mzi(m);
+    for (int q = tid; q < nm; q += 1024) {
+        const Mzi T = mzi(theta[2 * q], theta[2 * q + 1]);
+        Ts[q] = T;
+        Tout[q] = T;
+    }
     const int half = tid >> 9, pr = (tid >> 5) & 15, col = tid & 31;
-    for (int r = pr; r < 32; r += 16)
-        W[half][r][col] = make_float2((r == col) ? 1.f : 0.f, 0.f);
+    for (int r = pr; r < 32; r += 16) W[half][r][col] = make_float2((r == col) ? 1.f : 0.f, 0.f);
     __syncthreads();
     const int split = m / 2;
     const int nsteps = max(split, m - split);
@@ -65,8 +93,7 @@ __global__ __launch_bounds__(1024) void mesh_factors_kernel(int m, const float* 
         const int cend = half == 0 ? split : m;
         const int k = (c & 1) + 2 * pr;
         if (c < cend && k <= m - 2 && col < m) {
-            const int q = col_start(c, m) + pr;
-            const Mzi T = mzi(theta[2 * q], theta[2 * q + 1]);
+            const Mzi T = Ts[col_start(c, m) + pr];
             const float2 x0 = W[half][k][col], x1 = W[half][k + 1][col];
             float2 y0 = cmul(T.t00, x0), y1 = cmul(T.t10, x0);
             c_fma(y0, T.t01, x1);
@@ -108,78 +135,85 @@ __global__ __launch_bounds__(256) void mesh_apply_kernel(int m, const float2* __
     }
 }
 
-// Per-block partial sums of dL/dW1 = sum_b conj(S_b) (W2^H G_b) and
-// dL/dW2 = sum_b (G_b W1^H) conj(S_b), plus dL/dx_b.
-__global__ __launch_bounds__(256) void mesh_bwd_samples_kernel(int m, int B, const float2* __restrict__ Wf,
+// One sample per block: Y = W2^H G_b, V = G_b W1^H; contributions
+// conj(S_b[r]) Y[r][c] to dL/dW1 and V[r][c] conj(S_b[c]) to dL/dW2, and
+// dL/dx_b[k] = -enc Im(conj((W2^H G_b W1^H)[k][k]) S_b[k]).
+__global__ __launch_bounds__(256) void mesh_bwd_samples_kernel(int m, const float2* __restrict__ Wf,
                                                                const float* __restrict__ x, float enc,
                                                                const float2* __restrict__ gU,
                                                                float* __restrict__ gx,
-                                                               float2* __restrict__ partial, int per_block) {
-    __shared__ float2 W1[32][33], W2[32][33], G[32][33], Y[32][33], V[32][33];
+                                                               float2* __restrict__ partial) {
+    __shared__ float2 W1[32][33], W2[32][33], G[32][33], Y[32][33];
     __shared__ float2 S[32];
     const int tid = threadIdx.x;
+    const int b = blockIdx.x;
     for (int q = tid; q < m * m; q += 256) {
         const int r = q / m, c = q % m;
         W1[r][c] = Wf[q];
         W2[r][c] = Wf[(size_t)m * m + q];
+        G[r][c] = gU[(size_t)b * m * m + q];
     }
-    float2 pa[4], pb[4];
-    for (int e = 0; e < 4; ++e) pa[e] = pb[e] = c_zero();
-    const int b0 = blockIdx.x * per_block;
-    const int b1 = min(B, b0 + per_block);
-    for (int b = b0; b < b1; ++b) {
+    if (tid < m) {
+        float2 s = make_float2(1.f, 0.f);
+        if (x) {
+            float sn, cs;
+            sincosf(enc * x[(size_t)b * m + tid], &sn, &cs);
+            s = make_float2(cs, sn);
+        }
+        S[tid] = s;
+    }
+    __syncthreads();
+    float2* pa = partial + (size_t)b * 2 * m * m;
+    float2* pb = pa + m * m;
+    for (int q = tid; q < m * m; q += 256) {
+        const int r = q / m, c = q % m;
+        float2 y = c_zero(), v = c_zero();
+        for (int k = 0; k < m; ++k) {
+            c_fma_conj(y, W2[k][r], G[k][c]);    // (W2^H G)[r][c]
+            c_fma(v, G[r][k], cconj(W1[c][k]));  // (G W1^H)[r][c]
+        }
+        Y[r][c] = y;
+        pa[q] = cmul(cconj(S[r]), y);
+        pb[q] = cmul(v, cconj(S[c]));
+    }
+    if (gx) {
         __syncthreads();
-        for (int q = tid; q < m * m; q += 256) G[q / m][q % m] = gU[(size_t)b * m * m + q];
         if (tid < m) {
-            float2 s = make_float2(1.f, 0.f);
-            if (x) {
-                float sn, cs;
-                sincosf(enc * x[(size_t)b * m + tid], &sn, &cs);
-                s = make_float2(cs, sn);
-            }
-            S[tid] = s;
-        }
-        __syncthreads();
-        for (int q = tid; q < m * m; q += 256) {
-            const int r = q / m, c = q % m;
-            float2 y = c_zero(), v = c_zero();
-            for (int k = 0; k < m; ++k) {
-                c_fma_conj(y, W2[k][r], G[k][c]);       // (W2^H G)[r][c]
-                c_fma(v, G[r][k], cconj(W1[c][k]));     // (G W1^H)[r][c]
-            }
-            Y[r][c] = y;
-            V[r][c] = v;
-        }
-        __syncthreads();
-        if (gx && tid < m) {
             float2 gs = c_zero();  // (W2^H G W1^H)[k][k]
             for (int i = 0; i < m; ++i) c_fma(gs, Y[tid][i], cconj(W1[tid][i]));
             const float2 z = cmul(cconj(gs), S[tid]);
             gx[(size_t)b * m + tid] = -enc * z.y;
         }
-        for (int e = 0; e < 4; ++e) {
-            const int q = tid + e * 256;
-            if (q < m * m) {
-                const int r = q / m, c = q % m;
-                c_fma(pa[e], cconj(S[r]), Y[r][c]);
-                c_fma(pb[e], V[r][c], cconj(S[c]));
-            }
-        }
-    }
-    for (int e = 0; e < 4; ++e) {
-        const int q = tid + e * 256;
-        if (q < m * m) {
-            partial[((size_t)blockIdx.x * 2 + 0) * m * m + q] = pa[e];
-            partial[((size_t)blockIdx.x * 2 + 1) * m * m + q] = pb[e];
-        }
     }
 }
 
-// Fixed-order sum of the partials, then the reverse column sweeps of both
-// factors.  Thread layout as in mesh_factors_kernel.
-__global__ __launch_bounds__(1024) void mesh_bwd_final_kernel(int m, const float* __restrict__ theta,
+// G[e] = sum_b partial[b][e] for e < 2 m^2, in a fixed order: 64 lanes per
+// entry take the samples in a strided order, then a fixed tree.
+__global__ __launch_bounds__(256) void mesh_bwd_reduce_kernel(int m, int B, const float2* __restrict__ partial,
+                                                              float2* __restrict__ G) {
+    __shared__ float2 red[256];
+    const int E = 2 * m * m;
+    const int e = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int r = threadIdx.x & 63;
+    float2 s = c_zero();
+    if (e < E) {
+#pragma unroll 8
+        for (int b = r; b < B; b += 64) s = c_add(s, partial[(size_t)b * E + e]);
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 32; w > 0; w >>= 1) {
+        if (r < w) red[threadIdx.x] = c_add(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (r == 0 && e < E) G[e] = red[threadIdx.x];
+}
+
+// Reverse column sweeps of both factors.  Thread layout as in mesh_factors_kernel.
+__global__ __launch_bounds__(1024) void mesh_bwd_sweep_kernel(int m, const float* __restrict__ theta,
                                                               const float2* __restrict__ Wf,
-                                                              const float2* __restrict__ partial, int nblk,
+                                                              const Mzi* __restrict__ Tm,
+                                                              const float2* __restrict__ Gf,
                                                               float* __restrict__ gtheta) {
     __shared__ float2 X[2][32][33], G[2][32][33];
     const int tid = threadIdx.x;
@@ -187,9 +221,7 @@ __global__ __launch_bounds__(1024) void mesh_bwd_final_kernel(int m, const float
     for (int r = pr; r < m; r += 16) {
         if (col < m) {
             const int q = r * m + col;
-            float2 s = c_zero();
-            for (int blk = 0; blk < nblk; ++blk) s = c_add(s, partial[((size_t)blk * 2 + half) * m * m + q]);
-            G[half][r][col] = s;
+            G[half][r][col] = Gf[(size_t)half * m * m + q];
             X[half][r][col] = Wf[(size_t)half * m * m + q];
         }
     }
@@ -202,8 +234,7 @@ __global__ __launch_bounds__(1024) void mesh_bwd_final_kernel(int m, const float
         const int k = (c & 1) + 2 * pr;
         if (c < cend && k <= m - 2) {  // uniform over the 32 lanes of this pair slot
             const int q = col_start(c, m) + pr;
-            const float th = theta[2 * q], ph = theta[2 * q + 1];
-            const Mzi T = mzi(th, ph);
+            const Mzi T = Tm[q];
             float2 r0 = c_zero(), r1 = c_zero(), g0 = c_zero(), g1 = c_zero();
             if (col < m) {
                 const float2 x0 = X[half][k][col], x1 = X[half][k + 1][col];
@@ -216,6 +247,7 @@ __global__ __launch_bounds__(1024) void mesh_bwd_final_kernel(int m, const float
             }
             // G_T[a][b] = sum_col g_a conj(r_b)
             float2 p[4] = {cmul(g0, cconj(r0)), cmul(g0, cconj(r1)), cmul(g1, cconj(r0)), cmul(g1, cconj(r1))};
+#pragma unroll
             for (int e = 0; e < 4; ++e) {
 #pragma unroll
                 for (int o = 16; o > 0; o >>= 1) {
@@ -224,6 +256,7 @@ __global__ __launch_bounds__(1024) void mesh_bwd_final_kernel(int m, const float
                 }
             }
             if (col == 0) {
+                const float th = theta[2 * q], ph = theta[2 * q + 1];
                 float st, ct, sp, cp;
                 sincosf(th, &st, &ct);
                 sincosf(ph, &sp, &cp);
@@ -242,7 +275,7 @@ __global__ __launch_bounds__(1024) void mesh_bwd_final_kernel(int m, const float
                 // dT/dphi = [[ i t00, 0 ], [ i t10, 0 ]]
                 const float2 e00 = make_float2(-T.t00.y, T.t00.x);
                 const float2 e10 = make_float2(-T.t10.y, T.t10.x);
-                float gph = p[0].x * e00.x + p[0].y * e00.y + p[2].x * e10.x + p[2].y * e10.y;
+                const float gph = p[0].x * e00.x + p[0].y * e00.y + p[2].x * e10.x + p[2].y * e10.y;
                 gtheta[2 * q] = gth;
                 gtheta[2 * q + 1] = gph;
             }
@@ -262,12 +295,7 @@ __global__ __launch_bounds__(1024) void mesh_bwd_final_kernel(int m, const float
     }
 }
 
-int mesh_blocks(int B) { return std::max(1, std::min(kMeshMaxBlocks, (B + kMeshSamplesPerBlock - 1) / kMeshSamplesPerBlock)); }
-
-size_t mesh_ws(int m, int B) {
-    const size_t mm = (size_t)m * m * sizeof(float2);
-    return 2 * mm + (size_t)mesh_blocks(B) * 2 * mm;
-}
+size_t mesh_ws(int m, int B) { return mesh_ws_floats2(m, B) * sizeof(float2); }
 
 }  // namespace
 }  // namespace slos
@@ -290,9 +318,9 @@ extern "C" int mesh_to_unitary(int m, int B, const float* theta, const float* x,
     if (!theta || !U) return fail(SLOS_EINVAL, "mesh_to_unitary: NULL pointer");
     if (!ws || ws_bytes < mesh_ws(m, B)) return fail(SLOS_EWORKSPACE, "mesh_to_unitary: workspace too small");
     hipStream_t s = (hipStream_t)stream;
-    float2* Wf = (float2*)ws;
-    hipLaunchKernelGGL(mesh_factors_kernel, dim3(1), dim3(1024), 0, s, m, theta, Wf);
-    hipLaunchKernelGGL(mesh_apply_kernel, dim3(B), dim3(256), 0, s, m, (const float2*)Wf, x, enc_scale, (float2*)U);
+    MeshWs w = mesh_ws_split(ws, m);
+    hipLaunchKernelGGL(mesh_factors_kernel, dim3(1), dim3(1024), 0, s, m, theta, w.W, w.T);
+    hipLaunchKernelGGL(mesh_apply_kernel, dim3(B), dim3(256), 0, s, m, (const float2*)w.W, x, enc_scale, (float2*)U);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(SLOS_EHIP, std::string("mesh_to_unitary launch: ") + hipGetErrorString(e));
     return SLOS_OK;
@@ -308,16 +336,15 @@ extern "C" int mesh_to_unitary_backward(int m, int B, const float* theta, const 
     if (!theta || !grad_U || !grad_theta) return fail(SLOS_EINVAL, "mesh_to_unitary_backward: NULL pointer");
     if (!ws || ws_bytes < mesh_ws(m, B)) return fail(SLOS_EWORKSPACE, "mesh_to_unitary_backward: workspace too small");
     hipStream_t s = (hipStream_t)stream;
-    float2* Wf = (float2*)ws;
-    float2* partial = Wf + 2 * (size_t)m * m;
-    const int nblk = mesh_blocks(B);
-    const int per_block = (B + nblk - 1) / nblk;
+    MeshWs w = mesh_ws_split(ws, m);
     float* gx = (x && grad_x) ? grad_x : nullptr;
-    hipLaunchKernelGGL(mesh_factors_kernel, dim3(1), dim3(1024), 0, s, m, theta, Wf);
-    hipLaunchKernelGGL(mesh_bwd_samples_kernel, dim3(nblk), dim3(256), 0, s, m, B, (const float2*)Wf, x, enc_scale,
-                       (const float2*)grad_U, gx, partial, per_block);
-    hipLaunchKernelGGL(mesh_bwd_final_kernel, dim3(1), dim3(1024), 0, s, m, theta, (const float2*)Wf,
-                       (const float2*)partial, nblk, grad_theta);
+    hipLaunchKernelGGL(mesh_factors_kernel, dim3(1), dim3(1024), 0, s, m, theta, w.W, w.T);
+    hipLaunchKernelGGL(mesh_bwd_samples_kernel, dim3(B), dim3(256), 0, s, m, (const float2*)w.W, x, enc_scale,
+                       (const float2*)grad_U, gx, w.partial);
+    hipLaunchKernelGGL(mesh_bwd_reduce_kernel, dim3((2 * m * m + 3) / 4), dim3(256), 0, s, m, B,
+                       (const float2*)w.partial, w.G);
+    hipLaunchKernelGGL(mesh_bwd_sweep_kernel, dim3(1), dim3(1024), 0, s, m, theta, (const float2*)w.W,
+                       (const Mzi*)w.T, (const float2*)w.G, grad_theta);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(SLOS_EHIP, std::string("mesh_to_unitary_backward launch: ") + hipGetErrorString(e));
     return SLOS_OK;

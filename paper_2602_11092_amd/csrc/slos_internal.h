@@ -15,20 +15,34 @@ namespace slos {
 
 constexpr int kMaxModes = SLOS_MAX_MODES;
 constexpr int kMaxPhotons = SLOS_MAX_PHOTONS;
-constexpr int kModeBits = 5;  // predecessor entries pack (rank << 5) | mode
+constexpr int kModeBits = 5;  // host tables pack (rank << 5) | mode
 static_assert((1 << kModeBits) >= kMaxModes, "mode field too narrow");
+// Device predecessor entries hold two byte offsets: (rank << 11) | (mode << 3),
+// the LDS offset of the predecessor's amplitude (rank * 8 = (e >> 11) << 3)
+// and of the coefficient U[mode][i_k] in a 33-slot column whose slot 32 is
+// zero.  An empty entry points at that zero slot (and at predecessor 0).
+// successor rows are padded to a multiple of four entries (16-byte loads)
+__host__ __device__ constexpr int succ_row_len(int m) { return (m + 3) & ~3; }
+constexpr int kPredRankShift = 11;
+constexpr int kPredModeMask = 0x7FF;
+constexpr int kPredEmpty = 32 << 3;
+constexpr int kUcolSlots = 33;
 
 // One photon layer k of the transition graph (all k-photon states over m
 // modes, in basis order).  Device pointers.
 struct LayerDev {
-    const int32_t* pred;    // [k][N]: (rank of t - e_j in layer k-1) << 5 | j for the p-th
-                            // entry of t's sorted mode list, -1 when that entry repeats
-                            // the previous one (the same predecessor)
-    const int32_t* succ;    // [m][N_{k-1}]: rank of t' + e_j in layer k (nullptr if forward-only)
+    const int4* predv;      // [ngrp][N] int4: entries 4g..4g+3 of t's predecessor list, each
+                            // (rank of t - e_j in layer k-1) << 5 | j for that entry of t's
+                            // sorted mode list, -1 when it repeats the previous entry (same
+                            // predecessor) or lies past k
+    const int32_t* succ;    // [N_{k-1}][MP]: rank in layer k of t' + e_j, one row per t'
+                            // (MP = succ_row_len(m); nullptr if forward-only)
     const float* nrm;       // [N]: sqrt(prod_j t_j!)
     const int32_t* minoff;  // [m+1]: first rank whose smallest occupied mode is >= c
     int64_t N;              // number of states C(m+k-1, k)
     int64_t cum;            // number of states with fewer than k photons (sum of N_0..N_{k-1})
+    int32_t ngrp;           // ceil(k / 4)
+    int32_t pad;
 };
 
 // Per-sample description of a batch (device pointers).
@@ -97,6 +111,13 @@ int launch_layered_bwd(const slos_batch_s& Bt, int block, const float2* U, const
 
 }  // namespace slos
 
+// Global-address-space views of table pointers that kernels read out of
+// descriptor structs (such loads would otherwise be emitted as flat loads).
+typedef __attribute__((address_space(1))) const int4 g_int4;
+typedef __attribute__((address_space(1))) const int32_t g_int;
+typedef __attribute__((address_space(1))) const float g_float;
+typedef __attribute__((address_space(1))) const float2 g_float2;
+
 // complex helpers (device)
 __device__ __forceinline__ float2 c_zero() { return make_float2(0.f, 0.f); }
 // acc += a * b
@@ -115,3 +136,9 @@ __device__ __forceinline__ void c_fma_conj(float2& acc, float2 a, float2 b) {
 }
 __device__ __forceinline__ float2 c_scale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
 __device__ __forceinline__ float2 c_add(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+
+// Load through a global-address-space view of p.
+template <class T>
+__device__ __forceinline__ T ldg(const T* p) {
+    return *(__attribute__((address_space(1))) const T*)p;
+}

@@ -78,7 +78,7 @@ __global__ __launch_bounds__(BLOCK) void layered_layer_kernel(int m, const Layer
                                                               const float2* __restrict__ prev, float2* __restrict__ cur,
                                                               void* __restrict__ out, const void* __restrict__ gin,
                                                               int SG) {
-    __shared__ float2 us[64 * 32];
+    __shared__ float2 us[64 * kUcolSlots];
     const int tid = threadIdx.x;
     const int bl = tid % SG;
     const int tl = tid / SG;
@@ -87,13 +87,14 @@ __global__ __launch_bounds__(BLOCK) void layered_layer_kernel(int m, const Layer
     const int b = g * SG + bl;
     const int n_b = (b < Bt.B) ? Bt.n[b] : -1;
     const bool active = (mode == kForward) ? n_b >= k : (mode == kRecompute) ? n_b > k : n_b == k;
-    // stage column i_k of U for every sample of the group
+    // stage column i_k of U for every sample of the group (slot 32 = 0)
+    for (int q = tid; q < SG; q += BLOCK) us[q * kUcolSlots + 32] = c_zero();
     for (int q = tid; q < SG * m; q += BLOCK) {
         const int bq = q % SG, j = q / SG;
         const int bb = g * SG + bq;
         if (bb < Bt.B && Bt.n[bb] >= k) {
             const int ik = Bt.modes[(size_t)bb * kMaxPhotons + k - 1];
-            us[bq * 32 + j] = U[((size_t)bb * m + j) * m + ik];
+            us[bq * kUcolSlots + j] = U[((size_t)bb * m + j) * m + ik];
         }
     }
     __syncthreads();
@@ -109,12 +110,18 @@ __global__ __launch_bounds__(BLOCK) void layered_layer_kernel(int m, const Layer
         const bool need_d = !(mode == kSeed && !PROBS);
         if (need_d) {
             if (k == 1) {
-                acc = us[bl * 32 + t];
+                acc = us[bl * kUcolSlots + t];
             } else {
-                for (int p = 0; p < k; ++p) {
-                    const int e = L.pred[(size_t)p * N + t];
-                    if (e >= 0)
-                        c_fma(acc, us[bl * 32 + (e & 31)], prev[((size_t)g * Nprev + (e >> kModeBits)) * SG + bl]);
+                for (int gq = 0; gq < L.ngrp; ++gq) {
+                    const int4 e4 = L.predv[(size_t)gq * N + t];
+                    const int es[4] = {e4.x, e4.y, e4.z, e4.w};
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        // empty entries name the zero slot 32 of the coefficient column
+                        const unsigned e = (unsigned)es[q];
+                        c_fma(acc, us[bl * kUcolSlots + ((e & kPredModeMask) >> 3)],
+                              prev[((size_t)g * Nprev + (e >> kPredRankShift)) * SG + bl]);
+                    }
                 }
             }
         }
@@ -142,7 +149,7 @@ __global__ __launch_bounds__(BLOCK) void layered_pull_kernel(int m, const LayerD
                                                              const float2* __restrict__ gk, float2* __restrict__ gkm1,
                                                              const float2* __restrict__ dkm1,
                                                              float2* __restrict__ partial, int SG, int NGRP) {
-    __shared__ float2 us[64 * 32];
+    __shared__ float2 us[64 * kUcolSlots];
     __shared__ float2 Hs[32 * BLOCK];
     const int tid = threadIdx.x;
     const int bl = tid % SG;
@@ -157,7 +164,7 @@ __global__ __launch_bounds__(BLOCK) void layered_pull_kernel(int m, const LayerD
         const int bb = g * SG + bq;
         if (bb < Bt.B && Bt.n[bb] >= k) {
             const int ik = Bt.modes[(size_t)bb * kMaxPhotons + k - 1];
-            us[bq * 32 + j] = U[((size_t)bb * m + j) * m + ik];
+            us[bq * kUcolSlots + j] = U[((size_t)bb * m + j) * m + ik];
         }
     }
     for (int j = 0; j < 32; ++j) Hs[j * BLOCK + tid] = c_zero();
@@ -170,9 +177,9 @@ __global__ __launch_bounds__(BLOCK) void layered_pull_kernel(int m, const LayerD
             const float2 dv = (k >= 2) ? dkm1[((size_t)g * Nkm1 + tp) * SG + bl] : make_float2(1.f, 0.f);
             float2 acc = c_zero();
             for (int j = 0; j < m; ++j) {
-                const int s = succ[(size_t)j * Nkm1 + tp];
+                const int s = succ[(size_t)tp * succ_row_len(m) + j];
                 const float2 gv = gk[((size_t)g * Nk + s) * SG + bl];
-                c_fma_conj(acc, us[bl * 32 + j], gv);
+                c_fma_conj(acc, us[bl * kUcolSlots + j], gv);
                 float2 h = Hs[j * BLOCK + tid];
                 c_fma_conj(h, dv, gv);
                 Hs[j * BLOCK + tid] = h;
