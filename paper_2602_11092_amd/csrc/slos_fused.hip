@@ -34,43 +34,73 @@
 namespace slos {
 namespace {
 
-constexpr int kSU = 2;     // states per thread per iteration in the gathers
+// LDS map, byte addresses (the kernels declare no static LDS, so dynamic LDS
+// starts at address 0): the coefficient column, then the state buffers.
+constexpr uint32_t kUcolAddr = 0;                    // [33] column i_k of U; slot 32 stays zero
+constexpr uint32_t kXAddr = kUcolSlots * 8;          // state buffers
+static_assert(kUcolAddr == 0, "compact entries address the coefficient column directly");
+
+constexpr int kLU = 4;  // states per thread per iteration in the forward gathers
+constexpr int kLP = 2;  // states whose gathers are issued together
 
 template <int CTRL, int ROW_MASK = 0xF>
 __device__ __forceinline__ float dpp(float v) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xF, false));
 }
 
-// Sum over the 64 lanes of a wave in a fixed order; the result is uniform.
-__device__ __forceinline__ float wave_total(float v) {
+// Sum over the 64 lanes of a wave in a fixed order; lane 63 ends up holding it.
+__device__ __forceinline__ float wave_sum63(float v) {
     v += dpp<0xB1>(v);        // quad_perm [1,0,3,2]
     v += dpp<0x4E>(v);        // quad_perm [2,3,0,1]
     v += dpp<0x141>(v);       // row_half_mirror
     v += dpp<0x140>(v);       // row_mirror: every lane holds its row's sum
     v += dpp<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
     v += dpp<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3: lane 63 holds the total
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+    return v;
 }
 
-__device__ __forceinline__ int comp(const int4& e, int q) { return q == 0 ? e.x : q == 1 ? e.y : q == 2 ? e.z : e.w; }
+// A wave-uniform value re-materialised at its point of use: tests on it
+// become a scalar compare right before the branch instead of lane masks
+// hoisted to the kernel entry (which exhaust the scalar registers).
+__device__ __forceinline__ int fresh(int x) {
+    x = __builtin_amdgcn_readfirstlane(x);
+    asm volatile("" : "+s"(x));
+    return x;
+}
+// A fresh copy of a per-lane value (no reuse of values derived from it
+// across unrolled blocks, which would keep them live throughout).
+__device__ __forceinline__ int fresh_v(int x) {
+    asm volatile("" : "+v"(x));
+    return x;
+}
+// bit i of x, tested on a fresh copy
+__device__ __forceinline__ bool has(int x, int i) { return (fresh(x) >> i) & 1; }
+// does [s*BLOCK, (s+1)*BLOCK) meet [lo, hi)?
+template <int BLOCK>
+__device__ __forceinline__ bool slot_meets(int s, int lo, int hi) {
+    return (s + 1) * BLOCK > fresh(lo) && s * BLOCK < fresh(hi);
+}
+__host__ __device__ constexpr uint32_t range_bits(int lo, int hi) {
+    return (hi >= 32 ? 0xFFFFFFFFu : ((1u << hi) - 1u)) & ~((1u << lo) - 1u);
+}
+
+__device__ __forceinline__ uint32_t comp(const uint4& e, int q) { return q == 0 ? e.x : q == 1 ? e.y : q == 2 ? e.z : e.w; }
 
 // The first NQ entries of predecessor group h for states u0..u0+SP-1,
-// branch-free, so all their LDS reads issue before one wait.  Entries are byte
-// offsets, (rank << 11) | (mode << 3); an empty entry names the zero slot of
-// the coefficient column, so it needs no test.
+// branch-free so that all their LDS reads issue before one wait.  A compact
+// entry holds two byte offsets: e >> 22 into the coefficient column (an
+// empty entry names its zero slot) and e & 0x3FFFF8 into layer k-1 at pb.
 template <int SU, int NG, int SP, int NQ>
-__device__ __forceinline__ void gather_group(const int4 (&e)[SU][NG], int h, int u0, const float2* __restrict__ prev,
-                                             const float2* __restrict__ ucol, float2 (&acc)[SU]) {
-    const char* pb = (const char*)prev;
-    const char* ub = (const char*)ucol;
+__device__ __forceinline__ void gather_group(const uint4 (&e)[SU][NG], int h, int u0, uint32_t pb,
+                                             float2 (&acc)[SU]) {
     float2 uv[NQ][SP], dv[NQ][SP];
 #pragma unroll
     for (int q = 0; q < NQ; ++q)
 #pragma unroll
         for (int v = 0; v < SP; ++v) {
-            const unsigned x = (unsigned)comp(e[u0 + v][h], q);
-            uv[q][v] = *(const float2*)(ub + (x & kPredModeMask));
-            dv[q][v] = *(const float2*)(pb + ((x >> kPredRankShift) << 3));
+            const uint32_t x = comp(e[u0 + v][h], q);
+            uv[q][v] = lds_ld(kUcolAddr + (x >> kPredCompactModeShift));
+            dv[q][v] = lds_ld(pb + (x & kPredCompactRankMask));
         }
 #pragma unroll
     for (int q = 0; q < NQ; ++q)
@@ -78,74 +108,82 @@ __device__ __forceinline__ void gather_group(const int4 (&e)[SU][NG], int h, int
         for (int v = 0; v < SP; ++v) c_fma(acc[u0 + v], uv[q][v], dv[q][v]);
 }
 
-// acc[u] = d_k[t0 + u*BLOCK] for u < SU (0 where t >= tlim), pulled from
-// layer k-1 in LDS (prev) with coefficients ucol[j] = U[j][i_k].  The table
-// entries of all SU states and NG groups are loaded first (many loads in
-// flight), then the gathers run SP states at a time.
+// NGX consecutive groups from g0 for SU states: table loads first, then the gathers.
+template <int SU, int SP, int NGX>
+__device__ __forceinline__ void gather_groups(__amdgpu_buffer_rsrc_t r, const uint32_t (&vo)[SU], uint32_t gstride,
+                                              int g0, int k, uint32_t pb, float2 (&acc)[SU]) {
+    uint4 e[SU][NGX];
+#pragma unroll
+    for (int u = 0; u < SU; ++u)
+#pragma unroll
+        for (int h = 0; h < NGX; ++h) e[u][h] = buf_ld4(r, vo[u], (uint32_t)(g0 + h) * gstride);
+#pragma unroll
+    for (int h = 0; h < NGX; ++h) {
+        const int valid = k - 4 * (g0 + h);  // entries of this group that exist (uniform)
+#pragma unroll
+        for (int u0 = 0; u0 < SU; u0 += SP) {
+            if (valid >= 4) gather_group<SU, NGX, SP, 4>(e, h, u0, pb, acc);
+            else if (valid == 3) gather_group<SU, NGX, SP, 3>(e, h, u0, pb, acc);
+            else if (valid == 2) gather_group<SU, NGX, SP, 2>(e, h, u0, pb, acc);
+            else gather_group<SU, NGX, SP, 1>(e, h, u0, pb, acc);
+        }
+    }
+}
+
+// acc[u] = d_k[t0 + u*BLOCK] for u < SU, pulled from layer k-1 at LDS address
+// pb with coefficients U[j][i_k] from the coefficient column.  Lanes past
+// tlim compute the value of state tlim-1 (callers do not store it).
 template <int BLOCK, int SU, int SPR, int NG>
-__device__ __forceinline__ void gather_states(const LayerDev& L, int k, int t0, int tlim,
-                                              const float2* __restrict__ prev, const float2* __restrict__ ucol,
+__device__ __forceinline__ void gather_states(const LayerDev& L, int k, int t0, int tlim, uint32_t pb,
                                               float2 (&acc)[SU]) {
     constexpr int SP = SPR < SU ? SPR : SU;
     static_assert(SU % SP == 0, "states must split evenly into gather sets");
 #pragma unroll
     for (int u = 0; u < SU; ++u) acc[u] = c_zero();
-    if (k == 1) {
+    if (k == 1) {  // d_1[t] = U[t][i_1]
 #pragma unroll
-        for (int u = 0; u < SU; ++u) {
-            const int t = t0 + u * BLOCK;
-            if (t < tlim) acc[u] = ucol[t];
-        }
+        for (int u = 0; u < SU; ++u) acc[u] = lds_ld(kUcolAddr + 8u * (uint32_t)min(t0 + u * BLOCK, tlim - 1));
         return;
     }
-    const size_t N = (size_t)L.N;
-    g_int4* pv = (g_int4*)L.predv;
-    for (int g0 = 0; g0 < L.ngrp; g0 += NG) {
-        int4 e[SU][NG];
+    const uint32_t gstride = (uint32_t)L.N * 16u;
+    const __amdgpu_buffer_rsrc_t r = buf_rsrc(L.predv, (uint32_t)L.ngrp * gstride);
+    uint32_t vo[SU];
+#pragma unroll
+    for (int u = 0; u < SU; ++u) vo[u] = (uint32_t)min(t0 + u * BLOCK, tlim - 1) * 16u;
+    int g0 = 0;
+    if (NG >= 2)
+        for (; g0 + 2 <= L.ngrp; g0 += 2) gather_groups<SU, SP, 2>(r, vo, gstride, g0, k, pb, acc);
+    for (; g0 < L.ngrp; ++g0) gather_groups<SU, SP, 1>(r, vo, gstride, g0, k, pb, acc);
+}
+
+// One layer of the recursion, LDS to LDS, SU states per thread per iteration.
+template <int BLOCK, int SU>
+__device__ __forceinline__ void layer_into_lds(const LayerDev& L, int k, uint32_t prev, uint32_t cur) {
+    const int N = (int)L.N;
+    for (int t0 = threadIdx.x; t0 < N; t0 += BLOCK * SU) {
+        float2 acc[SU];
+        gather_states<BLOCK, SU, kLP, SU >= 4 ? 2 : 1>(L, k, t0, N, prev, acc);
 #pragma unroll
         for (int u = 0; u < SU; ++u) {
             const int t = t0 + u * BLOCK;
-#pragma unroll
-            for (int h = 0; h < NG; ++h) {
-                const int g = g0 + h;
-                e[u][h] = make_int4(kPredEmpty, kPredEmpty, kPredEmpty, kPredEmpty);
-                if (t < tlim && g < L.ngrp) {
-                    g_int* q4 = (g_int*)(pv + (size_t)g * N + t);
-                    e[u][h] = make_int4(q4[0], q4[1], q4[2], q4[3]);
-                }
-            }
-        }
-#pragma unroll
-        for (int h = 0; h < NG; ++h) {
-            const int valid = k - 4 * (g0 + h);  // entries of this group that exist (uniform)
-#pragma unroll
-            for (int u0 = 0; u0 < SU; u0 += SP) {
-                if (valid >= 4) gather_group<SU, NG, SP, 4>(e, h, u0, prev, ucol, acc);
-                else if (valid == 3) gather_group<SU, NG, SP, 3>(e, h, u0, prev, ucol, acc);
-                else if (valid == 2) gather_group<SU, NG, SP, 2>(e, h, u0, prev, ucol, acc);
-                else if (valid == 1) gather_group<SU, NG, SP, 1>(e, h, u0, prev, ucol, acc);
-            }
+            if (t < N) lds_st(cur + 8u * (uint32_t)t, acc[u]);
         }
     }
 }
 
-constexpr int kLU = 4;  // states whose table entries are in flight per thread
-constexpr int kLP = 2;  // states gathered together
-
-// One layer of the recursion into LDS, SU states per thread per iteration.
-template <int BLOCK, int SU = kLU>
-__device__ __forceinline__ void layer_into_lds(const LayerDev& L, int k, const float2* __restrict__ prev,
-                                               float2* __restrict__ cur, const float2* __restrict__ ucol) {
-    const int N = (int)L.N;
-    for (int t0 = threadIdx.x; t0 < N; t0 += BLOCK * SU) {
-        float2 acc[SU];
-        gather_states<BLOCK, SU, kLP, SU >= 4 ? 2 : 1>(L, k, t0, N, prev, ucol, acc);
-#pragma unroll
-        for (int u = 0; u < SU; ++u) {
-            const int t = t0 + u * BLOCK;
-            if (t < N) cur[t] = acc[u];
-        }
-    }
+// Layer record k, read with scalar loads.
+__device__ __forceinline__ LayerDev layer(const LayerDev* Ls, int k) {
+    const LayerDev* p = Ls + k;
+    LayerDev L;
+    L.predv = ldc(&p->predv);
+    L.succ = ldc(&p->succ);
+    L.nrm = ldc(&p->nrm);
+    L.minoff = ldc(&p->minoff);
+    L.N = ldc(&p->N);
+    L.cum = ldc(&p->cum);
+    L.ngrp = ldc(&p->ngrp);
+    L.pred_shift = ldc(&p->pred_shift);
+    return L;
 }
 
 // ------------------------------------------------------------------ forward
@@ -154,16 +192,14 @@ template <int BLOCK, bool PROBS>
 __global__ __launch_bounds__(BLOCK) void fused_fwd_kernel(int m, const LayerDev* __restrict__ Ls, BatchDev Bt,
                                                           const float2* __restrict__ U, void* __restrict__ out,
                                                           int S) {
-    extern __shared__ float2 lds[];
-    float2* ucol = lds;               // [33] column i_k of U; slot 32 stays zero
-    float2* X = lds + kUcolSlots;     // [S] photon layers
+    extern __shared__ float2 lds[];  // ucol at kUcolAddr, photon layers from kXAddr
     const int tid = threadIdx.x;
-    if (tid == 32) ucol[32] = c_zero();
+    if (tid < kUcolSlots) lds_st(kUcolAddr + 8 * tid, c_zero());  // slots m..32 stay zero
     for (int item = blockIdx.x; item < Bt.B; item += gridDim.x) {
-        const int b = ldg(Bt.order + (item));
-        const int n = ldg(Bt.n + (b));
-        const int64_t off = ldg(Bt.off + (b));
-        const float innorm = ldg(Bt.innorm + (b));
+        const int b = ldc(Bt.order + item);
+        const int n = ldc(Bt.n + b);
+        const int64_t off = ldc(Bt.off + b);
+        const float innorm = ldc(Bt.innorm + b);
         const float2* Ub = U + (size_t)b * m * m;
         const int32_t* modes = Bt.modes + (size_t)b * kMaxPhotons;  // read through ldg
         if (n == 0) {
@@ -174,31 +210,40 @@ __global__ __launch_bounds__(BLOCK) void fused_fwd_kernel(int m, const LayerDev*
             continue;
         }
         for (int k = 1; k <= n; ++k) {
-            if (tid < m) ucol[tid] = Ub[tid * m + ldg(modes + (k - 1))];
+            if (tid < m) lds_st(kUcolAddr + 8 * tid, Ub[tid * m + ldc(modes + (k - 1))]);
             __syncthreads();
-            const LayerDev L = Ls[k];
+            const LayerDev L = layer(Ls, k);
             const int N = (int)L.N;
-            // layers alternate between the two ends of X; layer n-1 sits at offset 0
+            // layers alternate between the two ends of the buffer; layer n-1 sits at its start
             if (k < n) {
-                const float2* prev = X + ((((n - k) & 1) == 0) ? 0 : S - (int)Ls[k - 1].N);
-                layer_into_lds<BLOCK>(L, k, prev, X + ((((n - 1 - k) & 1) == 0) ? 0 : S - N), ucol);
+                const int Np = (int)ldc(&Ls[k - 1].N);
+                const uint32_t prev = kXAddr + 8u * (uint32_t)((((n - k) & 1) == 0) ? 0 : S - Np);
+                const uint32_t cur = kXAddr + 8u * (uint32_t)((((n - 1 - k) & 1) == 0) ? 0 : S - N);
+                layer_into_lds<BLOCK, kLU>(L, k, prev, cur);
             } else {
-                const float2* prev = X;
+                const __amdgpu_buffer_rsrc_t rn = buf_rsrc(L.nrm, (uint32_t)N * 4u);
+                const __amdgpu_buffer_rsrc_t ro =
+                    buf_rsrc(PROBS ? (const void*)((float*)out + off) : (const void*)((float2*)out + off),
+                             (uint32_t)N * (PROBS ? 4u : 8u));
                 for (int t0 = tid; t0 < N; t0 += BLOCK * kLU) {
                     float c[kLU];
 #pragma unroll
-                    for (int u = 0; u < kLU; ++u) {
-                        const int t = t0 + u * BLOCK;
-                        c[u] = (t < N) ? ldg(L.nrm + t) * innorm : 0.f;
-                    }
+                    for (int u = 0; u < kLU; ++u)
+                        c[u] = buf_ldf(rn, (uint32_t)min(t0 + u * BLOCK, N - 1) * 4u, 0) * innorm;
                     float2 acc[kLU];
-                    gather_states<BLOCK, kLU, kLP, 2>(L, k, t0, N, prev, ucol, acc);
+                    gather_states<BLOCK, kLU, kLP, 2>(L, k, t0, N, kXAddr, acc);
 #pragma unroll
                     for (int u = 0; u < kLU; ++u) {
                         const int t = t0 + u * BLOCK;
                         if (t < N) {
-                            if (PROBS) ((float*)out)[off + t] = c[u] * c[u] * (acc[u].x * acc[u].x + acc[u].y * acc[u].y);
-                            else ((float2*)out)[off + t] = c_scale(acc[u], c[u]);
+                            if (PROBS) {
+                                const float p = c[u] * c[u] * (acc[u].x * acc[u].x + acc[u].y * acc[u].y);
+                                __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(p), ro, t * 4, 0, 0);
+                            } else {
+                                const float2 a = c_scale(acc[u], c[u]);
+                                __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(
+                                    __attribute__((ext_vector_type(2))) unsigned int, a), ro, t * 8, 0, 0);
+                            }
                         }
                     }
                 }
@@ -210,117 +255,89 @@ __global__ __launch_bounds__(BLOCK) void fused_fwd_kernel(int m, const LayerDev*
 
 // ------------------------------------------------------------------ backward
 
-// Every thread owns states t' = tid + s*BLOCK (s < OWN) of layer k-1:
-// acc[s] accumulates g_{k-1}[t'], and h[j] this lane's share of
-// G_U[j][i_k] = sum_t' conj(d_{k-1}[t']) g_k[t' + e_j].  Lanes without work
-// read the zero slot of the coefficient column instead of branching.
+// Every thread owns states t' = tid + s*BLOCK (s < OWN) of layer k-1: acc[s]
+// accumulates g_{k-1}[t'] and h[j] this lane's share of
+// G_U[j][i_k] = sum_t' conj(d_{k-1}[t']) g_k[t' + e_j].  For owned t' in
+// [lo, hi) and output modes j in [jlo, jhi):
+//   g = g_k[t' + e_j] (LDS, srcb + successor byte offset),
+//   acc[s] += conj(u_j) g,  h[j] += conj(d_{k-1}[t']) g  (d_{k-1} at Db).
+// Successor offsets come in groups of four modes, [j/4][t'][4]: one
+// coalesced 16-byte load serves four pairs.
 
-// t' in [lo, hi), every output mode j in [jlo, m): each owned state loads
-// its successor row (16-byte loads) and issues all its gathers together.
-template <int BLOCK, int OWN, int MMAX, int JC>
-__device__ __forceinline__ void pull_wide(int lo, int hi, int jlo, int m, int MP, const int32_t* __restrict__ succ,
-                                          const float2* __restrict__ src, int base, const float2* __restrict__ D,
-                                          const float2* __restrict__ ucol, float2 (&acc)[OWN], float2 (&h)[MMAX]) {
-    if (lo >= hi) return;
+// u_j is read at its point of use (a broadcast LDS read; volatile so that it
+// is not kept in registers across owned states).
+__device__ __forceinline__ float2 coeff(uint32_t j) {
+    typedef __attribute__((address_space(3))) const volatile unsigned long long lds_vu64;
+    return __builtin_bit_cast(float2, *(lds_vu64*)(size_t)(kUcolAddr + 8 * j));
+}
+
+template <int BLOCK, int OWN, int MMAX>
+__device__ __forceinline__ void pair_math(int j, uint32_t so, uint32_t srcb, float2 dv, float2& acc,
+                                          float2 (&h)[MMAX]) {
+    const float2 g = lds_ld(srcb + so);
+    c_fma_conj(acc, coeff(j), g);
+    c_fma_conj(h[j], dv, g);
+}
+
+// Owned t' in [lo, hi), modes j in [jlo, jhi), by groups of four modes: per
+// owned state, one 16-byte successor load per group that meets the range.
+// No divergent branches around the accumulators (a divergent region that
+// updates long-lived registers costs copies at its join): pairs outside the
+// ranges read the zero slot instead.
+template <int BLOCK, int OWN, int MMAX>
+__device__ __forceinline__ void pull(int lo, int hi, int jlo, int jhi, __amdgpu_buffer_rsrc_t rs, uint32_t gstride,
+                                     uint32_t srcb, uint32_t Db, float2 (&acc)[OWN], float2 (&h)[MMAX]) {
+    constexpr int NG = MMAX / 4;
+    if (lo >= hi || jlo >= jhi) return;
     const int tid = threadIdx.x;
-    const int zidx = (int)(ucol + 32 - src);
-    g_int* sg = (g_int*)succ;
+    const int jbits = (int)range_bits(jlo, jhi);
+    const int gbits = (int)range_bits(jlo >> 2, (jhi + 3) >> 2);
+    const uint32_t zoff = kUcolAddr + 32 * 8 - srcb;  // srcb + zoff: the zero slot
 #pragma unroll
     for (int s = 0; s < OWN; ++s) {
-        if ((s + 1) * BLOCK <= lo || s * BLOCK >= hi) continue;  // no owned state in range (uniform)
-        const int tp = tid + s * BLOCK;
+        if (!slot_meets<BLOCK>(s, lo, hi)) continue;  // no owned state in range (uniform)
+        const int tp = fresh_v(tid) + s * BLOCK;
         const bool act = tp >= lo && tp < hi;
-        const int tr = act ? tp : lo;
-        const float2 dv = D[tr];
+        const int tc = min(max(tp, lo), hi - 1);
+        const float2 dv = lds_ld(Db + 8u * (uint32_t)tc);
+        const uint32_t vo = (uint32_t)tc * 16u;
+        uint4 sv[NG];
 #pragma unroll
-        for (int j0 = 0; j0 < MMAX; j0 += JC) {
-            if (j0 >= MP) continue;  // past the row (uniform; no break, so j0 stays a constant)
-            int sv[JC];
+        for (int g = 0; g < NG; ++g)
+            if (has(gbits, g)) sv[g] = buf_ld4(rs, vo, (uint32_t)g * gstride);
 #pragma unroll
-            for (int q = 0; q < JC; q += 4) {
-                if (j0 + q < MP) {
-                    g_int* r = sg + (size_t)tr * MP + j0 + q;
-                    sv[q] = r[0];
-                    sv[q + 1] = r[1];
-                    sv[q + 2] = r[2];
-                    sv[q + 3] = r[3];
-                } else {
-                    sv[q] = sv[q + 1] = sv[q + 2] = sv[q + 3] = 0;
-                }
+        for (int g = 0; g < NG; ++g) {
+            if (!has(gbits, g)) continue;  // uniform
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int j = 4 * g + q;
+                const uint32_t so = (act && has(jbits, j)) ? comp(sv[g], q) : zoff;
+                pair_math<BLOCK, OWN, MMAX>(j, so, srcb, dv, acc[s], h);
             }
-            float2 gv[JC];
-#pragma unroll
-            for (int q = 0; q < JC; ++q) {
-                const int j = j0 + q;
-                const bool ok = act && j >= jlo && j < m;
-                gv[q] = src[ok ? sv[q] - base : zidx];
-            }
-#pragma unroll
-            for (int q = 0; q < JC; ++q) {
-                const float2 u = ucol[j0 + q];
-                c_fma_conj(acc[s], u, gv[q]);
-                c_fma_conj(h[j0 + q], dv, gv[q]);
-            }
+            __builtin_amdgcn_sched_barrier(0);  // one group at a time: bounded register use
         }
     }
 }
 
-// t' in [lo, hi) (a long range) and output modes j in [jlo, jhi) (a few):
-// per mode, all owned states gather together.
-template <int BLOCK, int OWN, int MMAX>
-__device__ __forceinline__ void pull_narrow(int lo, int hi, int jlo, int jhi, int MP,
-                                            const int32_t* __restrict__ succ, const float2* __restrict__ src,
-                                            int base, const float2* __restrict__ D, const float2* __restrict__ ucol,
-                                            float2 (&acc)[OWN], float2 (&h)[MMAX]) {
-    if (lo >= hi) return;
-    const int tid = threadIdx.x;
-    const int zidx = (int)(ucol + 32 - src);
-    g_int* sg = (g_int*)succ;
-#pragma unroll
-    for (int j = 0; j < MMAX; ++j) {
-        if (j < jlo || j >= jhi) continue;  // uniform
-        const float2 u = ucol[j];
-        int sidx[OWN];
-#pragma unroll
-        for (int s = 0; s < OWN; ++s) {
-            const int tp = tid + s * BLOCK;
-            sidx[s] = zidx;
-            if ((s + 1) * BLOCK > lo && s * BLOCK < hi && tp >= lo && tp < hi)
-                sidx[s] = sg[(size_t)tp * MP + j] - base;
-        }
-#pragma unroll
-        for (int s = 0; s < OWN; ++s) {
-            if ((s + 1) * BLOCK <= lo || s * BLOCK >= hi) continue;  // uniform
-            const int tp = tid + s * BLOCK;
-            const bool act = tp >= lo && tp < hi;
-            const float2 gv = src[sidx[s]];
-            const float2 dv = D[act ? tp : lo];
-            c_fma_conj(acc[s], u, gv);
-            c_fma_conj(h[j], dv, gv);
-        }
-    }
-}
-
-// Sums h[j] over the workgroup (per wave with DPP, then over waves in a fixed
-// order) into GUcol[j] for j < m.  Hw: [NW][32] LDS scratch.
+// Sums h[j] over the workgroup (per wave with DPP, then over the waves in a
+// fixed order) into the LDS column at GUcol, j < MMAX (h[j] = 0 for j >= m).
+// Hw: [NW][32] LDS scratch.
 template <int BLOCK, int MMAX>
-__device__ __forceinline__ void reduce_columns(const float2 (&h)[MMAX], int m, float2* __restrict__ Hw,
-                                               float2* __restrict__ GUcol) {
+__device__ __forceinline__ void reduce_columns(const float2 (&h)[MMAX], int m, uint32_t Hw, uint32_t GUcol) {
     constexpr int NW = BLOCK / 64;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
 #pragma unroll
     for (int j = 0; j < MMAX; ++j) {
-        if (j >= m) continue;
-        const float re = wave_total(h[j].x);
-        const float im = wave_total(h[j].y);
-        if (lane == 0) Hw[wave * 32 + j] = make_float2(re, im);
+        const float re = wave_sum63(h[j].x);
+        const float im = wave_sum63(h[j].y);
+        if (lane == 63) lds_st(Hw + 8u * (uint32_t)(wave * 32 + j), make_float2(re, im));
     }
     __syncthreads();
     if (tid < m) {
         float2 sum = c_zero();
-        for (int w = 0; w < NW; ++w) sum = c_add(sum, Hw[w * 32 + tid]);
-        GUcol[tid] = sum;
+        for (int w = 0; w < NW; ++w) sum = c_add(sum, lds_ld(Hw + 8u * (uint32_t)(w * 32 + tid)));
+        lds_st(GUcol + 8u * (uint32_t)tid, sum);
     }
 }
 
@@ -330,60 +347,62 @@ __global__ __launch_bounds__(BLOCK) void fused_bwd_kernel(int m, const LayerDev*
                                                           const void* __restrict__ gin,
                                                           float2* __restrict__ gU, int S, int PROBS) {
     constexpr int NW = BLOCK / 64;
-    constexpr int JC = 4;
     // states per thread in the gathers (register budget: acc and h stay live)
-    constexpr int GU = OWN >= 10 ? 2 : kLU;
-    constexpr int GM = OWN >= 10 ? 1 : kLU;
-    extern __shared__ float2 lds[];
-    float2* ucol = lds;                // [33] column i_k of U; slot 32 stays zero
-    float2* X = lds + kUcolSlots;      // [S] layers / chunks
-    float2* Hw = X + S;                // [NW][32] per-wave column sums
-    float2* GUacc = Hw + NW * 32;      // [kMaxPhotons][32] gradient column per photon layer
+    constexpr int GU = OWN >= 8 ? 2 : kLU;
+    constexpr int GM = OWN >= 8 ? 1 : 2;
+    extern __shared__ float2 lds[];  // ucol | X[S] layers and chunks | Hw[NW][32] | GUacc[16][32]
+    const uint32_t Hw = kXAddr + 8u * (uint32_t)S;
+    const uint32_t GUacc = Hw + 8u * NW * 32;
     const int tid = threadIdx.x;
-    if (tid == 32) ucol[32] = c_zero();
-    const float* gp = (const float*)gin;
-    const float2* ga = (const float2*)gin;
-    const int MP = succ_row_len(m);
+    if (tid < kUcolSlots) lds_st(kUcolAddr + 8 * tid, c_zero());  // slots m..32 stay zero
 
     for (int item = blockIdx.x; item < Bt.B; item += gridDim.x) {
-        const int b = ldg(Bt.order + item);
-        const int n = ldg(Bt.n + b);
-        const int64_t off = ldg(Bt.off + b);
-        const float innorm = ldg(Bt.innorm + b);
+        const int b = ldc(Bt.order + item);
+        const int n = ldc(Bt.n + b);
+        const int64_t off = ldc(Bt.off + b);
+        const float innorm = ldc(Bt.innorm + b);
         const float2* Ub = U + (size_t)b * m * m;
         const int32_t* modes = Bt.modes + (size_t)b * kMaxPhotons;
         float2* gUb = gU + (size_t)b * m * m;
 
-        for (int q = tid; q < kMaxPhotons * 32; q += BLOCK) GUacc[q] = c_zero();
+        for (int q = tid; q < kMaxPhotons * 32; q += BLOCK) lds_st(GUacc + 8u * q, c_zero());
         __syncthreads();
 
         if (n == 1) {
             // g_1[j] is G_U[j][i_1] itself (d_0 = 1)
             if (tid < m) {
-                const float c = ldg(Ls[1].nrm + tid) * innorm;
-                GUacc[tid] = PROBS ? c_scale(Ub[tid * m + ldg(modes)], 2.f * gp[off + tid] * c * c)
-                                   : c_scale(ga[off + tid], c);
+                const float c = ldg(layer(Ls, 1).nrm + tid) * innorm;
+                const float2 v = PROBS ? c_scale(Ub[tid * m + ldc(modes)], 2.f * ((const float*)gin)[off + tid] * c * c)
+                                       : c_scale(((const float2*)gin)[off + tid], c);
+                lds_st(GUacc + 8u * tid, v);
             }
             __syncthreads();
         } else if (n >= 2) {
-            const LayerDev Ln = Ls[n];
-            const LayerDev Lp = Ls[n - 1];
+            const LayerDev Ln = layer(Ls, n);
+            const LayerDev Lp = layer(Ls, n - 1);
             const int Np = (int)Lp.N;
-            // ---- recompute layers 1..n-1; layer n-1 ends at offset 0
+            // ---- recompute layers 1..n-1; layer n-1 ends at the start of X
             for (int k = 1; k <= n - 1; ++k) {
-                if (tid < m) ucol[tid] = Ub[tid * m + ldg(modes + k - 1)];
+                if (tid < m) lds_st(kUcolAddr + 8 * tid, Ub[tid * m + ldc(modes + k - 1)]);
                 __syncthreads();
-                const int Nk = (int)Ls[k].N;
-                const int Nkm1 = (int)Ls[k - 1].N;
-                layer_into_lds<BLOCK, GU>(Ls[k], k, X + ((((n - k) & 1) == 0) ? 0 : S - Nkm1),
-                                      X + ((((n - 1 - k) & 1) == 0) ? 0 : S - Nk), ucol);
+                const LayerDev Lk = layer(Ls, k);
+                const int Nk = (int)Lk.N;
+                const int Nkm1 = (int)ldc(&Ls[k - 1].N);
+                layer_into_lds<BLOCK, GU>(Lk, k, kXAddr + 8u * (uint32_t)((((n - k) & 1) == 0) ? 0 : S - Nkm1),
+                                          kXAddr + 8u * (uint32_t)((((n - 1 - k) & 1) == 0) ? 0 : S - Nk));
                 __syncthreads();
             }
             // ---- top layer, in chunks of smallest-mode blocks
-            if (tid < m) ucol[tid] = Ub[tid * m + ldg(modes + n - 1)];
-            const float2* D = X;
-            float2* C = X + Np;
+            if (tid < m) lds_st(kUcolAddr + 8 * tid, Ub[tid * m + ldc(modes + n - 1)]);
+            const uint32_t D = kXAddr;                     // d_{n-1}
+            const uint32_t C = kXAddr + 8u * (uint32_t)Np;  // the chunk of g_n
             const int cap = S - Np;
+            const uint32_t gstride = (uint32_t)Np * 16u;  // one group of four successor columns
+            const __amdgpu_buffer_rsrc_t rs = buf_rsrc(Ln.succ, (uint32_t)((m + 3) / 4) * gstride);
+            const __amdgpu_buffer_rsrc_t rn = buf_rsrc(Ln.nrm, (uint32_t)Ln.N * 4u);
+            const __amdgpu_buffer_rsrc_t rg =
+                buf_rsrc(PROBS ? (const void*)((const float*)gin + off) : (const void*)((const float2*)gin + off),
+                         (uint32_t)Ln.N * (PROBS ? 4u : 8u));
             float2 acc[OWN];
             float2 h[MMAX];
 #pragma unroll
@@ -394,48 +413,51 @@ __global__ __launch_bounds__(BLOCK) void fused_bwd_kernel(int m, const LayerDev*
             int a = 0;
             while (a < m) {
                 int bb = a + 1;
-                while (bb < m && ldg(Ln.minoff + bb + 1) - ldg(Ln.minoff + a) <= cap) ++bb;
-                const int base = ldg(Ln.minoff + a);
-                const int end = ldg(Ln.minoff + bb);
+                while (bb < m && ldc(Ln.minoff + bb + 1) - ldc(Ln.minoff + a) <= cap) ++bb;
+                const int base = ldc(Ln.minoff + a);
+                const int end = ldc(Ln.minoff + bb);
                 // g_n on the chunk.  First the per-state factors (a streaming
-                // pass with independent loads): 2 dL/dp_t c_t^2 (probabilities,
-                // kept in .x) or c_t G_a[t] (amplitudes, final).  Then, for
-                // probabilities, d_n[t] from layer n-1; each thread revisits
-                // exactly the states it wrote, so no barrier is needed between.
+                // pass): 2 dL/dp_t c_t^2 (probabilities, kept in .x) or
+                // c_t G_a[t] (amplitudes, final).  Then, for probabilities,
+                // d_n[t] from layer n-1; each thread revisits exactly the
+                // states it wrote, so no barrier is needed in between.
                 for (int t0 = base + tid; t0 < end; t0 += BLOCK * 4) {
                     float cv[4];
                     float2 gv[4];
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const int t = t0 + u * BLOCK;
-                        cv[u] = (t < end) ? ldg(Ln.nrm + t) * innorm : 0.f;
-                        gv[u] = c_zero();
-                        if (t < end) gv[u] = PROBS ? make_float2(gp[off + t], 0.f) : ga[off + t];
+                    for (int q = 0; q < 4; ++q) {
+                        const uint32_t tc = (uint32_t)min(t0 + q * BLOCK, end - 1);
+                        cv[q] = buf_ldf(rn, tc * 4u, 0) * innorm;
+                        if (PROBS) gv[q] = make_float2(buf_ldf(rg, tc * 4u, 0), 0.f);
+                        else gv[q] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rg, (int)(tc * 8u), 0, 0));
                     }
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const int t = t0 + u * BLOCK;
+                    for (int q = 0; q < 4; ++q) {
+                        const int t = t0 + q * BLOCK;
                         if (t < end)
-                            C[t - base] = PROBS ? make_float2(2.f * gv[u].x * cv[u] * cv[u], 0.f) : c_scale(gv[u], cv[u]);
+                            lds_st(C + 8u * (uint32_t)(t - base),
+                                   PROBS ? make_float2(2.f * gv[q].x * cv[q] * cv[q], 0.f) : c_scale(gv[q], cv[q]));
                     }
                 }
                 if (PROBS) {
                     for (int t0 = base + tid; t0 < end; t0 += BLOCK * GM) {
                         float2 d[GM];
-                        gather_states<BLOCK, GM, kLP, GM >= 4 ? 2 : 1>(Ln, n, t0, end, D, ucol, d);
+                        gather_states<BLOCK, GM, kLP, GM >= 4 ? 2 : 1>(Ln, n, t0, end, D, d);
 #pragma unroll
-                        for (int u = 0; u < GM; ++u) {
-                            const int t = t0 + u * BLOCK;
-                            if (t < end) C[t - base] = c_scale(d[u], C[t - base].x);
+                        for (int q = 0; q < GM; ++q) {
+                            const int t = t0 + q * BLOCK;
+                            if (t < end) {
+                                const uint32_t ca = C + 8u * (uint32_t)(t - base);
+                                lds_st(ca, c_scale(d[q], lds_ld(ca).x));
+                            }
                         }
                     }
                 }
                 __syncthreads();
                 // {min(t') in [a, bb), j >= a} and {min(t') >= bb, a <= j < bb}
-                pull_wide<BLOCK, OWN, MMAX, JC>(ldg(Lp.minoff + a), ldg(Lp.minoff + bb), a, m, MP, Ln.succ, C,
-                                                base, D, ucol, acc, h);
-                pull_narrow<BLOCK, OWN, MMAX>(ldg(Lp.minoff + bb), Np, a, bb, MP, Ln.succ, C, base, D, ucol, acc,
-                                              h);
+                const uint32_t srcb = C - 8u * (uint32_t)base;
+                pull<BLOCK, OWN, MMAX>(ldc(Lp.minoff + a), ldc(Lp.minoff + bb), a, m, rs, gstride, srcb, D, acc, h);
+                pull<BLOCK, OWN, MMAX>(ldc(Lp.minoff + bb), Np, a, bb, rs, gstride, srcb, D, acc, h);
                 __syncthreads();
                 a = bb;
             }
@@ -443,40 +465,45 @@ __global__ __launch_bounds__(BLOCK) void fused_bwd_kernel(int m, const LayerDev*
 #pragma unroll
             for (int s = 0; s < OWN; ++s) {
                 const int tp = tid + s * BLOCK;
-                if (tp < Np) X[tp] = acc[s];
+                if (tp < Np) lds_st(kXAddr + 8u * (uint32_t)tp, acc[s]);
             }
-            reduce_columns<BLOCK, MMAX>(h, m, Hw, GUacc + (n - 1) * 32);
+            reduce_columns<BLOCK, MMAX>(h, m, Hw, GUacc + 8u * (uint32_t)((n - 1) * 32));
             // ---- lower layers.  d_0..d_{n-2} stored after g_{n-1} (layer k at
             // Np + number of states with < k photons); g ping-pongs between 0 and R.
-            const int R = Np + (int)Ls[n - 1].cum;
-            if (tid == 0) X[Np] = make_float2(1.f, 0.f);
+            const int R = Np + (int)Lp.cum;
+            if (tid == 0) lds_st(kXAddr + 8u * (uint32_t)Np, make_float2(1.f, 0.f));
             __syncthreads();
             for (int k = 1; k <= n - 2; ++k) {
-                if (tid < m) ucol[tid] = Ub[tid * m + ldg(modes + k - 1)];
+                if (tid < m) lds_st(kUcolAddr + 8 * tid, Ub[tid * m + ldc(modes + k - 1)]);
                 __syncthreads();
-                layer_into_lds<BLOCK, GU>(Ls[k], k, X + Np + (int)Ls[k - 1].cum, X + Np + (int)Ls[k].cum, ucol);
+                const LayerDev Lk = layer(Ls, k);
+                layer_into_lds<BLOCK, GU>(Lk, k, kXAddr + 8u * (uint32_t)(Np + (int)ldc(&Ls[k - 1].cum)),
+                                          kXAddr + 8u * (uint32_t)(Np + (int)Lk.cum));
                 __syncthreads();
             }
             for (int k = n - 1; k >= 1; --k) {
-                if (tid < m) ucol[tid] = Ub[tid * m + ldg(modes + k - 1)];
-                const float2* gk = X + ((((n - 1 - k) & 1) == 0) ? 0 : R);
-                float2* gkm1 = X + ((((n - k) & 1) == 0) ? 0 : R);
-                const float2* dkm1 = X + Np + (int)Ls[k - 1].cum;
-                const int Nkm1 = (int)Ls[k - 1].N;
+                if (tid < m) lds_st(kUcolAddr + 8 * tid, Ub[tid * m + ldc(modes + k - 1)]);
+                const uint32_t gk = kXAddr + 8u * (uint32_t)((((n - 1 - k) & 1) == 0) ? 0 : R);
+                const uint32_t gkm1 = kXAddr + 8u * (uint32_t)((((n - k) & 1) == 0) ? 0 : R);
+                const LayerDev Lkm1 = layer(Ls, k - 1);
+                const uint32_t dkm1 = kXAddr + 8u * (uint32_t)(Np + (int)Lkm1.cum);
+                const int Nkm1 = (int)Lkm1.N;
+                const uint32_t gsk = (uint32_t)Nkm1 * 16u;
+                const __amdgpu_buffer_rsrc_t rsk = buf_rsrc(ldc(&Ls[k].succ), (uint32_t)((m + 3) / 4) * gsk);
 #pragma unroll
                 for (int s = 0; s < OWN; ++s) acc[s] = c_zero();
 #pragma unroll
                 for (int j = 0; j < MMAX; ++j) h[j] = c_zero();
                 __syncthreads();
-                pull_wide<BLOCK, OWN, MMAX, JC>(0, Nkm1, 0, m, MP, Ls[k].succ, gk, 0, dkm1, ucol, acc, h);
+                pull<BLOCK, OWN, MMAX>(0, Nkm1, 0, m, rsk, gsk, gk, dkm1, acc, h);
                 if (k >= 2) {
 #pragma unroll
                     for (int s = 0; s < OWN; ++s) {
                         const int tp = tid + s * BLOCK;
-                        if (tp < Nkm1) gkm1[tp] = acc[s];
+                        if (tp < Nkm1) lds_st(gkm1 + 8u * (uint32_t)tp, acc[s]);
                     }
                 }
-                reduce_columns<BLOCK, MMAX>(h, m, Hw, GUacc + (k - 1) * 32);
+                reduce_columns<BLOCK, MMAX>(h, m, Hw, GUacc + 8u * (uint32_t)((k - 1) * 32));
                 __syncthreads();
             }
         }
@@ -486,7 +513,7 @@ __global__ __launch_bounds__(BLOCK) void fused_bwd_kernel(int m, const LayerDev*
             const int j = q / m, i = q % m;
             float2 v = c_zero();
             for (int k = 1; k <= n; ++k)
-                if (ldg(modes + k - 1) == i) v = c_add(v, GUacc[(k - 1) * 32 + j]);
+                if (ldc(modes + k - 1) == i) v = c_add(v, lds_ld(GUacc + 8u * (uint32_t)((k - 1) * 32 + j)));
             gUb[q] = v;
         }
         __syncthreads();
@@ -520,6 +547,13 @@ int own_for(int block, int64_t Np) {
     return -1;
 }
 
+// every layer's predecessor entries must be compact (LDS byte offsets)
+bool compact_tables(const slos_plan_s& P, int n_max) {
+    for (int k = 1; k <= n_max && k < (int)P.layers.size(); ++k)
+        if (P.layers[k].pred_shift != kPredShiftCompact) return false;
+    return true;
+}
+
 template <int BLOCK, bool PROBS>
 void* fwd_fn() { return (void*)&fused_fwd_kernel<BLOCK, PROBS>; }
 
@@ -532,7 +566,7 @@ void* pick_fwd(int block, bool probs) {
     }
 }
 
-int mmax_for(int m) { const int r = succ_row_len(m); return r <= 8 ? 8 : r <= 12 ? 12 : r <= 16 ? 16 : r <= 20 ? 20 : r <= 24 ? 24 : 32; }
+int mmax_for(int m) { return m <= 8 ? 8 : m <= 12 ? 12 : m <= 16 ? 16 : m <= 20 ? 20 : m <= 24 ? 24 : 32; }
 
 template <int BLOCK, int OWN>
 void* bwd_by_m(int mm) {
@@ -542,7 +576,7 @@ void* bwd_by_m(int mm) {
         case 16: return (void*)&fused_bwd_kernel<BLOCK, OWN, 16>;
         case 20: return (void*)&fused_bwd_kernel<BLOCK, OWN, 20>;
         case 24: return (void*)&fused_bwd_kernel<BLOCK, OWN, 24>;
-        case 32: return (void*)&fused_bwd_kernel<BLOCK, OWN, 32>;
+        case 32: return OWN > 10 ? nullptr : (void*)&fused_bwd_kernel<BLOCK, (OWN > 10 ? 10 : OWN), 32>;
     }
     return nullptr;
 }
@@ -595,12 +629,20 @@ bool fused_fwd_supported(const slos_plan_s& P, int n_max, int block, std::string
         if (why) *why = "photon layers do not fit in LDS";
         return false;
     }
+    if (!compact_tables(P, n_max)) {
+        if (why) *why = "photon layers too large for compact tables";
+        return false;
+    }
     return true;
 }
 
 bool fused_bwd_supported(const slos_plan_s& P, int n_max, int block, std::string* why) {
     if (block != 256 && block != 512) {
         if (why) *why = "block must be 256 or 512";
+        return false;
+    }
+    if (!compact_tables(P, n_max)) {
+        if (why) *why = "photon layers too large for compact tables";
         return false;
     }
     if (P.n_max >= 1 && P.layers.size() > 1 && P.layers[1].succ == nullptr) {

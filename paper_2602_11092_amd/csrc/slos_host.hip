@@ -236,7 +236,8 @@ extern "C" int slos_plan_create(int m, int n_max, int flags, slos_plan_t* out) {
     if (n_max < 1 || n_max > kMaxPhotons) return fail(SLOS_EINVAL, "slos_plan_create: n_max must be in [1, 16]");
     if (flags & ~SLOS_PLAN_FORWARD_ONLY) return fail(SLOS_EINVAL, "slos_plan_create: unknown flags");
     const int64_t Ntop = slos_fock_dim(m, n_max);
-    if (Ntop < 0 || Ntop >= ((int64_t)1 << 31) || slos_fock_dim(m, n_max - 1) >= ((int64_t)1 << (32 - kPredRankShift)))
+    // successor byte offsets (rank * 8) must fit 32 bits, predecessor ranks the wide entry
+    if (Ntop < 0 || Ntop >= ((int64_t)1 << 29) || slos_fock_dim(m, n_max - 1) >= kPredWideStates)
         return fail(SLOS_EUNSUPPORTED, "slos_plan_create: Fock space too large for 32-bit tables");
 
     auto* P = new slos_plan_s();
@@ -258,34 +259,37 @@ extern "C" int slos_plan_create(int m, int n_max, int flags, slos_plan_t* out) {
 
     const bool want_succ = !(flags & SLOS_PLAN_FORWARD_ONLY);
     std::vector<HostLayer> H(n_max + 1);
+    std::vector<int> shifts(n_max + 1, kPredShiftCompact);
     std::vector<Counter> C;
     C.reserve(n_max + 1);
     for (int k = 0; k <= n_max; ++k) C.emplace_back(m, k);
     for (int k = 1; k <= n_max; ++k) {
         build_layer(m, k, C[k], C[k - 1], P->N[k], P->N[k - 1], want_succ, H[k]);
         // device layout: groups of four predecessor entries per state, [group][state][4],
-        // each entry (rank << 11) | (mode << 3), an empty one kPredEmpty
+        // each (mode << shift) | (rank << 3), an empty one pred_empty(shift)
         const int ngrp = (k + 3) / 4;
         const int64_t Nk = P->N[k];
-        std::vector<int32_t> packed((size_t)ngrp * Nk * 4, kPredEmpty);
+        const int shift = P->N[k - 1] <= kPredCompactStates ? kPredShiftCompact : kPredShiftWide;
+        std::vector<int32_t> packed((size_t)ngrp * Nk * 4, (int32_t)pred_empty(shift));
         for (int p = 0; p < k; ++p)
             for (int64_t t = 0; t < Nk; ++t) {
                 const int32_t e = H[k].pred[(size_t)p * Nk + t];
                 if (e >= 0)
                     packed[((size_t)(p / 4) * Nk + t) * 4 + (p % 4)] =
-                        ((e >> kModeBits) << kPredRankShift) | ((e & 31) << 3);
+                        (int32_t)(((uint32_t)(e & 31) << shift) | ((uint32_t)(e >> kModeBits) << 3));
             }
         H[k].pred.swap(packed);
+        shifts[k] = shift;
+        // device successors: groups of four modes, [j/4][t'][4], byte offsets rank * 8
         if (want_succ) {
-            // device layout: one row of successors per (k-1)-photon state, [state][MP],
-            // MP = m rounded up to a multiple of 4 (padding entries repeat j = 0)
-            const int MP = succ_row_len(m);
             const int64_t Nkm1 = P->N[k - 1];
-            std::vector<int32_t> rows((size_t)Nkm1 * MP, 0);
-            for (int64_t t = 0; t < Nkm1; ++t)
-                for (int j = 0; j < MP; ++j)
-                    rows[(size_t)t * MP + j] = H[k].succ[(size_t)(j < m ? j : 0) * Nkm1 + t];
-            H[k].succ.swap(rows);
+            const int sg = (m + 3) / 4;
+            std::vector<int32_t> grouped((size_t)sg * Nkm1 * 4, 0);
+            for (int j = 0; j < m; ++j)
+                for (int64_t t = 0; t < Nkm1; ++t)
+                    grouped[((size_t)(j / 4) * Nkm1 + t) * 4 + (j % 4)] =
+                        (int32_t)((uint32_t)H[k].succ[(size_t)j * Nkm1 + t] << 3);
+            H[k].succ.swap(grouped);
         }
     }
 
@@ -311,9 +315,10 @@ extern "C" int slos_plan_create(int m, int n_max, int flags, slos_plan_t* out) {
         LayerDev& L = P->layers[k];
         L.N = P->N[k];
         L.cum = P->layers[k - 1].cum + P->N[k - 1];
-        L.predv = (const int4*)(base + o_pred[k]);
+        L.predv = (const uint4*)(base + o_pred[k]);
         L.ngrp = (k + 3) / 4;
-        L.succ = want_succ ? (const int32_t*)(base + o_succ[k]) : nullptr;
+        L.pred_shift = shifts[k];
+        L.succ = want_succ ? (const uint32_t*)(base + o_succ[k]) : nullptr;
         L.nrm = (const float*)(base + o_nrm[k]);
         L.minoff = (const int32_t*)(base + o_min[k]);
         e = hipMemcpy(base + o_pred[k], H[k].pred.data(), H[k].pred.size() * 4, hipMemcpyHostToDevice);

@@ -17,32 +17,38 @@ constexpr int kMaxModes = SLOS_MAX_MODES;
 constexpr int kMaxPhotons = SLOS_MAX_PHOTONS;
 constexpr int kModeBits = 5;  // host tables pack (rank << 5) | mode
 static_assert((1 << kModeBits) >= kMaxModes, "mode field too narrow");
-// Device predecessor entries hold two byte offsets: (rank << 11) | (mode << 3),
-// the LDS offset of the predecessor's amplitude (rank * 8 = (e >> 11) << 3)
-// and of the coefficient U[mode][i_k] in a 33-slot column whose slot 32 is
-// zero.  An empty entry points at that zero slot (and at predecessor 0).
-// successor rows are padded to a multiple of four entries (16-byte loads)
-__host__ __device__ constexpr int succ_row_len(int m) { return (m + 3) & ~3; }
-constexpr int kPredRankShift = 11;
-constexpr int kPredModeMask = 0x7FF;
-constexpr int kPredEmpty = 32 << 3;
+// Device predecessor entries (uint32): (mode << shift) | (rank << 3), the
+// rank of t - e_mode in layer k-1 and the output mode.  With shift 25
+// ("compact", layer k-1 below 2^19 states) e >> 22 is the byte offset of the
+// coefficient U[mode][i_k] in a 33-slot column and e & 0x3FFFF8 the byte
+// offset of the predecessor's amplitude, one instruction each; larger layers
+// use shift 26 (ranks below 2^23).  An empty entry (a repeated predecessor,
+// or past the photon number) names mode 32, the column's zero slot, and
+// rank 0.  Successor entries (uint32) are byte offsets, rank * 8.
+constexpr int kPredShiftCompact = 25;
+constexpr int kPredShiftWide = 26;
+constexpr int64_t kPredCompactStates = (int64_t)1 << 19;
+constexpr int64_t kPredWideStates = (int64_t)1 << 23;
+constexpr uint32_t kPredCompactRankMask = 0x3FFFF8u;  // rank * 8 in a compact entry
+constexpr int kPredCompactModeShift = 22;             // e >> 22 = mode * 8 in a compact entry
+__host__ __device__ constexpr uint32_t pred_empty(int shift) { return 32u << shift; }
+__host__ __device__ constexpr uint32_t pred_rank_mask(int shift) { return ((1u << shift) - 1u) & ~7u; }
 constexpr int kUcolSlots = 33;
 
 // One photon layer k of the transition graph (all k-photon states over m
 // modes, in basis order).  Device pointers.
 struct LayerDev {
-    const int4* predv;      // [ngrp][N] int4: entries 4g..4g+3 of t's predecessor list, each
-                            // (rank of t - e_j in layer k-1) << 5 | j for that entry of t's
-                            // sorted mode list, -1 when it repeats the previous entry (same
-                            // predecessor) or lies past k
-    const int32_t* succ;    // [N_{k-1}][MP]: rank in layer k of t' + e_j, one row per t'
-                            // (MP = succ_row_len(m); nullptr if forward-only)
+    const uint4* predv;     // [ngrp][N] groups of four predecessor entries: entries 4g..4g+3
+                            // of t's sorted mode list (empty past k or where a mode repeats)
+    const uint32_t* succ;   // [ceil(m/4)][N_{k-1}][4]: entry j & 3 of group j / 4 is the byte
+                            // offset (rank * 8) in layer k of t' + e_j; padding entries are 0
+                            // (nullptr if forward-only)
     const float* nrm;       // [N]: sqrt(prod_j t_j!)
     const int32_t* minoff;  // [m+1]: first rank whose smallest occupied mode is >= c
     int64_t N;              // number of states C(m+k-1, k)
     int64_t cum;            // number of states with fewer than k photons (sum of N_0..N_{k-1})
     int32_t ngrp;           // ceil(k / 4)
-    int32_t pad;
+    int32_t pred_shift;     // kPredShiftCompact or kPredShiftWide
 };
 
 // Per-sample description of a batch (device pointers).
@@ -137,8 +143,38 @@ __device__ __forceinline__ void c_fma_conj(float2& acc, float2 a, float2 b) {
 __device__ __forceinline__ float2 c_scale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
 __device__ __forceinline__ float2 c_add(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 
+// Wave-uniform read of read-only data (batch descriptors, layer records,
+// offsets) through the constant address space: a scalar load, the value in
+// scalar registers.
+template <class T>
+__device__ __forceinline__ T ldc(const T* p) {
+    return *(__attribute__((address_space(4))) const T*)p;
+}
+
 // Load through a global-address-space view of p.
 template <class T>
 __device__ __forceinline__ T ldg(const T* p) {
     return *(__attribute__((address_space(1))) const T*)p;
+}
+
+// LDS accessed through byte addresses.  The fused kernels declare no static
+// LDS, so their dynamic LDS starts at address 0 and a region's address is a
+// plain integer (which folds into the instruction's offset field).
+typedef __attribute__((address_space(3))) unsigned long long lds_u64;
+__device__ __forceinline__ float2 lds_ld(uint32_t a) { return __builtin_bit_cast(float2, *(const lds_u64*)(size_t)a); }
+__device__ __forceinline__ void lds_st(uint32_t a, float2 v) { *(lds_u64*)(size_t)a = __builtin_bit_cast(unsigned long long, v); }
+
+// Raw buffer access: 32-bit per-lane byte offset plus a wave-uniform offset,
+// no 64-bit address arithmetic.  Every offset used stays inside the buffer.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* p, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc((void*)p, (short)0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ uint4 buf_ld4(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0));
+}
+__device__ __forceinline__ uint32_t buf_ld1(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0);
+}
+__device__ __forceinline__ float buf_ldf(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
 }

@@ -112,15 +112,17 @@ __global__ __launch_bounds__(BLOCK) void layered_layer_kernel(int m, const Layer
             if (k == 1) {
                 acc = us[bl * kUcolSlots + t];
             } else {
+                const int sh = L.pred_shift;
+                const uint32_t rmask = pred_rank_mask(sh);
                 for (int gq = 0; gq < L.ngrp; ++gq) {
-                    const int4 e4 = L.predv[(size_t)gq * N + t];
-                    const int es[4] = {e4.x, e4.y, e4.z, e4.w};
+                    const uint4 e4 = L.predv[(size_t)gq * N + t];
+                    const uint32_t es[4] = {e4.x, e4.y, e4.z, e4.w};
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
                         // empty entries name the zero slot 32 of the coefficient column
-                        const unsigned e = (unsigned)es[q];
-                        c_fma(acc, us[bl * kUcolSlots + ((e & kPredModeMask) >> 3)],
-                              prev[((size_t)g * Nprev + (e >> kPredRankShift)) * SG + bl]);
+                        const uint32_t e = es[q];
+                        c_fma(acc, us[bl * kUcolSlots + (e >> sh)],
+                              prev[((size_t)g * Nprev + ((e & rmask) >> 3)) * SG + bl]);
                     }
                 }
             }
@@ -172,12 +174,12 @@ __global__ __launch_bounds__(BLOCK) void layered_pull_kernel(int m, const LayerD
     if (active) {
         const int Nk = (int)Ls[k].N;
         const int Nkm1 = (int)Ls[k - 1].N;
-        const int32_t* succ = Ls[k].succ;
+        const uint32_t* succ = Ls[k].succ;
         for (int tp = blockIdx.x * TPB + tl; tp < Nkm1; tp += gridDim.x * TPB) {
             const float2 dv = (k >= 2) ? dkm1[((size_t)g * Nkm1 + tp) * SG + bl] : make_float2(1.f, 0.f);
             float2 acc = c_zero();
             for (int j = 0; j < m; ++j) {
-                const int s = succ[(size_t)tp * succ_row_len(m) + j];
+                const uint32_t s = succ[((size_t)(j >> 2) * Nkm1 + tp) * 4 + (j & 3)] >> 3;
                 const float2 gv = gk[((size_t)g * Nk + s) * SG + bl];
                 c_fma_conj(acc, us[bl * kUcolSlots + j], gv);
                 float2 h = Hs[j * BLOCK + tid];
