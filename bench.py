@@ -207,12 +207,13 @@ def main():
     if not args.no_plain:
         plain = plain_path(B, wl, theta, x, gp, plan, N, dev, stream, ms_per_step)
 
-    # ---- copy probe for counter calibration
+    # ---- copy probe for counter calibration: an elementwise kernel of its own
+    # name that reads 1 GiB and writes 1 GiB
     if args.copy_probe:
-        src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
         for _ in range(3):
-            dst.copy_(src)
+            torch.neg(src, out=dst)
         torch.cuda.synchronize()
 
     cpu = None

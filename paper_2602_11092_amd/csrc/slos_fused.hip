@@ -544,6 +544,7 @@ int own_for(int block, int64_t Np) {
     const int64_t need = (Np + block - 1) / block;
     if (block == 256) return need <= 1 ? 1 : need <= 2 ? 2 : need <= 4 ? 4 : -1;
     if (block == 512) return need <= 4 ? 4 : need <= 10 ? 10 : need <= 18 ? 18 : -1;
+    if (block == 768) return need <= 12 ? 12 : -1;
     return -1;
 }
 
@@ -576,7 +577,9 @@ void* bwd_by_m(int mm) {
         case 16: return (void*)&fused_bwd_kernel<BLOCK, OWN, 16>;
         case 20: return (void*)&fused_bwd_kernel<BLOCK, OWN, 20>;
         case 24: return (void*)&fused_bwd_kernel<BLOCK, OWN, 24>;
-        case 32: return OWN > 10 ? nullptr : (void*)&fused_bwd_kernel<BLOCK, (OWN > 10 ? 10 : OWN), 32>;
+        case 32:
+            if constexpr (OWN <= 10) return (void*)&fused_bwd_kernel<BLOCK, OWN, 32>;
+            return nullptr;  // h and acc do not fit the registers
     }
     return nullptr;
 }
@@ -596,6 +599,8 @@ void* pick_bwd(int block, int m, int64_t Np) {
             case 10: return bwd_by_m<512, 10>(mm);
             case 18: return bwd_by_m<512, 18>(mm);
         }
+    } else if (block == 768) {
+        if (own == 12) return bwd_by_m<768, 12>(mm);
     }
     return nullptr;
 }
@@ -637,8 +642,8 @@ bool fused_fwd_supported(const slos_plan_s& P, int n_max, int block, std::string
 }
 
 bool fused_bwd_supported(const slos_plan_s& P, int n_max, int block, std::string* why) {
-    if (block != 256 && block != 512) {
-        if (why) *why = "block must be 256 or 512";
+    if (block != 256 && block != 512 && block != 768) {
+        if (why) *why = "block must be 256, 512 or 768";
         return false;
     }
     if (!compact_tables(P, n_max)) {
@@ -661,7 +666,10 @@ bool fused_bwd_supported(const slos_plan_s& P, int n_max, int block, std::string
 }
 
 int fused_default_block(const slos_plan_s& P, int n_max, bool backward) {
-    if (backward) return (n_max >= 2 && P.N[n_max - 1] > 1024) ? 512 : 256;
+    if (backward) {
+        const int64_t Np = n_max >= 2 ? P.N[n_max - 1] : 1;
+        return Np <= 1024 ? 256 : Np <= 5120 ? 512 : 768;
+    }
     const int64_t Nbig = n_max >= 1 ? P.N[n_max] : 1;
     return Nbig >= 8192 ? 1024 : 256;
 }

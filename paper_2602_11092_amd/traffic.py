@@ -1,0 +1,82 @@
+"""HBM traffic per launch of the library's kernels from two rocprofv3 counter
+runs of the benchmark (one with FETCH_SIZE, one with WRITE_SIZE, both with
+the benchmark's --copy-probe), scaled by what the same counters read for the
+probe's elementwise kernel of known size (1 GiB read, 1 GiB written).
+
+    python -m paper_2602_11092_amd.traffic FETCH_DB WRITE_DB OUT_DIR "<command>"
+
+writes OUT_DIR/traffic_<entry point>.json (read by bench.py while the kernel
+sources are unchanged) and OUT_DIR/traffic_<entry point>.txt.
+"""
+import hashlib
+import json
+import os
+import sqlite3
+import sys
+
+# kernel symbol fragment -> C-ABI entry point that launches it
+KERNELS = {
+    "fused_fwd_kernel": "fock_probs",
+    "fused_bwd_kernel": "fock_probs_backward",
+    "mesh_factors_kernel": "mesh_to_unitary",
+    "mesh_bwd_sweep_kernel": "mesh_to_unitary_backward",
+}
+PROBE = "neg_kernel"
+PROBE_BYTES = float(1 << 30)
+
+
+def per_dispatch_kib(db, counter):
+    """{kernel name: mean counter value per dispatch (KiB)} from a rocpd database."""
+    con = sqlite3.connect(db)
+    out = {}
+    for name, val, n in con.execute(
+            "select kernel_name, sum(value), count(distinct dispatch_id) from counters_collection "
+            "where counter_name = ? group by kernel_name", (counter,)):
+        out[name] = (val / max(n, 1), n)
+    return out
+
+
+def sources_sha256(root):
+    h = hashlib.sha256()
+    csrc = os.path.join(root, "paper_2602_11092_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()
+
+
+def main(fetch_db, write_db, out_dir, command):
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    fetch = per_dispatch_kib(fetch_db, "FETCH_SIZE")
+    write = per_dispatch_kib(write_db, "WRITE_SIZE")
+    probe_f = [v for k, v in fetch.items() if PROBE in k]
+    probe_w = [v for k, v in write.items() if PROBE in k]
+    if not probe_f or not probe_w:
+        raise SystemExit("copy probe kernel not found in the counter runs")
+    kf = PROBE_BYTES / (probe_f[0][0] * 1024.0)
+    kw = PROBE_BYTES / (probe_w[0][0] * 1024.0)
+    sha = sources_sha256(root)
+    for frag, entry in KERNELS.items():
+        fs = [(k, v) for k, v in fetch.items() if frag in k]
+        ws = [(k, v) for k, v in write.items() if frag in k]
+        if not fs or not ws:
+            continue
+        f_kib, nf = fs[0][1]
+        w_kib, nw = ws[0][1]
+        rd = f_kib * 1024.0 * kf
+        wr = w_kib * 1024.0 * kw
+        d = {"kernel": fs[0][0], "entry_point": entry, "fetch_kib_raw": f_kib, "write_kib_raw": w_kib,
+             "fetch_scale": kf, "write_scale": kw, "read_bytes_per_launch": rd, "write_bytes_per_launch": wr,
+             "bytes_per_launch": rd + wr, "dispatches": [nf, nw], "src_sha256": sha, "command": command}
+        with open(os.path.join(out_dir, "traffic_%s.json" % entry), "w") as f:
+            json.dump(d, f, indent=1)
+        with open(os.path.join(out_dir, "traffic_%s.txt" % entry), "w") as f:
+            f.write("HBM traffic of %s (%s), per launch\n" % (entry, fs[0][0][:90]))
+            f.write("command: %s\n" % command)
+            f.write("FETCH_SIZE %.1f KiB raw x %.4f (probe calibration) = %.3f MB read\n" % (f_kib, kf, rd / 1e6))
+            f.write("WRITE_SIZE %.1f KiB raw x %.4f (probe calibration) = %.3f MB written\n" % (w_kib, kw, wr / 1e6))
+            f.write("dispatches averaged: %d (fetch run), %d (write run)\n" % (nf, nw))
+        print(entry, "read %.3f MB write %.3f MB per launch" % (rd / 1e6, wr / 1e6))
+
+
+if __name__ == "__main__":
+    main(*sys.argv[1:5])
