@@ -319,11 +319,53 @@ __device__ __forceinline__ void pull(int lo, int hi, int jlo, int jhi, __amdgpu_
     }
 }
 
+// A few modes j in [jlo, jhi) over owned t' in [lo, hi), one mode at a time
+// (a runtime loop: one successor column per mode, no wasted modes).  The G_U
+// share of mode j is summed over the wave in a fixed order and added by lane
+// 63 to its wave's slot Hn[wave][j] in LDS.
+template <int BLOCK, int OWN>
+__device__ __forceinline__ void pull_few(int lo, int hi, int jlo, int jhi, __amdgpu_buffer_rsrc_t rs,
+                                         uint32_t gstride, uint32_t srcb, uint32_t Db, uint32_t Hn,
+                                         float2 (&acc)[OWN]) {
+    if (lo >= hi || jlo >= jhi) return;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const uint32_t zoff = kUcolAddr + 32 * 8 - srcb;  // srcb + zoff: the zero slot
+    for (int j = jlo; j < jhi; ++j) {
+        const uint32_t col = 4u * (uint32_t)(j & 3), goff = (uint32_t)(j >> 2) * gstride;
+        uint32_t sv[OWN];
+#pragma unroll
+        for (int s = 0; s < OWN; ++s) {
+            if (!slot_meets<BLOCK>(s, lo, hi)) continue;  // uniform
+            const int tc = min(max(fresh_v(tid) + s * BLOCK, lo), hi - 1);
+            sv[s] = buf_ld1(rs, (uint32_t)tc * 16u + col, goff);
+        }
+        const float2 uj = coeff(j);
+        float2 hj = c_zero();
+#pragma unroll
+        for (int s = 0; s < OWN; ++s) {
+            if (!slot_meets<BLOCK>(s, lo, hi)) continue;
+            const int tp = fresh_v(tid) + s * BLOCK;
+            const int tc = min(max(tp, lo), hi - 1);
+            const float2 g = lds_ld(srcb + ((tp >= lo && tp < hi) ? sv[s] : zoff));
+            c_fma_conj(acc[s], uj, g);
+            c_fma_conj(hj, lds_ld(Db + 8u * (uint32_t)tc), g);
+        }
+        const float re = wave_sum63(hj.x);
+        const float im = wave_sum63(hj.y);
+        if (lane == 63) {
+            const uint32_t a = Hn + 8u * (uint32_t)(wave * 32 + j);
+            lds_st(a, c_add(lds_ld(a), make_float2(re, im)));
+        }
+    }
+}
+
 // Sums h[j] over the workgroup (per wave with DPP, then over the waves in a
-// fixed order) into the LDS column at GUcol, j < MMAX (h[j] = 0 for j >= m).
-// Hw: [NW][32] LDS scratch.
+// fixed order) into the LDS column at GUcol, j < MMAX (h[j] = 0 for j >= m),
+// adding the per-wave sums at Hn if given.  Hw: [NW][32] LDS scratch.
 template <int BLOCK, int MMAX>
-__device__ __forceinline__ void reduce_columns(const float2 (&h)[MMAX], int m, uint32_t Hw, uint32_t GUcol) {
+__device__ __forceinline__ void reduce_columns(const float2 (&h)[MMAX], int m, uint32_t Hw, uint32_t GUcol,
+                                               uint32_t Hn = 0xFFFFFFFFu) {
     constexpr int NW = BLOCK / 64;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -331,7 +373,11 @@ __device__ __forceinline__ void reduce_columns(const float2 (&h)[MMAX], int m, u
     for (int j = 0; j < MMAX; ++j) {
         const float re = wave_sum63(h[j].x);
         const float im = wave_sum63(h[j].y);
-        if (lane == 63) lds_st(Hw + 8u * (uint32_t)(wave * 32 + j), make_float2(re, im));
+        if (lane == 63) {
+            float2 v = make_float2(re, im);
+            if (Hn != 0xFFFFFFFFu) v = c_add(v, lds_ld(Hn + 8u * (uint32_t)(wave * 32 + j)));  // per-wave extra
+            lds_st(Hw + 8u * (uint32_t)(wave * 32 + j), v);
+        }
     }
     __syncthreads();
     if (tid < m) {
@@ -348,11 +394,13 @@ __global__ __launch_bounds__(BLOCK) void fused_bwd_kernel(int m, const LayerDev*
                                                           float2* __restrict__ gU, int S, int PROBS) {
     constexpr int NW = BLOCK / 64;
     // states per thread in the gathers (register budget: acc and h stay live)
-    constexpr int GU = OWN >= 8 ? 2 : kLU;
-    constexpr int GM = OWN >= 8 ? 1 : 2;
-    extern __shared__ float2 lds[];  // ucol | X[S] layers and chunks | Hw[NW][32] | GUacc[16][32]
+    // (the layer recomputes run while acc and h are dead: the forward's width)
+    constexpr int GU = kLU;
+    constexpr int GM = 2;
+    extern __shared__ float2 lds[];  // ucol | X[S] layers and chunks | Hw[NW][32] | GUacc[16][32] | Hn[NW][32]
     const uint32_t Hw = kXAddr + 8u * (uint32_t)S;
     const uint32_t GUacc = Hw + 8u * NW * 32;
+    const uint32_t Hn = GUacc + 8u * kMaxPhotons * 32;  // [NW][32] per-wave G_U sums of single-mode pulls
     const int tid = threadIdx.x;
     if (tid < kUcolSlots) lds_st(kUcolAddr + 8 * tid, c_zero());  // slots m..32 stay zero
 
@@ -365,7 +413,7 @@ __global__ __launch_bounds__(BLOCK) void fused_bwd_kernel(int m, const LayerDev*
         const int32_t* modes = Bt.modes + (size_t)b * kMaxPhotons;
         float2* gUb = gU + (size_t)b * m * m;
 
-        for (int q = tid; q < kMaxPhotons * 32; q += BLOCK) lds_st(GUacc + 8u * q, c_zero());
+        for (int q = tid; q < kMaxPhotons * 32 + NW * 32; q += BLOCK) lds_st(GUacc + 8u * q, c_zero());  // GUacc, Hn
         __syncthreads();
 
         if (n == 1) {
@@ -416,40 +464,40 @@ __global__ __launch_bounds__(BLOCK) void fused_bwd_kernel(int m, const LayerDev*
                 while (bb < m && ldc(Ln.minoff + bb + 1) - ldc(Ln.minoff + a) <= cap) ++bb;
                 const int base = ldc(Ln.minoff + a);
                 const int end = ldc(Ln.minoff + bb);
-                // g_n on the chunk.  First the per-state factors (a streaming
-                // pass): 2 dL/dp_t c_t^2 (probabilities, kept in .x) or
-                // c_t G_a[t] (amplitudes, final).  Then, for probabilities,
-                // d_n[t] from layer n-1; each thread revisits exactly the
-                // states it wrote, so no barrier is needed in between.
-                for (int t0 = base + tid; t0 < end; t0 += BLOCK * 4) {
-                    float cv[4];
-                    float2 gv[4];
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const uint32_t tc = (uint32_t)min(t0 + q * BLOCK, end - 1);
-                        cv[q] = buf_ldf(rn, tc * 4u, 0) * innorm;
-                        if (PROBS) gv[q] = make_float2(buf_ldf(rg, tc * 4u, 0), 0.f);
-                        else gv[q] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rg, (int)(tc * 8u), 0, 0));
-                    }
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const int t = t0 + q * BLOCK;
-                        if (t < end)
-                            lds_st(C + 8u * (uint32_t)(t - base),
-                                   PROBS ? make_float2(2.f * gv[q].x * cv[q] * cv[q], 0.f) : c_scale(gv[q], cv[q]));
-                    }
-                }
+                // g_n on the chunk: 2 dL/dp_t c_t^2 d_n[t] (probabilities; the
+                // factor loads issue together with the gather's table loads) or
+                // c_t G_a[t] (amplitudes, a streaming pass).
                 if (PROBS) {
                     for (int t0 = base + tid; t0 < end; t0 += BLOCK * GM) {
+                        float cv[GM], gv[GM];
+#pragma unroll
+                        for (int q = 0; q < GM; ++q) {
+                            const uint32_t tc = (uint32_t)min(t0 + q * BLOCK, end - 1);
+                            cv[q] = buf_ldf(rn, tc * 4u, 0) * innorm;
+                            gv[q] = buf_ldf(rg, tc * 4u, 0);
+                        }
                         float2 d[GM];
-                        gather_states<BLOCK, GM, kLP, GM >= 4 ? 2 : 1>(Ln, n, t0, end, D, d);
+                        gather_states<BLOCK, GM, kLP, 2>(Ln, n, t0, end, D, d);
 #pragma unroll
                         for (int q = 0; q < GM; ++q) {
                             const int t = t0 + q * BLOCK;
-                            if (t < end) {
-                                const uint32_t ca = C + 8u * (uint32_t)(t - base);
-                                lds_st(ca, c_scale(d[q], lds_ld(ca).x));
-                            }
+                            if (t < end) lds_st(C + 8u * (uint32_t)(t - base), c_scale(d[q], 2.f * gv[q] * cv[q] * cv[q]));
+                        }
+                    }
+                } else {
+                    for (int t0 = base + tid; t0 < end; t0 += BLOCK * 4) {
+                        float cv[4];
+                        float2 gv[4];
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const uint32_t tc = (uint32_t)min(t0 + q * BLOCK, end - 1);
+                            cv[q] = buf_ldf(rn, tc * 4u, 0) * innorm;
+                            gv[q] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rg, (int)(tc * 8u), 0, 0));
+                        }
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const int t = t0 + q * BLOCK;
+                            if (t < end) lds_st(C + 8u * (uint32_t)(t - base), c_scale(gv[q], cv[q]));
                         }
                     }
                 }
@@ -457,7 +505,7 @@ __global__ __launch_bounds__(BLOCK) void fused_bwd_kernel(int m, const LayerDev*
                 // {min(t') in [a, bb), j >= a} and {min(t') >= bb, a <= j < bb}
                 const uint32_t srcb = C - 8u * (uint32_t)base;
                 pull<BLOCK, OWN, MMAX>(ldc(Lp.minoff + a), ldc(Lp.minoff + bb), a, m, rs, gstride, srcb, D, acc, h);
-                pull<BLOCK, OWN, MMAX>(ldc(Lp.minoff + bb), Np, a, bb, rs, gstride, srcb, D, acc, h);
+                pull_few<BLOCK, OWN>(ldc(Lp.minoff + bb), Np, a, bb, rs, gstride, srcb, D, Hn, acc);
                 __syncthreads();
                 a = bb;
             }
@@ -467,7 +515,7 @@ __global__ __launch_bounds__(BLOCK) void fused_bwd_kernel(int m, const LayerDev*
                 const int tp = tid + s * BLOCK;
                 if (tp < Np) lds_st(kXAddr + 8u * (uint32_t)tp, acc[s]);
             }
-            reduce_columns<BLOCK, MMAX>(h, m, Hw, GUacc + 8u * (uint32_t)((n - 1) * 32));
+            reduce_columns<BLOCK, MMAX>(h, m, Hw, GUacc + 8u * (uint32_t)((n - 1) * 32), Hn);
             // ---- lower layers.  d_0..d_{n-2} stored after g_{n-1} (layer k at
             // Np + number of states with < k photons); g ping-pongs between 0 and R.
             const int R = Np + (int)Lp.cum;
@@ -571,14 +619,19 @@ int mmax_for(int m) { return m <= 8 ? 8 : m <= 12 ? 12 : m <= 16 ? 16 : m <= 20 
 
 template <int BLOCK, int OWN>
 void* bwd_by_m(int mm) {
+    if constexpr (BLOCK == 768) {
+        if (mm > 20) return nullptr;  // h and acc do not fit the 168 registers of 12 waves
+    }
     switch (mm) {
         case 8: return (void*)&fused_bwd_kernel<BLOCK, OWN, 8>;
         case 12: return (void*)&fused_bwd_kernel<BLOCK, OWN, 12>;
         case 16: return (void*)&fused_bwd_kernel<BLOCK, OWN, 16>;
         case 20: return (void*)&fused_bwd_kernel<BLOCK, OWN, 20>;
-        case 24: return (void*)&fused_bwd_kernel<BLOCK, OWN, 24>;
+        case 24:
+            if constexpr (BLOCK != 768) return (void*)&fused_bwd_kernel<BLOCK, OWN, 24>;
+            return nullptr;
         case 32:
-            if constexpr (OWN <= 10) return (void*)&fused_bwd_kernel<BLOCK, OWN, 32>;
+            if constexpr (OWN <= 10 && BLOCK != 768) return (void*)&fused_bwd_kernel<BLOCK, OWN, 32>;
             return nullptr;  // h and acc do not fit the registers
     }
     return nullptr;
@@ -606,7 +659,7 @@ void* pick_bwd(int block, int m, int64_t Np) {
 }
 
 size_t bwd_lds_for_block(const slos_plan_s& P, int n_max, int block) {
-    return (size_t)(lds_bwd_states(P, n_max) + kUcolSlots + (block / 64) * 32 + kMaxPhotons * 32) * sizeof(float2);
+    return (size_t)(lds_bwd_states(P, n_max) + kUcolSlots + 2 * (block / 64) * 32 + kMaxPhotons * 32) * sizeof(float2);
 }
 
 int grid_for(const slos_plan_s& P, const void* fn, int block, size_t lds, int B) {
@@ -662,13 +715,17 @@ bool fused_bwd_supported(const slos_plan_s& P, int n_max, int block, std::string
         if (why) *why = "layer n-1 too large for the register-resident adjoint at this block size";
         return false;
     }
+    if (n_max >= 2 && pick_bwd(block, P.m, P.N[n_max - 1]) == nullptr) {
+        if (why) *why = "no register-resident adjoint for this block size and mode count";
+        return false;
+    }
     return true;
 }
 
 int fused_default_block(const slos_plan_s& P, int n_max, bool backward) {
     if (backward) {
         const int64_t Np = n_max >= 2 ? P.N[n_max - 1] : 1;
-        return Np <= 1024 ? 256 : Np <= 5120 ? 512 : 768;
+        return Np <= 1024 ? 256 : (Np <= 5120 || P.m > 20) ? 512 : 768;
     }
     const int64_t Nbig = n_max >= 1 ? P.N[n_max] : 1;
     return Nbig >= 8192 ? 1024 : 256;
