@@ -271,12 +271,12 @@ __device__ __forceinline__ float2 coeff(uint32_t j) {
     return __builtin_bit_cast(float2, *(lds_vu64*)(size_t)(kUcolAddr + 8 * j));
 }
 
-template <int BLOCK, int OWN, int MMAX>
+template <int BLOCK, int OWN, int MMAX, bool WITH_H = true>
 __device__ __forceinline__ void pair_math(int j, uint32_t so, uint32_t srcb, float2 dv, float2& acc,
                                           float2 (&h)[MMAX]) {
     const float2 g = lds_ld(srcb + so);
     c_fma_conj(acc, coeff(j), g);
-    c_fma_conj(h[j], dv, g);
+    if (WITH_H) c_fma_conj(h[j], dv, g);
 }
 
 // Owned t' in [lo, hi), modes j in [jlo, jhi), by groups of four modes: per
@@ -284,7 +284,7 @@ __device__ __forceinline__ void pair_math(int j, uint32_t so, uint32_t srcb, flo
 // No divergent branches around the accumulators (a divergent region that
 // updates long-lived registers costs copies at its join): pairs outside the
 // ranges read the zero slot instead.
-template <int BLOCK, int OWN, int MMAX>
+template <int BLOCK, int OWN, int MMAX, bool WITH_H = true>
 __device__ __forceinline__ void pull(int lo, int hi, int jlo, int jhi, __amdgpu_buffer_rsrc_t rs, uint32_t gstride,
                                      uint32_t srcb, uint32_t Db, float2 (&acc)[OWN], float2 (&h)[MMAX]) {
     constexpr int NG = MMAX / 4;
@@ -312,7 +312,7 @@ __device__ __forceinline__ void pull(int lo, int hi, int jlo, int jhi, __amdgpu_
             for (int q = 0; q < 4; ++q) {
                 const int j = 4 * g + q;
                 const uint32_t so = (act && has(jbits, j)) ? comp(sv[g], q) : zoff;
-                pair_math<BLOCK, OWN, MMAX>(j, so, srcb, dv, acc[s], h);
+                pair_math<BLOCK, OWN, MMAX, WITH_H>(j, so, srcb, dv, acc[s], h);
             }
             __builtin_amdgcn_sched_barrier(0);  // one group at a time: bounded register use
         }
@@ -357,6 +357,38 @@ __device__ __forceinline__ void pull_few(int lo, int hi, int jlo, int jhi, __amd
             const uint32_t a = Hn + 8u * (uint32_t)(wave * 32 + j);
             lds_st(a, c_add(lds_ld(a), make_float2(re, im)));
         }
+    }
+}
+
+// G_U[j][i_k] = sum_t' conj(d_{k-1}[t']) g_k[t' + e_j] for a small layer:
+// wave w takes the modes j = w, w + NW, ..., its lanes stride over t', and
+// lane 63 writes the wave's fixed-order sum straight to GUcol[j] (each mode
+// has one wave, so no cross-wave step).
+template <int BLOCK>
+__device__ __forceinline__ void lower_h(int m, int Nkm1, __amdgpu_buffer_rsrc_t rs, uint32_t gstride, uint32_t gk,
+                                        uint32_t Dk, uint32_t GUcol) {
+    constexpr int NW = BLOCK / 64;
+    constexpr int U = 4;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int j = wave; j < m; j += NW) {
+        const uint32_t col = 4u * (uint32_t)(j & 3), goff = (uint32_t)(j >> 2) * gstride;
+        float2 hj = c_zero();
+        for (int t0 = lane; t0 < Nkm1; t0 += 64 * U) {
+            uint32_t sv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                sv[u] = buf_ld1(rs, (uint32_t)min(t0 + 64 * u, Nkm1 - 1) * 16u + col, goff);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int tp = t0 + 64 * u;
+                // past the layer: the zero slot
+                const float2 g = lds_ld(tp < Nkm1 ? gk + sv[u] : kUcolAddr + 32 * 8);
+                c_fma_conj(hj, lds_ld(Dk + 8u * (uint32_t)min(tp, Nkm1 - 1)), g);
+            }
+        }
+        const float re = wave_sum63(hj.x);
+        const float im = wave_sum63(hj.y);
+        if (lane == 63) lds_st(GUcol + 8u * (uint32_t)j, make_float2(re, im));
     }
 }
 
@@ -538,20 +570,18 @@ __global__ __launch_bounds__(BLOCK) void fused_bwd_kernel(int m, const LayerDev*
                 const int Nkm1 = (int)Lkm1.N;
                 const uint32_t gsk = (uint32_t)Nkm1 * 16u;
                 const __amdgpu_buffer_rsrc_t rsk = buf_rsrc(ldc(&Ls[k].succ), (uint32_t)((m + 3) / 4) * gsk);
-#pragma unroll
-                for (int s = 0; s < OWN; ++s) acc[s] = c_zero();
-#pragma unroll
-                for (int j = 0; j < MMAX; ++j) h[j] = c_zero();
                 __syncthreads();
-                pull<BLOCK, OWN, MMAX>(0, Nkm1, 0, m, rsk, gsk, gk, dkm1, acc, h);
                 if (k >= 2) {
+#pragma unroll
+                    for (int s = 0; s < OWN; ++s) acc[s] = c_zero();
+                    pull<BLOCK, OWN, MMAX, false>(0, Nkm1, 0, m, rsk, gsk, gk, dkm1, acc, h);
 #pragma unroll
                     for (int s = 0; s < OWN; ++s) {
                         const int tp = tid + s * BLOCK;
                         if (tp < Nkm1) lds_st(gkm1 + 8u * (uint32_t)tp, acc[s]);
                     }
                 }
-                reduce_columns<BLOCK, MMAX>(h, m, Hw, GUacc + 8u * (uint32_t)((k - 1) * 32));
+                lower_h<BLOCK>(m, Nkm1, rsk, gsk, gk, dkm1, GUacc + 8u * (uint32_t)((k - 1) * 32));
                 __syncthreads();
             }
         }
