@@ -18,6 +18,7 @@ namespace {
 
 struct Mzi {
     float2 t00, t01, t10, t11;
+    float2 eth, etp;  // e^{i theta}, e^{i (theta + phi)} (for dT/dtheta)
 };
 
 // MZI(theta, phi) = BS PS(theta) BS PS(phi), BS = (1/sqrt2)[[1,i],[i,1]],
@@ -37,6 +38,8 @@ __device__ __forceinline__ Mzi mzi(float th, float ph) {
     T.t01 = iep1;
     T.t10 = make_float2(iep1.x * eph.x - iep1.y * eph.y, iep1.x * eph.y + iep1.y * eph.x);
     T.t11 = make_float2(-em1.x, -em1.y);
+    T.eth = make_float2(ct, st);
+    T.etp = make_float2(ct * cp - st * sp, ct * sp + st * cp);
     return T;
 }
 
@@ -45,12 +48,27 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
 }
 __device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
 
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ float dpp(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xF, false));
+}
+// Sum over each half-wave (lanes 0..31, 32..63) in a fixed order; lanes 31
+// and 63 end up holding the two sums.
+__device__ __forceinline__ float sum32(float v) {
+    v += dpp<0xB1>(v);        // quad_perm [1,0,3,2]
+    v += dpp<0x4E>(v);        // quad_perm [2,3,0,1]
+    v += dpp<0x141>(v);       // row_half_mirror
+    v += dpp<0x140>(v);       // row_mirror: every lane holds its row's sum
+    v += dpp<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+    return v;
+}
+
 __host__ __device__ __forceinline__ int col_start(int c, int m) {
     return ((c + 1) / 2) * (m / 2) + (c / 2) * ((m - 1) / 2);
 }
 __host__ __device__ __forceinline__ int num_mzi(int m) { return m * (m - 1) / 2; }
 
-// Workspace layout (float2 units): W[2][m][m] | T[nmzi][4] | G[2][m][m] | partial[B][2][m][m]
+// Workspace layout (float2 units): W[2][m][m] | T[nmzi][6] | G[2][m][m] | partial[B][2][m][m]
 struct MeshWs {
     float2* W;
     Mzi* T;
@@ -58,7 +76,7 @@ struct MeshWs {
     float2* partial;
 };
 __host__ __device__ inline size_t mesh_ws_floats2(int m, int B) {
-    return (size_t)2 * m * m + (size_t)num_mzi(m) * 4 + (size_t)2 * m * m + (size_t)B * 2 * m * m;
+    return (size_t)2 * m * m + (size_t)num_mzi(m) * 6 + (size_t)2 * m * m + (size_t)B * 2 * m * m;
 }
 __host__ __device__ inline MeshWs mesh_ws_split(void* ws, int m) {
     MeshWs w;
@@ -245,23 +263,16 @@ __global__ __launch_bounds__(1024) void mesh_bwd_sweep_kernel(int m, const float
                 g0 = G[half][k][col];
                 g1 = G[half][k + 1][col];
             }
-            // G_T[a][b] = sum_col g_a conj(r_b)
+            // G_T[a][b] = sum_col g_a conj(r_b)  (half-wave sums: lane col 31 holds them)
             float2 p[4] = {cmul(g0, cconj(r0)), cmul(g0, cconj(r1)), cmul(g1, cconj(r0)), cmul(g1, cconj(r1))};
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-#pragma unroll
-                for (int o = 16; o > 0; o >>= 1) {
-                    p[e].x += __shfl_xor(p[e].x, o, 32);
-                    p[e].y += __shfl_xor(p[e].y, o, 32);
-                }
+                p[e].x = sum32(p[e].x);
+                p[e].y = sum32(p[e].y);
             }
-            if (col == 0) {
-                const float th = theta[2 * q], ph = theta[2 * q + 1];
-                float st, ct, sp, cp;
-                sincosf(th, &st, &ct);
-                sincosf(ph, &sp, &cp);
-                const float2 eth = make_float2(ct, st);
-                const float2 etp = cmul(eth, make_float2(cp, sp));
+            if (col == 31) {
+                const float2 eth = T.eth;
+                const float2 etp = T.etp;
                 // dT/dtheta = 1/2 [[ i e^{i(th+ph)}, -e^{i th} ], [ -e^{i(th+ph)}, -i e^{i th} ]]
                 const float2 d00 = make_float2(-0.5f * etp.y, 0.5f * etp.x);
                 const float2 d01 = make_float2(-0.5f * eth.x, -0.5f * eth.y);
