@@ -72,6 +72,7 @@ def main():
 
     import workloads as W
     from paper_2602_11092_amd import _binding as B
+    from paper_2602_11092_amd.autotune import autotune
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -100,11 +101,18 @@ def main():
     gt = torch.empty_like(theta)
     gx = torch.empty_like(x)
     mws = B.mesh_workspace(m, Bn, dev)
+    B.mesh_to_unitary(theta, x, wl.enc_scale, out=U, ws=mws)
+    # kernel variant and workgroup size per op, picked by timing on this batch
+    tuned = autotune(batch, U, ops=(B.OP_PROBS, B.OP_PROBS_BACKWARD), warmup=2, iters=3)
+    names = {B.VARIANT_FUSED: "fused", B.VARIANT_LAYERED: "layered"}
+    tuned_cfg = {op_name: "%s/%d" % (names[tuned[op]["variant"]], tuned[op]["block"])
+                 for op, op_name in ((B.OP_PROBS, "fock_probs"), (B.OP_PROBS_BACKWARD, "fock_probs_backward"))}
+    log("autotune: %s" % json.dumps({k: [(names[v], b, round(t, 1)) for v, b, t in tuned[op]["timings"]]
+                                      for op, k in ((B.OP_PROBS, "fwd"), (B.OP_PROBS_BACKWARD, "bwd"))}))
     fws = batch.workspace(B.OP_PROBS, dev)
     bws = batch.workspace(B.OP_PROBS_BACKWARD, dev)
 
     # dL/dp from the readout + cross-entropy of the workload (once)
-    B.mesh_to_unitary(theta, x, wl.enc_scale, out=U, ws=mws)
     B.fock_probs(batch, U, out=p, ws=fws)
     pv = p.detach().clone().view(Bn, N).requires_grad_(True)
     loss = torch.nn.functional.cross_entropy(pv @ Wr.t() + br, labels)
@@ -235,7 +243,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "m": m, "n": n, "batch": Bn, "fock_dim": N,
                    "pass": "mesh fwd + fock_probs + fock_probs_backward + mesh bwd",
-                   "launch": "eager" if args.eager else "hip_graph"},
+                   "launch": "eager" if args.eager else "hip_graph", "autotuned": tuned_cfg},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "hbm_frac_step": round(hbm_frac_step, 4),

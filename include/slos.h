@@ -149,9 +149,12 @@ SLOS_API int slos_batch_out_offsets(slos_batch_t batch, int64_t* off_host);
 SLOS_API int slos_workspace_bytes(slos_batch_t batch, int op, size_t* bytes);
 
 /* Chooses the kernel variant and workgroup size used for `op` on this batch
- * (the autotuner's hook).  block = 0 keeps the library's choice.  Returns
- * SLOS_EUNSUPPORTED if the variant cannot run this batch (the fused variant
- * needs a sample's photon layers to fit in LDS). */
+ * (the autotuner's hook).  block = 0 keeps the library's choice; otherwise
+ * one of 64, 128, 256, 512, 1024 (layered; fused forward: 256, 512, 1024) or
+ * 256, 512, 768 (fused adjoint).  Returns SLOS_EINVAL for other sizes and
+ * SLOS_EUNSUPPORTED if the variant cannot run this batch at that size (the
+ * fused variant needs a sample's photon layers to fit in LDS and, in the
+ * adjoint, layer n-1 to fit the per-thread registers). */
 SLOS_API int slos_batch_set_config(slos_batch_t batch, int op, int variant, int block);
 
 /* Reads back the configuration in use for `op` (variant, block). */

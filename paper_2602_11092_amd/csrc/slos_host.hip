@@ -482,9 +482,11 @@ extern "C" int slos_batch_set_config(slos_batch_t batch, int op, int variant, in
     if (!op_valid(op)) return fail(SLOS_EINVAL, "slos_batch_set_config: bad op");
     if (variant < SLOS_VARIANT_AUTO || variant > SLOS_VARIANT_LAYERED)
         return fail(SLOS_EINVAL, "slos_batch_set_config: bad variant");
-    if (block != 0 && block != 64 && block != 128 && block != 256 && block != 512 && block != 1024)
-        return fail(SLOS_EINVAL, "slos_batch_set_config: block must be 0, 64, 128, 256, 512 or 1024");
+    if (block != 0 && block != 64 && block != 128 && block != 256 && block != 512 && block != 768 && block != 1024)
+        return fail(SLOS_EINVAL, "slos_batch_set_config: block must be 0, 64, 128, 256, 512, 768 or 1024");
     const bool bwd = op_backward(op);
+    if (block == 768 && variant != SLOS_VARIANT_FUSED)
+        return fail(SLOS_EUNSUPPORTED, "slos_batch_set_config: 768 is a fused-adjoint workgroup size only");
     if (variant == SLOS_VARIANT_FUSED) {
         std::string why;
         const int blk = block ? block : fused_default_block(*batch->plan, batch->n_max, bwd);
