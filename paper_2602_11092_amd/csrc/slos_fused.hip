@@ -108,15 +108,10 @@ __device__ __forceinline__ void gather_group(const uint4 (&e)[SU][NG], int h, in
         for (int v = 0; v < SP; ++v) c_fma(acc[u0 + v], uv[q][v], dv[q][v]);
 }
 
-// NGX consecutive groups from g0 for SU states: table loads first, then the gathers.
+// Gathers for SU states whose table entries (groups g0 .. g0+NGX-1) are loaded.
 template <int SU, int SP, int NGX>
-__device__ __forceinline__ void gather_groups(__amdgpu_buffer_rsrc_t r, const uint32_t (&vo)[SU], uint32_t gstride,
-                                              int g0, int k, uint32_t pb, float2 (&acc)[SU]) {
-    uint4 e[SU][NGX];
-#pragma unroll
-    for (int u = 0; u < SU; ++u)
-#pragma unroll
-        for (int h = 0; h < NGX; ++h) e[u][h] = buf_ld4(r, vo[u], (uint32_t)(g0 + h) * gstride);
+__device__ __forceinline__ void gather_loaded(const uint4 (&e)[SU][NGX], int g0, int k, uint32_t pb,
+                                              float2 (&acc)[SU]) {
 #pragma unroll
     for (int h = 0; h < NGX; ++h) {
         const int valid = k - 4 * (g0 + h);  // entries of this group that exist (uniform)
@@ -128,6 +123,24 @@ __device__ __forceinline__ void gather_groups(__amdgpu_buffer_rsrc_t r, const ui
             else gather_group<SU, NGX, SP, 1>(e, h, u0, pb, acc);
         }
     }
+}
+
+template <int SU, int NGX>
+__device__ __forceinline__ void load_entries(__amdgpu_buffer_rsrc_t r, const uint32_t (&vo)[SU], uint32_t gstride,
+                                             int g0, uint4 (&e)[SU][NGX]) {
+#pragma unroll
+    for (int u = 0; u < SU; ++u)
+#pragma unroll
+        for (int h = 0; h < NGX; ++h) e[u][h] = buf_ld4(r, vo[u], (uint32_t)(g0 + h) * gstride);
+}
+
+// NGX consecutive groups from g0 for SU states: table loads first, then the gathers.
+template <int SU, int SP, int NGX>
+__device__ __forceinline__ void gather_groups(__amdgpu_buffer_rsrc_t r, const uint32_t (&vo)[SU], uint32_t gstride,
+                                              int g0, int k, uint32_t pb, float2 (&acc)[SU]) {
+    uint4 e[SU][NGX];
+    load_entries<SU, NGX>(r, vo, gstride, g0, e);
+    gather_loaded<SU, SP, NGX>(e, g0, k, pb, acc);
 }
 
 // acc[u] = d_k[t0 + u*BLOCK] for u < SU, pulled from layer k-1 at LDS address
@@ -238,11 +251,11 @@ __global__ __launch_bounds__(BLOCK) void fused_fwd_kernel(int m, const LayerDev*
                         if (t < N) {
                             if (PROBS) {
                                 const float p = c[u] * c[u] * (acc[u].x * acc[u].x + acc[u].y * acc[u].y);
-                                __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(p), ro, t * 4, 0, 0);
+                                __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(p), ro, t * 4, 0, kCpolStream);
                             } else {
                                 const float2 a = c_scale(acc[u], c[u]);
                                 __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(
-                                    __attribute__((ext_vector_type(2))) unsigned int, a), ro, t * 8, 0, 0);
+                                    __attribute__((ext_vector_type(2))) unsigned int, a), ro, t * 8, 0, kCpolStream);
                             }
                         }
                     }
@@ -361,34 +374,49 @@ __device__ __forceinline__ void pull_few(int lo, int hi, int jlo, int jhi, __amd
 }
 
 // G_U[j][i_k] = sum_t' conj(d_{k-1}[t']) g_k[t' + e_j] for a small layer:
-// wave w takes the modes j = w, w + NW, ..., its lanes stride over t', and
-// lane 63 writes the wave's fixed-order sum straight to GUcol[j] (each mode
-// has one wave, so no cross-wave step).
-template <int BLOCK>
+// wave w takes the modes j = w + NW r (r < R, all in one loop so that their
+// loads overlap), its lanes stride over t', and lane 63 writes each mode's
+// fixed-order wave sum straight to GUcol[j] (one wave per mode, so no
+// cross-wave step).  Modes past m read the zero slot and are not written.
+template <int BLOCK, int MMAX>
 __device__ __forceinline__ void lower_h(int m, int Nkm1, __amdgpu_buffer_rsrc_t rs, uint32_t gstride, uint32_t gk,
                                         uint32_t Dk, uint32_t GUcol) {
     constexpr int NW = BLOCK / 64;
+    constexpr int R = (MMAX + NW - 1) / NW;
     constexpr int U = 4;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int j = wave; j < m; j += NW) {
-        const uint32_t col = 4u * (uint32_t)(j & 3), goff = (uint32_t)(j >> 2) * gstride;
-        float2 hj = c_zero();
-        for (int t0 = lane; t0 < Nkm1; t0 += 64 * U) {
-            uint32_t sv[U];
+    const uint32_t zero = kUcolAddr + 32 * 8;
+    float2 hj[R];
 #pragma unroll
-            for (int u = 0; u < U; ++u)
-                sv[u] = buf_ld1(rs, (uint32_t)min(t0 + 64 * u, Nkm1 - 1) * 16u + col, goff);
+    for (int r = 0; r < R; ++r) hj[r] = c_zero();
+    for (int t0 = lane; t0 < Nkm1; t0 += 64 * U) {
+        uint32_t sv[R][U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int tp = t0 + 64 * u;
-                // past the layer: the zero slot
-                const float2 g = lds_ld(tp < Nkm1 ? gk + sv[u] : kUcolAddr + 32 * 8);
-                c_fma_conj(hj, lds_ld(Dk + 8u * (uint32_t)min(tp, Nkm1 - 1)), g);
+        for (int r = 0; r < R; ++r) {
+            const int j = min(wave + NW * r, m - 1);
+            const uint32_t col = 4u * (uint32_t)(j & 3), goff = (uint32_t)(j >> 2) * gstride;
+#pragma unroll
+            for (int u = 0; u < U; ++u) sv[r][u] = buf_ld1(rs, (uint32_t)min(t0 + 64 * u, Nkm1 - 1) * 16u + col, goff);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int tp = t0 + 64 * u;
+            const float2 dv = lds_ld(Dk + 8u * (uint32_t)min(tp, Nkm1 - 1));
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                // past the layer or past m: the zero slot
+                const bool ok = tp < Nkm1 && wave + NW * r < m;
+                const float2 g = lds_ld(ok ? gk + sv[r][u] : zero);
+                c_fma_conj(hj[r], dv, g);
             }
         }
-        const float re = wave_sum63(hj.x);
-        const float im = wave_sum63(hj.y);
-        if (lane == 63) lds_st(GUcol + 8u * (uint32_t)j, make_float2(re, im));
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const float re = wave_sum63(hj[r].x);
+        const float im = wave_sum63(hj[r].y);
+        const int j = wave + NW * r;
+        if (lane == 63 && j < m) lds_st(GUcol + 8u * (uint32_t)j, make_float2(re, im));
     }
 }
 
@@ -506,7 +534,7 @@ __global__ __launch_bounds__(BLOCK) void fused_bwd_kernel(int m, const LayerDev*
                         for (int q = 0; q < GM; ++q) {
                             const uint32_t tc = (uint32_t)min(t0 + q * BLOCK, end - 1);
                             cv[q] = buf_ldf(rn, tc * 4u, 0) * innorm;
-                            gv[q] = buf_ldf(rg, tc * 4u, 0);
+                            gv[q] = buf_ldf_stream(rg, tc * 4u);
                         }
                         float2 d[GM];
                         gather_states<BLOCK, GM, kLP, 2>(Ln, n, t0, end, D, d);
@@ -524,7 +552,7 @@ __global__ __launch_bounds__(BLOCK) void fused_bwd_kernel(int m, const LayerDev*
                         for (int q = 0; q < 4; ++q) {
                             const uint32_t tc = (uint32_t)min(t0 + q * BLOCK, end - 1);
                             cv[q] = buf_ldf(rn, tc * 4u, 0) * innorm;
-                            gv[q] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rg, (int)(tc * 8u), 0, 0));
+                            gv[q] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rg, (int)(tc * 8u), 0, kCpolStream));
                         }
 #pragma unroll
                         for (int q = 0; q < 4; ++q) {
@@ -581,7 +609,7 @@ __global__ __launch_bounds__(BLOCK) void fused_bwd_kernel(int m, const LayerDev*
                         if (tp < Nkm1) lds_st(gkm1 + 8u * (uint32_t)tp, acc[s]);
                     }
                 }
-                lower_h<BLOCK>(m, Nkm1, rsk, gsk, gk, dkm1, GUacc + 8u * (uint32_t)((k - 1) * 32));
+                lower_h<BLOCK, MMAX>(m, Nkm1, rsk, gsk, gk, dkm1, GUacc + 8u * (uint32_t)((k - 1) * 32));
                 __syncthreads();
             }
         }

@@ -178,3 +178,10 @@ __device__ __forceinline__ uint32_t buf_ld1(__amdgpu_buffer_rsrc_t r, uint32_t v
 __device__ __forceinline__ float buf_ldf(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
     return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
 }
+// Streaming (non-temporal) access for data touched once per call (per-sample
+// inputs and outputs), so that it does not push the transition tables out of
+// the L2 cache.  Cache-policy bits: 2 = non-temporal.
+constexpr int kCpolStream = 2;
+__device__ __forceinline__ float buf_ldf_stream(__amdgpu_buffer_rsrc_t r, uint32_t voff) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, 0, kCpolStream));
+}
