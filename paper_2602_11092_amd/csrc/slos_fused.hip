@@ -456,7 +456,7 @@ __global__ __launch_bounds__(BLOCK) void fused_bwd_kernel(int m, const LayerDev*
     // states per thread in the gathers (register budget: acc and h stay live)
     // (the layer recomputes run while acc and h are dead: the forward's width)
     constexpr int GU = kLU;
-    constexpr int GM = 2;
+    constexpr int GM = BLOCK <= 512 ? 4 : 2;  // 512 threads leave registers for wider gathers
     extern __shared__ float2 lds[];  // ucol | X[S] layers and chunks | Hw[NW][32] | GUacc[16][32] | Hn[NW][32]
     const uint32_t Hw = kXAddr + 8u * (uint32_t)S;
     const uint32_t GUacc = Hw + 8u * NW * 32;
