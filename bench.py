@@ -315,7 +315,7 @@ def cpu_baseline(wl, U, p, gp, N):
     t0 = time.perf_counter()
     worst = max(worst, one(0))
     t1 = time.perf_counter() - t0
-    S = int(max(1, min(wl.B - 1, 15.0 / max(t1, 1e-3))))
+    S = int(max(1, min(wl.B - 1, 20.0 / max(t1, 1e-3))))  # about 15-20 s of CPU work
     t0 = time.perf_counter()
     for b in range(1, 1 + S):
         worst = max(worst, one(b))
