@@ -354,7 +354,7 @@ __device__ __forceinline__ void pull_few(int lo, int hi, int jlo, int jhi, __amd
             sv[s] = buf_ld1(rs, (uint32_t)tc * 16u + col, goff);
         }
         const float2 uj = coeff(j);
-        float2 hj = c_zero();
+        float2 hq[4] = {c_zero(), c_zero(), c_zero(), c_zero()};  // four partial sums: short chains
 #pragma unroll
         for (int s = 0; s < OWN; ++s) {
             if (!slot_meets<BLOCK>(s, lo, hi)) continue;
@@ -362,8 +362,9 @@ __device__ __forceinline__ void pull_few(int lo, int hi, int jlo, int jhi, __amd
             const int tc = min(max(tp, lo), hi - 1);
             const float2 g = lds_ld(srcb + ((tp >= lo && tp < hi) ? sv[s] : zoff));
             c_fma_conj(acc[s], uj, g);
-            c_fma_conj(hj, lds_ld(Db + 8u * (uint32_t)tc), g);
+            c_fma_conj(hq[s & 3], lds_ld(Db + 8u * (uint32_t)tc), g);
         }
+        const float2 hj = c_add(c_add(hq[0], hq[1]), c_add(hq[2], hq[3]));
         const float re = wave_sum63(hj.x);
         const float im = wave_sum63(hj.y);
         if (lane == 63) {
