@@ -78,9 +78,10 @@ def main():
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
     wl = W.make(args.workload)
+    if wl.theta is None or not wl.backward or not (wl.n == wl.n.max()).all():
+        return bench_other(args, wl, dev)
     m, Bn = wl.m, wl.B
     n = int(wl.n.max())
-    assert (wl.n == n).all() and wl.theta is not None
     N = math.comb(m + n - 1, n)
 
     # ---- inputs resident in HBM
@@ -324,6 +325,73 @@ def cpu_baseline(wl, U, p, gp, N):
             "sample": "%d of %d samples, forward amplitudes + minor-permanent gradient, FP64 Ryser, OpenMP" % (
                 S, wl.B),
             "seconds": round(dt, 2), "max_abs_dp": worst}
+
+
+def bench_other(args, wl, dev):
+    """The other workloads (given unitaries, mixed photon numbers, forward
+    only): one step is mesh forward (if the workload has a mesh) + fock_probs
+    (+ fock_probs_backward with the workload's dL/dp).  A secondary line: the
+    benchmark's metric is quoted on the m=20, n=5 training step."""
+    import numpy as np
+    import torch
+
+    from paper_2602_11092_amd import _binding as B
+    from paper_2602_11092_amd.autotune import autotune
+
+    stream = torch.cuda.current_stream()
+    m, Bn = wl.m, wl.B
+    plan = B.Plan(m, int(wl.n.max()))
+    batch = B.Batch(plan, wl.occ)
+    if wl.U is not None:
+        U = torch.from_numpy(wl.U).to(dev)
+        theta = x = mws = None
+    else:
+        theta = torch.from_numpy(wl.theta).to(dev)
+        x = torch.from_numpy(wl.x).to(dev)
+        U = torch.empty(Bn, m, m, dtype=torch.complex64, device=dev)
+        mws = B.mesh_workspace(m, Bn, dev)
+        B.mesh_to_unitary(theta, x, wl.enc_scale, out=U, ws=mws)
+    ops = (B.OP_PROBS, B.OP_PROBS_BACKWARD) if wl.backward else (B.OP_PROBS,)
+    tuned = autotune(batch, U, ops=ops, warmup=1, iters=2)
+    names = {B.VARIANT_FUSED: "fused", B.VARIANT_LAYERED: "layered"}
+    p = torch.empty(batch.out_len, dtype=torch.float32, device=dev)
+    gU = torch.empty_like(U)
+    fws = batch.workspace(B.OP_PROBS, dev)
+    bws = batch.workspace(B.OP_PROBS_BACKWARD, dev) if wl.backward else None
+    if wl.backward:
+        if wl.loss_w is not None:  # L = sum_b sum_t w_t p_bt: dL/dp = w for every sample
+            gp = torch.from_numpy(np.tile(wl.loss_w, Bn)).to(dev)
+        else:
+            gp = torch.ones(batch.out_len, dtype=torch.float32, device=dev)
+
+    def step():
+        if theta is not None:
+            B.mesh_to_unitary(theta, x, wl.enc_scale, out=U, ws=mws)
+        B.fock_probs(batch, U, out=p, ws=fws)
+        if wl.backward:
+            B.fock_probs_backward(batch, U, gp, out=gU, ws=bws)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(args.steps):
+        step()
+    b.record(stream)
+    b.synchronize()
+    ms = a.elapsed_time(b) / args.steps
+    amps = int(batch.out_len)
+    out = {"metric": "Fock amplitudes/sec, batched %s (%s)" % ("fwd+bwd" if wl.backward else "fwd", wl.name),
+           "value": amps / (ms * 1e-3), "unit": "Fock amplitudes/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "c64", "data": "synthetic",
+           "config": {"workload": wl.name, "m": m, "n": sorted(set(int(v) for v in wl.n)), "batch": Bn,
+                      "outputs_per_step": amps, "launch": "eager",
+                      "autotuned": {str(op): "%s/%d" % (names[t["variant"]], t["block"]) for op, t in tuned.items()}},
+           "roofline": None, "cpu_baseline": None}
+    print(json.dumps(out), flush=True)
 
 
 def load_traffic(kernel):

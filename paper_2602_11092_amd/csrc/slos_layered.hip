@@ -17,17 +17,21 @@
 namespace slos {
 namespace {
 
-constexpr int kGX = 64;  // blocks along the state axis in the pull launches
-
 struct Shape {
     int SG;    // samples per group (lanes sharing a state)
     int NGRP;  // number of groups
+    int GX;    // blocks along the state axis in the pull launches (about 2048 blocks in all)
 };
 
 Shape shape_of(const slos_batch_s& Bt) {
     int sg = 1;
     while (sg < Bt.B && sg < 64) sg <<= 1;
-    return Shape{sg, (Bt.B + sg - 1) / sg};
+    const int ngrp = (Bt.B + sg - 1) / sg;
+    // no more blocks than the largest pull range needs (256 threads each)
+    const int64_t Nmax = Bt.n_max >= 1 ? Bt.plan->N[Bt.n_max - 1] : 1;
+    const int64_t need = (Nmax * sg + 255) / 256;
+    const int cap = std::max(8, std::min(512, 2048 / ngrp));
+    return Shape{sg, ngrp, (int)std::max<int64_t>(1, std::min<int64_t>(need, cap))};
 }
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -36,7 +40,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 struct Layout {
     size_t store_off[kMaxPhotons + 1];  // bwd: layer k at store_off[k] (k = 1..n_max-1)
     size_t buf0, buf1;                  // fwd: ping-pong layers; bwd: g ping-pong
-    size_t partial;                     // bwd: [n_max][NGRP][kGX][SG][32] float2
+    size_t partial;                     // bwd: [n_max][NGRP][GX][SG][32] float2
     size_t total;
 };
 
@@ -61,7 +65,7 @@ Layout layout_of(const slos_batch_s& Bt, bool backward) {
     L.buf1 = off;
     off += align256((size_t)maxN * per_state);
     L.partial = off;
-    if (backward) off += align256((size_t)std::max(Bt.n_max, 1) * sh.NGRP * kGX * sh.SG * 32 * sizeof(float2));
+    if (backward) off += align256((size_t)std::max(Bt.n_max, 1) * sh.NGRP * sh.GX * sh.SG * 32 * sizeof(float2));
     L.total = off;
     return L;
 }
@@ -144,15 +148,20 @@ __global__ __launch_bounds__(BLOCK) void layered_layer_kernel(int m, const Layer
 }
 
 // g_{k-1}[t'] = sum_j conj(u_j) g_k[t'+e_j]; partial sums of
-// G_U[j][i_k] = sum_t' conj(d_{k-1}[t']) g_k[t'+e_j] per block.
-template <int BLOCK>
+// G_U[j][i_k] = sum_t' conj(d_{k-1}[t']) g_k[t'+e_j] per block.  Each lane
+// keeps its G_U partials for MMAX modes in registers (modes past m read
+// padding successors and zero coefficients and are never written out),
+// loads the successors of four modes at once, and the block adds the lanes
+// of each sample in a fixed order through an LDS window of 8 modes.
+template <int BLOCK, int MMAX>
 __global__ __launch_bounds__(BLOCK) void layered_pull_kernel(int m, const LayerDev* __restrict__ Ls, BatchDev Bt,
                                                              const float2* __restrict__ U, int k,
                                                              const float2* __restrict__ gk, float2* __restrict__ gkm1,
                                                              const float2* __restrict__ dkm1,
                                                              float2* __restrict__ partial, int SG, int NGRP) {
+    constexpr int WIN = 8;
     __shared__ float2 us[64 * kUcolSlots];
-    __shared__ float2 Hs[32 * BLOCK];
+    __shared__ float2 Hs[WIN * BLOCK];
     const int tid = threadIdx.x;
     const int bl = tid % SG;
     const int tl = tid / SG;
@@ -161,6 +170,8 @@ __global__ __launch_bounds__(BLOCK) void layered_pull_kernel(int m, const LayerD
     const int b = g * SG + bl;
     const int n_b = (b < Bt.B) ? Bt.n[b] : -1;
     const bool active = n_b >= k;
+    for (int q = tid; q < SG * kUcolSlots; q += BLOCK) us[q] = c_zero();
+    __syncthreads();
     for (int q = tid; q < SG * m; q += BLOCK) {
         const int bq = q % SG, j = q / SG;
         const int bb = g * SG + bq;
@@ -169,33 +180,52 @@ __global__ __launch_bounds__(BLOCK) void layered_pull_kernel(int m, const LayerD
             us[bq * kUcolSlots + j] = U[((size_t)bb * m + j) * m + ik];
         }
     }
-    for (int j = 0; j < 32; ++j) Hs[j * BLOCK + tid] = c_zero();
     __syncthreads();
+    float2 h[MMAX];
+#pragma unroll
+    for (int j = 0; j < MMAX; ++j) h[j] = c_zero();
     if (active) {
         const int Nk = (int)Ls[k].N;
         const int Nkm1 = (int)Ls[k - 1].N;
-        const uint32_t* succ = Ls[k].succ;
+        const uint4* succ4 = (const uint4*)Ls[k].succ;
+        const int ngs = (m + 3) >> 2;  // successor groups in the table
+        const float2* gkg = gk + (size_t)g * Nk * SG + bl;
         for (int tp = blockIdx.x * TPB + tl; tp < Nkm1; tp += gridDim.x * TPB) {
             const float2 dv = (k >= 2) ? dkm1[((size_t)g * Nkm1 + tp) * SG + bl] : make_float2(1.f, 0.f);
             float2 acc = c_zero();
-            for (int j = 0; j < m; ++j) {
-                const uint32_t s = succ[((size_t)(j >> 2) * Nkm1 + tp) * 4 + (j & 3)] >> 3;
-                const float2 gv = gk[((size_t)g * Nk + s) * SG + bl];
-                c_fma_conj(acc, us[bl * kUcolSlots + j], gv);
-                float2 h = Hs[j * BLOCK + tid];
-                c_fma_conj(h, dv, gv);
-                Hs[j * BLOCK + tid] = h;
+#pragma unroll
+            for (int q4 = 0; q4 < MMAX / 4; ++q4) {
+                if (q4 >= ngs) continue;  // uniform
+                const uint4 s4 = succ4[(size_t)q4 * Nkm1 + tp];
+                const uint32_t sv[4] = {s4.x, s4.y, s4.z, s4.w};
+                float2 gv[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) gv[q] = gkg[(size_t)(sv[q] >> 3) * SG];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    c_fma_conj(acc, us[bl * kUcolSlots + 4 * q4 + q], gv[q]);
+                    c_fma_conj(h[4 * q4 + q], dv, gv[q]);
+                }
             }
             if (k >= 2) gkm1[((size_t)g * Nkm1 + tp) * SG + bl] = acc;
         }
     }
-    __syncthreads();
-    // fixed-order sum over the lanes that share a sample
-    for (int q = tid; q < SG * 32; q += BLOCK) {
-        const int bq = q % SG, j = q / SG;
-        float2 sum = c_zero();
-        for (int tq = 0; tq < TPB; ++tq) sum = c_add(sum, Hs[j * BLOCK + tq * SG + bq]);
-        partial[((((size_t)(k - 1) * NGRP + g) * gridDim.x + blockIdx.x) * SG + bq) * 32 + j] = sum;
+    // fixed-order sum over the lanes that share a sample, WIN modes at a time
+#pragma unroll
+    for (int j0 = 0; j0 < MMAX; j0 += WIN) {
+        __syncthreads();
+#pragma unroll
+        for (int w = 0; w < WIN; ++w)
+            if (j0 + w < MMAX) Hs[w * BLOCK + tid] = h[j0 + w];
+        __syncthreads();
+        for (int q = tid; q < SG * WIN; q += BLOCK) {
+            const int bq = q % SG, w = q / SG;
+            const int j = j0 + w;
+            if (j >= 32) continue;
+            float2 sum = c_zero();
+            for (int tq = 0; tq < TPB; ++tq) sum = c_add(sum, Hs[w * BLOCK + tq * SG + bq]);
+            partial[((((size_t)(k - 1) * NGRP + g) * gridDim.x + blockIdx.x) * SG + bq) * 32 + j] = sum;
+        }
     }
 }
 
@@ -292,6 +322,15 @@ int launch_layered_fwd(const slos_batch_s& Bt, int block, const float2* U, void*
     return SLOS_OK;
 }
 
+static void* pull_fn(int m) {
+    if (m <= 8) return (void*)&layered_pull_kernel<256, 8>;
+    if (m <= 12) return (void*)&layered_pull_kernel<256, 12>;
+    if (m <= 16) return (void*)&layered_pull_kernel<256, 16>;
+    if (m <= 20) return (void*)&layered_pull_kernel<256, 20>;
+    if (m <= 24) return (void*)&layered_pull_kernel<256, 24>;
+    return (void*)&layered_pull_kernel<256, 32>;
+}
+
 int launch_layered_bwd(const slos_batch_s& Bt, int block, const float2* U, const void* gin, bool probs, float2* gU,
                        void* ws, hipStream_t stream) {
     const slos_plan_s& P = *Bt.plan;
@@ -317,10 +356,10 @@ int launch_layered_bwd(const slos_batch_s& Bt, int block, const float2* U, const
         const float2* dkm1 = store(k - 1);
         void* args[] = {(void*)&m, (void*)&Ls, (void*)&Bt.dev, (void*)&U, (void*)&k, (void*)&gk,
                         (void*)&gkm1, (void*)&dkm1, (void*)&partial, (void*)&SG, (void*)&NGRP};
-        hipError_t e = hipLaunchKernel((void*)&layered_pull_kernel<256>, dim3(kGX, NGRP), dim3(256), args, 0, stream);
+        hipError_t e = hipLaunchKernel(pull_fn(m), dim3(sh.GX, NGRP), dim3(256), args, 0, stream);
         if (e != hipSuccess) return fail(SLOS_EHIP, std::string("layered pull launch: ") + hipGetErrorString(e));
     }
-    int GX = kGX;
+    int GX = sh.GX;
     void* args[] = {(void*)&m, (void*)&Bt.dev, (void*)&partial, (void*)&gU, (void*)&SG, (void*)&NGRP, (void*)&GX};
     hipError_t e = hipLaunchKernel((void*)&layered_final_kernel, dim3(Bt.B), dim3(256), args, 0, stream);
     if (e != hipSuccess) return fail(SLOS_EHIP, std::string("layered final launch: ") + hipGetErrorString(e));
