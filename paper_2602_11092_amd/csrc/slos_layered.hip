@@ -230,20 +230,35 @@ __global__ __launch_bounds__(BLOCK) void layered_pull_kernel(int m, const LayerD
 }
 
 // G_U[b][j][i] = sum over photon layers k with i_k = i of the partial sums.
-__global__ void layered_final_kernel(int m, BatchDev Bt, const float2* __restrict__ partial, float2* __restrict__ gU,
-                                     int SG, int NGRP, int GX) {
+// One block per sample: for each layer, the 256 threads add the GX block
+// partials of each mode in 8 interleaved slices (coalesced over the modes),
+// then the slices are combined in a fixed order.
+__global__ __launch_bounds__(256) void layered_final_kernel(int m, BatchDev Bt, const float2* __restrict__ partial,
+                                                            float2* __restrict__ gU, int SG, int NGRP, int GX) {
+    __shared__ float2 part[8][32];
+    __shared__ float2 col[kMaxPhotons][32];
     const int b = blockIdx.x;
     const int g = b / SG, bl = b % SG;
     const int n_b = Bt.n[b];
     const int32_t* modes = Bt.modes + (size_t)b * kMaxPhotons;
-    for (int q = threadIdx.x; q < m * m; q += blockDim.x) {
-        const int j = q / m, i = q % m;
+    const int tid = threadIdx.x, j = tid & 31, sl = tid >> 5;
+    for (int k = 1; k <= n_b; ++k) {
         float2 v = c_zero();
-        for (int k = 1; k <= n_b; ++k) {
-            if (modes[k - 1] != i) continue;
-            for (int x = 0; x < GX; ++x)
-                v = c_add(v, partial[((((size_t)(k - 1) * NGRP + g) * GX + x) * SG + bl) * 32 + j]);
+        for (int x = sl; x < GX; x += 8) v = c_add(v, partial[((((size_t)(k - 1) * NGRP + g) * GX + x) * SG + bl) * 32 + j]);
+        part[sl][j] = v;
+        __syncthreads();
+        if (tid < 32) {
+            float2 sum = c_zero();
+            for (int q = 0; q < 8; ++q) sum = c_add(sum, part[q][tid]);
+            col[k - 1][tid] = sum;
         }
+        __syncthreads();
+    }
+    for (int q = tid; q < m * m; q += blockDim.x) {
+        const int jj = q / m, i = q % m;
+        float2 v = c_zero();
+        for (int k = 1; k <= n_b; ++k)
+            if (modes[k - 1] == i) v = c_add(v, col[k - 1][jj]);
         gU[(size_t)b * m * m + q] = v;
     }
 }
