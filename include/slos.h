@@ -151,7 +151,7 @@ SLOS_API int slos_workspace_bytes(slos_batch_t batch, int op, size_t* bytes);
 /* Chooses the kernel variant and workgroup size used for `op` on this batch
  * (the autotuner's hook).  block = 0 keeps the library's choice; otherwise
  * one of 64, 128, 256, 512, 1024 (layered; fused forward: 256, 512, 1024) or
- * 256, 512, 768 (fused adjoint).  Returns SLOS_EINVAL for other sizes and
+ * 256, 512, 768, 1024 (fused adjoint).  Returns SLOS_EINVAL for other sizes and
  * SLOS_EUNSUPPORTED if the variant cannot run this batch at that size (the
  * fused variant needs a sample's photon layers to fit in LDS and, in the
  * adjoint, layer n-1 to fit the per-thread registers). */

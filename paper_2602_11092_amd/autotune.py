@@ -23,7 +23,7 @@ from . import _binding as B
 # (variant, workgroup size) candidates per direction
 FORWARD_CANDIDATES = [(B.VARIANT_FUSED, 256), (B.VARIANT_FUSED, 512), (B.VARIANT_FUSED, 1024),
                       (B.VARIANT_LAYERED, 128), (B.VARIANT_LAYERED, 256), (B.VARIANT_LAYERED, 512)]
-BACKWARD_CANDIDATES = [(B.VARIANT_FUSED, 256), (B.VARIANT_FUSED, 512), (B.VARIANT_FUSED, 768),
+BACKWARD_CANDIDATES = [(B.VARIANT_FUSED, 256), (B.VARIANT_FUSED, 512), (B.VARIANT_FUSED, 768), (B.VARIANT_FUSED, 1024),
                        (B.VARIANT_LAYERED, 128), (B.VARIANT_LAYERED, 256), (B.VARIANT_LAYERED, 512)]
 _BACKWARD = (B.OP_AMPLITUDES_BACKWARD, B.OP_PROBS_BACKWARD)
 

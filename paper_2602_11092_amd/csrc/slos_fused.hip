@@ -314,13 +314,17 @@ __device__ __forceinline__ void pull(int lo, int hi, int jlo, int jhi, __amdgpu_
         const int tc = min(max(tp, lo), hi - 1);
         const float2 dv = lds_ld(Db + 8u * (uint32_t)tc);
         const uint32_t vo = (uint32_t)tc * 16u;
+        // all groups' loads up front, or (the 1024-thread shape, short of
+        // registers) each group's load just before its use
+        constexpr bool kPreload = BLOCK < 1024;
         uint4 sv[NG];
 #pragma unroll
         for (int g = 0; g < NG; ++g)
-            if (has(gbits, g)) sv[g] = buf_ld4(rs, vo, (uint32_t)g * gstride);
+            if (kPreload && has(gbits, g)) sv[g] = buf_ld4(rs, vo, (uint32_t)g * gstride);
 #pragma unroll
         for (int g = 0; g < NG; ++g) {
             if (!has(gbits, g)) continue;  // uniform
+            if (!kPreload) sv[g] = buf_ld4(rs, vo, (uint32_t)g * gstride);
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int j = 4 * g + q;
@@ -354,7 +358,8 @@ __device__ __forceinline__ void pull_few(int lo, int hi, int jlo, int jhi, __amd
             sv[s] = buf_ld1(rs, (uint32_t)tc * 16u + col, goff);
         }
         const float2 uj = coeff(j);
-        float2 hq[4] = {c_zero(), c_zero(), c_zero(), c_zero()};  // four partial sums: short chains
+        constexpr int HQ = BLOCK >= 1024 ? 1 : 4;  // partial sums (short chains) where registers allow
+        float2 hq[4] = {c_zero(), c_zero(), c_zero(), c_zero()};
 #pragma unroll
         for (int s = 0; s < OWN; ++s) {
             if (!slot_meets<BLOCK>(s, lo, hi)) continue;
@@ -362,7 +367,7 @@ __device__ __forceinline__ void pull_few(int lo, int hi, int jlo, int jhi, __amd
             const int tc = min(max(tp, lo), hi - 1);
             const float2 g = lds_ld(srcb + ((tp >= lo && tp < hi) ? sv[s] : zoff));
             c_fma_conj(acc[s], uj, g);
-            c_fma_conj(hq[s & 3], lds_ld(Db + 8u * (uint32_t)tc), g);
+            c_fma_conj(hq[s % HQ], lds_ld(Db + 8u * (uint32_t)tc), g);
         }
         const float2 hj = c_add(c_add(hq[0], hq[1]), c_add(hq[2], hq[3]));
         const float re = wave_sum63(hj.x);
@@ -457,7 +462,7 @@ __global__ __launch_bounds__(BLOCK) void fused_bwd_kernel(int m, const LayerDev*
     // states per thread in the gathers (register budget: acc and h stay live)
     // (the layer recomputes run while acc and h are dead: the forward's width)
     constexpr int GU = kLU;
-    constexpr int GM = BLOCK <= 512 ? 4 : 2;  // 512 threads leave registers for wider gathers
+    constexpr int GM = BLOCK <= 512 ? 4 : BLOCK <= 768 ? 2 : 1;  // wider gathers where registers allow
     extern __shared__ float2 lds[];  // ucol | X[S] layers and chunks | Hw[NW][32] | GUacc[16][32] | Hn[NW][32]
     const uint32_t Hw = kXAddr + 8u * (uint32_t)S;
     const uint32_t GUacc = Hw + 8u * NW * 32;
@@ -652,6 +657,7 @@ int own_for(int block, int64_t Np) {
     if (block == 256) return need <= 1 ? 1 : need <= 2 ? 2 : need <= 4 ? 4 : -1;
     if (block == 512) return need <= 4 ? 4 : need <= 10 ? 10 : need <= 18 ? 18 : -1;
     if (block == 768) return need <= 12 ? 12 : -1;
+    if (block == 1024) return need <= 10 ? 10 : -1;
     return -1;
 }
 
@@ -678,8 +684,8 @@ int mmax_for(int m) { return m <= 8 ? 8 : m <= 12 ? 12 : m <= 16 ? 16 : m <= 20 
 
 template <int BLOCK, int OWN>
 void* bwd_by_m(int mm) {
-    if constexpr (BLOCK == 768) {
-        if (mm > 20) return nullptr;  // h and acc do not fit the 168 registers of 12 waves
+    if constexpr (BLOCK >= 768) {
+        if (mm > 20) return nullptr;  // h and acc do not fit the registers of 12 or 16 waves
     }
     switch (mm) {
         case 8: return (void*)&fused_bwd_kernel<BLOCK, OWN, 8>;
@@ -687,10 +693,10 @@ void* bwd_by_m(int mm) {
         case 16: return (void*)&fused_bwd_kernel<BLOCK, OWN, 16>;
         case 20: return (void*)&fused_bwd_kernel<BLOCK, OWN, 20>;
         case 24:
-            if constexpr (BLOCK != 768) return (void*)&fused_bwd_kernel<BLOCK, OWN, 24>;
+            if constexpr (BLOCK < 768) return (void*)&fused_bwd_kernel<BLOCK, OWN, 24>;
             return nullptr;
         case 32:
-            if constexpr (OWN <= 10 && BLOCK != 768) return (void*)&fused_bwd_kernel<BLOCK, OWN, 32>;
+            if constexpr (OWN <= 10 && BLOCK < 768) return (void*)&fused_bwd_kernel<BLOCK, OWN, 32>;
             return nullptr;  // h and acc do not fit the registers
     }
     return nullptr;
@@ -713,6 +719,8 @@ void* pick_bwd(int block, int m, int64_t Np) {
         }
     } else if (block == 768) {
         if (own == 12) return bwd_by_m<768, 12>(mm);
+    } else if (block == 1024) {
+        if (own == 10) return bwd_by_m<1024, 10>(mm);
     }
     return nullptr;
 }
@@ -754,8 +762,8 @@ bool fused_fwd_supported(const slos_plan_s& P, int n_max, int block, std::string
 }
 
 bool fused_bwd_supported(const slos_plan_s& P, int n_max, int block, std::string* why) {
-    if (block != 256 && block != 512 && block != 768) {
-        if (why) *why = "block must be 256, 512 or 768";
+    if (block != 256 && block != 512 && block != 768 && block != 1024) {
+        if (why) *why = "block must be 256, 512, 768 or 1024";
         return false;
     }
     if (!compact_tables(P, n_max)) {
