@@ -197,3 +197,30 @@ def test_backward_deterministic_and_variants_agree():
     batch.set_config(B.OP_PROBS_BACKWARD, B.VARIANT_LAYERED)
     g3 = _grad(batch, U, gp, True)
     assert rel_err(g3, g1) < 1e-5
+
+
+@pytest.mark.parametrize("block", [256, 512, 768, 1024])
+def test_fused_adjoint_every_workgroup_size(block):
+    """Every fused adjoint shape the autotuner may pick (256/512/768/1024
+    threads, with their own per-thread state counts) against the oracle."""
+    rng = np.random.default_rng(4242 + block)
+    m, n, Bn = 12, 4, 6
+    U = W.haar_unitaries(rng, Bn, m).astype(np.complex64)
+    occ = np.zeros((Bn, m), dtype=np.int32)
+    for b in range(Bn):
+        for i in rng.choice(m, size=n, replace=True):
+            occ[b, i] += 1
+    say("fused adjoint block", block)
+    plan = B.Plan(m, n)
+    batch = B.Batch(plan, occ)
+    batch.set_config(B.OP_PROBS_BACKWARD, B.VARIANT_FUSED, block)
+    assert batch.get_config(B.OP_PROBS_BACKWARD) == (B.VARIANT_FUSED, block)
+    Ud = to_dev_c64(U)
+    gp = rng.random(batch.out_len).astype(np.float32)
+    G = B.fock_probs_backward(batch, Ud, torch.from_numpy(gp).to(DEV))
+    torch.cuda.synchronize()
+    G = G.cpu().numpy()
+    for b in range(Bn):
+        sl = slice(batch.offsets[b], batch.offsets[b + 1])
+        ref = O.probs_grad(widen(U[b]), occ[b], gp[sl].astype(np.float64))
+        assert rel_err(G[b], ref) <= G_RTOL, (block, b, rel_err(G[b], ref))
