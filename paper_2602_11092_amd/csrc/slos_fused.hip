@@ -23,12 +23,15 @@
 //   G_U[j][i_k] += sum_t' conj(d_{k-1}[t']) g_k[t' + e_j]
 // Layers are recomputed rather than stored.  Every thread owns fixed states
 // t' of layer k-1 (register accumulators for g_{k-1}); for each output mode j
-// it gathers g_k[t' + e_j] and the workgroup sums the G_U contributions per
-// wave (DPP) into LDS.  The top layer is consumed in chunks of consecutive
-// "smallest occupied mode" blocks: for a chunk of smallest modes [a, b) the
-// pairs (t', j) whose successor falls in it are exactly
-// {min(t') in [a,b), j >= a} and {min(t') >= b, a <= j < b}, two contiguous
-// ranges of t', so the pull stays a plain gather from LDS.
+// it gathers g_k[t' + e_j] from LDS.  The top layer is consumed in chunks of
+// consecutive "smallest occupied mode" blocks: for a chunk of smallest modes
+// [a, b) the pairs (t', j) whose successor falls in it are exactly
+// {min(t') in [a,b), j >= a} (whole groups of four modes per owned state,
+// G_U partials per lane in registers, one fixed-order DPP reduction per
+// layer) and {min(t') >= b, a <= j < b} (a few modes, one at a time, each
+// mode's G_U share reduced per wave), two contiguous ranges of t', so the
+// pull stays a plain gather from LDS.  The smaller lower layers take g_{k-1}
+// from the same pull and G_U from mode-per-wave dot products.
 #include "slos_internal.h"
 
 namespace slos {
