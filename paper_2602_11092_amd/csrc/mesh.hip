@@ -234,8 +234,10 @@ __global__ __launch_bounds__(1024) void mesh_bwd_sweep_kernel(int m, const float
                                                               const float2* __restrict__ Gf,
                                                               float* __restrict__ gtheta) {
     __shared__ float2 X[2][32][33], G[2][32][33];
+    __shared__ Mzi Ts[496];  // every MZI record, staged once (the sweep's steps read them in order)
     const int tid = threadIdx.x;
     const int half = tid >> 9, pr = (tid >> 5) & 15, col = tid & 31;
+    for (int q = tid; q < num_mzi(m); q += 1024) Ts[q] = Tm[q];
     for (int r = pr; r < m; r += 16) {
         if (col < m) {
             const int q = r * m + col;
@@ -252,7 +254,7 @@ __global__ __launch_bounds__(1024) void mesh_bwd_sweep_kernel(int m, const float
         const int k = (c & 1) + 2 * pr;
         if (c < cend && k <= m - 2) {  // uniform over the 32 lanes of this pair slot
             const int q = col_start(c, m) + pr;
-            const Mzi T = Tm[q];
+            const Mzi T = Ts[q];
             float2 r0 = c_zero(), r1 = c_zero(), g0 = c_zero(), g1 = c_zero();
             if (col < m) {
                 const float2 x0 = X[half][k][col], x1 = X[half][k + 1][col];
