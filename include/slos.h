@@ -79,6 +79,13 @@ extern "C" {
 /* Plan flags. */
 #define SLOS_PLAN_DEFAULT 0
 #define SLOS_PLAN_FORWARD_ONLY 1  /* skip the successor tables; backward calls return SLOS_EUNSUPPORTED */
+/* Restricted computation space (Sec. II-B: computation spaces; the
+ * QuantumBridge example of Sec. II-D uses it): only unbunched outputs,
+ * t_j <= 1, C(m, n) of them, in the basis order above restricted to them.
+ * The recursion stays exact (removing a photon keeps a state unbunched).
+ * Input states may be bunched.  Such plans are forward-only: backward calls
+ * return SLOS_EUNSUPPORTED.  Requires n_max <= m. */
+#define SLOS_PLAN_UNBUNCHED 2
 
 /* Kernel variants for slos_batch_set_config. */
 #define SLOS_VARIANT_AUTO 0    /* library heuristic (or the last value set) */
@@ -93,6 +100,10 @@ typedef struct slos_batch_s* slos_batch_t;
 /* C(m+n-1, n), the dimension of the n-photon Fock space over m modes
  * (Sec. II-A-1).  Returns -1 if m < 1, n < 0 or the value overflows int64. */
 SLOS_API int64_t slos_fock_dim(int m, int n);
+
+/* C(m, n), the number of unbunched n-photon states (t_j <= 1) over m modes;
+ * -1 if m < 1 or n < 0. */
+SLOS_API int64_t slos_unbunched_dim(int m, int n);
 
 /* Occupation vector (occ[0..m-1], host) of the state of the given rank in
  * the basis order above.  Returns SLOS_EINVAL for a bad m, n, rank or NULL. */
@@ -112,6 +123,12 @@ SLOS_API int64_t slos_fock_rank(int m, int n, const int32_t* occ);
  *   minoff [m+1]         first rank of layer k whose smallest occupied mode is >= c.
  * Returns SLOS_EINVAL for bad m or k, SLOS_EUNSUPPORTED if N_k >= 2^26. */
 SLOS_API int slos_transition_tables(int m, int k, int32_t* pred, int32_t* succ, float* nrm, int32_t* minoff);
+
+/* The same with plan flags: SLOS_PLAN_UNBUNCHED gives the tables of the
+ * unbunched space (N_k = C(m, k), k <= m; succ is -1 where t' + e_j would
+ * be bunched).  SLOS_EINVAL for unknown flags or k > m when unbunched. */
+SLOS_API int slos_transition_tables_ex(int m, int k, int flags, int32_t* pred, int32_t* succ, float* nrm,
+                                       int32_t* minoff);
 
 /* Message for the calling thread's most recent failed call ("" if none). */
 SLOS_API const char* slos_last_error(void);

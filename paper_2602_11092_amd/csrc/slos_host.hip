@@ -35,40 +35,47 @@ int64_t binom(int64_t a, int64_t b) {
     return (int64_t)r;
 }
 
-// Counting helper for the basis order (sorted mode lists in lexicographic
-// order).  below[r][c] = number of sorted lists of length r whose first entry
-// is < c and all entries lie in [0, m): the rank offset contributed by a
-// position holding c when r more entries follow it, measured from 0.
+// Counting helper for the basis order: sorted mode lists in lexicographic
+// order, non-decreasing (every Fock state) or, with `strict`, strictly
+// increasing (the unbunched states, t_j <= 1: the same order restricted to
+// them).  below[r][c] = number of lists of length r + 1 whose first entry is
+// < c: the rank offset contributed by a position holding c when r more
+// entries follow it.
 struct Counter {
     int m = 0;
     int K = 0;
+    bool strict = false;
     std::vector<std::vector<int64_t>> below;  // [r][c], r = 0..K, c = 0..m
 
-    Counter(int m_, int K_) : m(m_), K(K_), below(K_ + 1, std::vector<int64_t>(m_ + 1, 0)) {
+    Counter(int m_, int K_, bool strict_ = false)
+        : m(m_), K(K_), strict(strict_), below(K_ + 1, std::vector<int64_t>(m_ + 1, 0)) {
         for (int r = 0; r <= K; ++r) {
             int64_t acc = 0;
             for (int c = 0; c <= m; ++c) {
                 below[r][c] = acc;
-                if (c < m) acc += count_from(c, r);
+                if (c < m) acc += count_after(c, r);
             }
         }
     }
-    // number of sorted lists of length r with entries in [c, m)
+    // number of lists of length r with entries in [c, m)
     int64_t count_from(int c, int r) const {
         if (r == 0) return 1;
-        return binom((int64_t)(m - c) + r - 1, r);
+        if (c >= m) return 0;
+        return strict ? binom((int64_t)(m - c), r) : binom((int64_t)(m - c) + r - 1, r);
     }
+    // completions of length r after an entry c
+    int64_t count_after(int c, int r) const { return count_from(strict ? c + 1 : c, r); }
     // rank of sorted list L[0..len) skipping index `skip` (-1: none)
     int64_t rank(const int* L, int len, int skip = -1) const {
         const int K2 = (skip >= 0) ? len - 1 : len;
         int64_t r = 0;
-        int prev = 0;
+        int lo = 0;
         int pos = 0;
         for (int q = 0; q < len; ++q) {
             if (q == skip) continue;
             const int rem = K2 - pos - 1;
-            r += below[rem][L[q]] - below[rem][prev];
-            prev = L[q];
+            r += below[rem][L[q]] - below[rem][lo];
+            lo = strict ? L[q] + 1 : L[q];
             ++pos;
         }
         return r;
@@ -79,24 +86,32 @@ struct Counter {
             const int rem = len - pos - 1;
             int j = lo;
             while (true) {
-                const int64_t blk = count_from(j, rem);
+                const int64_t blk = count_after(j, rem);
                 if (r < blk) break;
                 r -= blk;
                 ++j;
             }
             L[pos] = j;
-            lo = j;
+            lo = strict ? j + 1 : j;
         }
     }
 };
 
 // next sorted list in lexicographic order; false after the last one
-bool next_list(int* L, int len, int m) {
+bool next_list(int* L, int len, int m, bool strict = false) {
+    if (!strict) {
+        int q = len - 1;
+        while (q >= 0 && L[q] == m - 1) --q;
+        if (q < 0) return false;
+        ++L[q];
+        for (int r = q + 1; r < len; ++r) L[r] = L[q];
+        return true;
+    }
     int q = len - 1;
-    while (q >= 0 && L[q] == m - 1) --q;
+    while (q >= 0 && L[q] == m - len + q) --q;
     if (q < 0) return false;
     ++L[q];
-    for (int r = q + 1; r < len; ++r) L[r] = L[q];
+    for (int r = q + 1; r < len; ++r) L[r] = L[r - 1] + 1;
     return true;
 }
 
@@ -143,7 +158,7 @@ void build_layer(int m, int k, const Counter& Ck, const Counter& Ckm1, int64_t N
                 }
             }
             H.nrm[t] = (float)std::sqrt(f);
-            next_list(L, k, m);
+            next_list(L, k, m, Ck.strict);
         }
     });
     if (want_succ) {
@@ -153,18 +168,19 @@ void build_layer(int m, int k, const Counter& Ck, const Counter& Ckm1, int64_t N
             if (k - 1 > 0) Ckm1.unrank(lo, k - 1, L);
             for (int64_t t = lo; t < hi; ++t) {
                 for (int j = 0; j < m; ++j) {
-                    // insert j into the sorted list
+                    // insert j into the sorted list (-1 when it leaves an unbunched space)
                     int q = 0, o = 0;
-                    bool done = false;
+                    bool done = false, twice = false;
                     for (int p = 0; p < k - 1; ++p) {
+                        if (L[p] == j) twice = true;
                         if (!done && j < L[p]) { T[o++] = j; done = true; }
                         T[o++] = L[p];
                         ++q;
                     }
                     if (!done) T[o++] = j;
-                    H.succ[(size_t)j * Nkm1 + t] = (int32_t)Ck.rank(T, k);
+                    H.succ[(size_t)j * Nkm1 + t] = (Ck.strict && twice) ? -1 : (int32_t)Ck.rank(T, k);
                 }
-                if (k - 1 > 0) next_list(L, k - 1, m);
+                if (k - 1 > 0) next_list(L, k - 1, m, Ckm1.strict);
             }
         });
     }
@@ -213,13 +229,28 @@ extern "C" int64_t slos_fock_rank(int m, int n, const int32_t* occ) {
     return C.rank(L.data(), n);
 }
 
+extern "C" int64_t slos_unbunched_dim(int m, int n) {
+    if (m < 1 || n < 0) return -1;
+    return binom((int64_t)m, n);
+}
+
 extern "C" int slos_transition_tables(int m, int k, int32_t* pred, int32_t* succ, float* nrm, int32_t* minoff) {
+    return slos_transition_tables_ex(m, k, SLOS_PLAN_DEFAULT, pred, succ, nrm, minoff);
+}
+
+extern "C" int slos_transition_tables_ex(int m, int k, int flags, int32_t* pred, int32_t* succ, float* nrm,
+                                         int32_t* minoff) {
     if (m < 1 || m > kMaxModes) return fail(SLOS_EINVAL, "slos_transition_tables: m must be in [1, 32]");
     if (k < 1 || k > kMaxPhotons) return fail(SLOS_EINVAL, "slos_transition_tables: k must be in [1, 16]");
-    const int64_t Nk = slos_fock_dim(m, k), Nkm1 = slos_fock_dim(m, k - 1);
+    if (flags & ~(SLOS_PLAN_FORWARD_ONLY | SLOS_PLAN_UNBUNCHED))
+        return fail(SLOS_EINVAL, "slos_transition_tables: unknown flags");
+    const bool strict = (flags & SLOS_PLAN_UNBUNCHED) != 0;
+    if (strict && k > m) return fail(SLOS_EINVAL, "slos_transition_tables: unbunched layers need k <= m");
+    const int64_t Nk = strict ? slos_unbunched_dim(m, k) : slos_fock_dim(m, k);
+    const int64_t Nkm1 = strict ? slos_unbunched_dim(m, k - 1) : slos_fock_dim(m, k - 1);
     if (Nk < 0 || Nk >= ((int64_t)1 << (31 - kModeBits)))
         return fail(SLOS_EUNSUPPORTED, "slos_transition_tables: layer too large for 32-bit tables");
-    Counter Ck(m, k), Ckm1(m, k - 1);
+    Counter Ck(m, k, strict), Ckm1(m, k - 1, strict);
     HostLayer H;
     build_layer(m, k, Ck, Ckm1, Nk, Nkm1, succ != nullptr, H);
     if (pred) std::memcpy(pred, H.pred.data(), H.pred.size() * 4);
@@ -234,10 +265,14 @@ extern "C" int slos_plan_create(int m, int n_max, int flags, slos_plan_t* out) {
     *out = nullptr;
     if (m < 1 || m > kMaxModes) return fail(SLOS_EINVAL, "slos_plan_create: m must be in [1, 32]");
     if (n_max < 1 || n_max > kMaxPhotons) return fail(SLOS_EINVAL, "slos_plan_create: n_max must be in [1, 16]");
-    if (flags & ~SLOS_PLAN_FORWARD_ONLY) return fail(SLOS_EINVAL, "slos_plan_create: unknown flags");
-    const int64_t Ntop = slos_fock_dim(m, n_max);
+    if (flags & ~(SLOS_PLAN_FORWARD_ONLY | SLOS_PLAN_UNBUNCHED))
+        return fail(SLOS_EINVAL, "slos_plan_create: unknown flags");
+    const bool strict = (flags & SLOS_PLAN_UNBUNCHED) != 0;
+    if (strict && n_max > m) return fail(SLOS_EINVAL, "slos_plan_create: unbunched plans need n_max <= m");
+    const int64_t Ntop = strict ? slos_unbunched_dim(m, n_max) : slos_fock_dim(m, n_max);
     // successor byte offsets (rank * 8) must fit 32 bits, predecessor ranks the wide entry
-    if (Ntop < 0 || Ntop >= ((int64_t)1 << 29) || slos_fock_dim(m, n_max - 1) >= kPredWideStates)
+    if (Ntop < 0 || Ntop >= ((int64_t)1 << 29) ||
+        (strict ? slos_unbunched_dim(m, n_max - 1) : slos_fock_dim(m, n_max - 1)) >= kPredWideStates)
         return fail(SLOS_EUNSUPPORTED, "slos_plan_create: Fock space too large for 32-bit tables");
 
     auto* P = new slos_plan_s();
@@ -245,7 +280,7 @@ extern "C" int slos_plan_create(int m, int n_max, int flags, slos_plan_t* out) {
     P->n_max = n_max;
     P->flags = flags;
     P->N.resize(n_max + 1);
-    for (int k = 0; k <= n_max; ++k) P->N[k] = slos_fock_dim(m, k);
+    for (int k = 0; k <= n_max; ++k) P->N[k] = strict ? slos_unbunched_dim(m, k) : slos_fock_dim(m, k);
 
     if (hipGetDevice(&P->device) != hipSuccess) {
         delete P;
@@ -257,12 +292,13 @@ extern "C" int slos_plan_create(int m, int n_max, int flags, slos_plan_t* out) {
     P->num_cu = cu;
     P->max_lds = (size_t)lds;
 
-    const bool want_succ = !(flags & SLOS_PLAN_FORWARD_ONLY);
+    // the unbunched space has no successor tables (t' + e_j can leave it): forward only
+    const bool want_succ = !(flags & (SLOS_PLAN_FORWARD_ONLY | SLOS_PLAN_UNBUNCHED));
     std::vector<HostLayer> H(n_max + 1);
     std::vector<int> shifts(n_max + 1, kPredShiftCompact);
     std::vector<Counter> C;
     C.reserve(n_max + 1);
-    for (int k = 0; k <= n_max; ++k) C.emplace_back(m, k);
+    for (int k = 0; k <= n_max; ++k) C.emplace_back(m, k, strict);
     for (int k = 1; k <= n_max; ++k) {
         build_layer(m, k, C[k], C[k - 1], P->N[k], P->N[k - 1], want_succ, H[k]);
         // device layout: groups of four predecessor entries per state, [group][state][4],
@@ -520,6 +556,8 @@ int run(slos_batch_t batch, int op, const float* U, const void* gin, void* out, 
     if (bwd && !gin) return fail(SLOS_EINVAL, nm + ": gradient input is NULL");
     if (bwd && (batch->plan->flags & SLOS_PLAN_FORWARD_ONLY))
         return fail(SLOS_EUNSUPPORTED, nm + ": plan was created forward-only");
+    if (bwd && (batch->plan->flags & SLOS_PLAN_UNBUNCHED))
+        return fail(SLOS_EUNSUPPORTED, nm + ": unbunched plans are forward-only");
     int v, blk;
     resolve(*batch, op, &v, &blk);
     const bool probs = (op == SLOS_OP_PROBS || op == SLOS_OP_PROBS_BACKWARD);

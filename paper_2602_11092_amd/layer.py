@@ -17,21 +17,30 @@ from .autograd import fock_amplitudes, fock_probs, mesh_to_unitary
 class QuantumLayer(nn.Module):
     """x [batch, m] float32 -> probabilities [batch, C(m+n-1, n)] (or
     complex amplitudes with measurement="amplitudes") for one input Fock
-    state.  Trainable parameters: the m(m-1) mesh phases."""
+    state.  Trainable parameters: the m(m-1) mesh phases.
+
+    computation_space="unbunched" keeps only the output states with at most
+    one photon per mode (C(m, n) of them, in the same relative order); it is
+    forward-only, so it needs torch.no_grad() or a theta without grad."""
 
     def __init__(self, m: int, input_state: Sequence[int], enc_scale: float = math.pi,
-                 measurement: str = "probs", seed: int = 0):
+                 measurement: str = "probs", seed: int = 0, computation_space: str = "fock"):
         super().__init__()
         occ = np.asarray(input_state, dtype=np.int32)
         if occ.shape != (m,):
             raise ValueError("input_state must have m entries")
         if measurement not in ("probs", "amplitudes"):
             raise ValueError("measurement must be 'probs' or 'amplitudes'")
+        if computation_space not in ("fock", "unbunched"):
+            raise ValueError("computation_space must be 'fock' or 'unbunched'")
+        if computation_space == "unbunched" and int(occ.sum()) > m:
+            raise ValueError("the unbunched space needs at most m photons")
         self.m = m
         self.n = int(occ.sum())
         self.occ = occ
         self.enc_scale = float(enc_scale)
         self.measurement = measurement
+        self.computation_space = computation_space
         g = torch.Generator().manual_seed(seed)
         self.theta = nn.Parameter(torch.rand(m * (m - 1), generator=g) * (2 * math.pi))
         self._plan = None
@@ -39,11 +48,13 @@ class QuantumLayer(nn.Module):
 
     @property
     def output_size(self) -> int:
+        if self.computation_space == "unbunched":
+            return B.slos_unbunched_dim(self.m, self.n)
         return B.slos_fock_dim(self.m, self.n)
 
     def _batch(self, nb: int) -> B.Batch:
         if self._plan is None:
-            self._plan = B.Plan(self.m, max(self.n, 1))
+            self._plan = B.Plan(self.m, max(self.n, 1), unbunched=self.computation_space == "unbunched")
         bt = self._batches.get(nb)
         if bt is None:
             bt = B.Batch(self._plan, np.tile(self.occ, (nb, 1)))
@@ -51,6 +62,8 @@ class QuantumLayer(nn.Module):
         return bt
 
     def forward(self, x: torch.Tensor) -> torch.Tensor:
+        if self.computation_space == "unbunched" and torch.is_grad_enabled() and self.theta.requires_grad:
+            raise RuntimeError("the unbunched computation space is forward-only: use torch.no_grad()")
         U = mesh_to_unitary(self.theta, x.to(torch.float32), self.enc_scale, self.m)
         bt = self._batch(x.shape[0])
         if self.measurement == "probs":

@@ -1,0 +1,149 @@
+"""GPU parity of the unbunched computation space: the HIP kernels on an
+unbunched plan against the FP64 Ryser oracle evaluated on the output states
+with at most one photon per mode, in the Fock basis order restricted to them
+(lexicographic order of the occupied-mode lists).  Inputs may be bunched."""
+import itertools
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import oracle as O
+from paper_2602_11092_amd import QuantumLayer
+from paper_2602_11092_amd import _binding as B
+from tests.gpu_util import A_TOL, DEV, P_TOL, run_forward, say, to_dev_c64, widen
+
+pytestmark = pytest.mark.gpu
+
+VARIANTS = [B.VARIANT_FUSED, B.VARIANT_LAYERED]
+
+
+def _outputs(m, n):
+    rows = np.zeros((math.comb(m, n), m), dtype=np.int32)
+    for r, modes in enumerate(itertools.combinations(range(m), n)):
+        rows[r, list(modes)] = 1
+    return rows
+
+
+def _batch(rng, B_, m, n_lo, n_hi, bunched):
+    U = W.haar_unitaries(rng, B_, m).astype(np.complex64)
+    occ = np.zeros((B_, m), dtype=np.int32)
+    for b in range(B_):
+        n = int(rng.integers(n_lo, n_hi + 1))
+        for i in rng.choice(m, size=n, replace=bunched):
+            occ[b, i] += 1
+    return U, occ
+
+
+def _check(batch, U64, occ, out, amplitudes):
+    m = occ.shape[1]
+    worst = 0.0
+    for b in range(batch.B):
+        n = int(occ[b].sum())
+        o0, o1 = batch.offsets[b], batch.offsets[b + 1]
+        assert o1 - o0 == math.comb(m, n)
+        outs = _outputs(m, n)
+        ref = (O.amplitudes if amplitudes else O.probabilities)(widen(U64[b]), occ[b], outputs=outs)
+        worst = max(worst, float(np.abs(out[o0:o1] - ref).max()))
+    assert worst <= (A_TOL if amplitudes else P_TOL), worst
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("amplitudes", [False, True])
+@pytest.mark.parametrize("bunched", [False, True])
+def test_unbunched_mixed_batch_m10(variant, amplitudes, bunched):
+    rng = np.random.default_rng(31 + bunched)
+    U, occ = _batch(rng, 40, 10, 1, 7, bunched)
+    say("unbunched m10 variant", variant, "amplitudes", amplitudes, "bunched inputs", bunched)
+    plan = B.Plan(10, int(occ.sum(1).max()), unbunched=True)
+    batch = B.Batch(plan, occ)
+    op = B.OP_AMPLITUDES if amplitudes else B.OP_PROBS
+    batch.set_config(op, variant, 256)
+    out = run_forward(batch, to_dev_c64(U), amplitudes)
+    _check(batch, U, occ, out, amplitudes)
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_unbunched_dual_rail_m4_n2(variant):
+    # two dual-rail qubits: photons in modes 0 and 2 of 4; six unbunched outputs
+    rng = np.random.default_rng(5)
+    U = W.haar_unitaries(rng, 3, 4).astype(np.complex64)
+    occ = np.tile(np.array([1, 0, 1, 0], dtype=np.int32), (3, 1))
+    batch = B.Batch(B.Plan(4, 2, unbunched=True), occ)
+    batch.set_config(B.OP_AMPLITUDES, variant, 256)
+    out = run_forward(batch, to_dev_c64(U), True)
+    assert out.size == 3 * 6
+    _check(batch, U, occ, out, True)
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_unbunched_edge_cases(variant):
+    # one photon (every output unbunched: equals the full space), n = m (a
+    # single output, |Perm U|^2), and identity unitaries (a permutation of the input)
+    m = 6
+    rng = np.random.default_rng(9)
+    U = W.haar_unitaries(rng, 4, m).astype(np.complex64)
+    U[3] = np.eye(m, dtype=np.complex64)
+    occ = np.array([[0, 0, 1, 0, 0, 0], [1] * m, [2, 0, 0, 1, 0, 0], [1, 0, 1, 1, 0, 0]], dtype=np.int32)
+    batch = B.Batch(B.Plan(m, m, unbunched=True), occ)
+    batch.set_config(B.OP_PROBS, variant, 256)
+    p = run_forward(batch, to_dev_c64(U), False)
+    _check(batch, U, occ, p, False)
+    o = batch.offsets
+    assert o[2] - o[1] == 1
+    assert abs(p[o[1]] - abs(O.permanent(widen(U[1]))) ** 2) <= P_TOL
+    # the identity maps |1,0,1,1,0,0> to itself
+    pid = p[o[3]:o[4]]
+    want = np.zeros(math.comb(m, 3))
+    want[[r for r, t in enumerate(_outputs(m, 3)) if (t == occ[3]).all()][0]] = 1.0
+    assert np.abs(pid - want).max() <= P_TOL
+
+
+def test_unbunched_probabilities_are_the_fock_subvector():
+    # the same batch on a full plan, restricted to the unbunched outputs
+    m, n = 9, 4
+    rng = np.random.default_rng(12)
+    U, occ = _batch(rng, 16, m, n, n, True)
+    Ud = to_dev_c64(U)
+    pu = run_forward(B.Batch(B.Plan(m, n, unbunched=True), occ), Ud, False).reshape(16, -1)
+    pf = run_forward(B.Batch(B.Plan(m, n), occ), Ud, False).reshape(16, -1)
+    keep = np.array([int(t.max()) <= 1 for t in O.fock_basis(m, n)])
+    assert np.abs(pu - pf[:, keep]).max() <= 1e-6
+
+
+def test_unbunched_m24_n8_sampled():
+    wl = W.make("haar_m24_n8_b16")
+    say("unbunched haar_m24_n8_b16 forward")
+    batch = B.Batch(B.Plan(24, 8, unbunched=True), wl.occ)
+    p = run_forward(batch, to_dev_c64(wl.U), False)
+    N = math.comb(24, 8)
+    pb = p.reshape(16, N)
+    assert (pb.sum(axis=1, dtype=np.float64) <= 1 + 1e-4).all()
+    combos = list(itertools.combinations(range(24), 8))
+    rng = np.random.default_rng(2)
+    for b in [0, 9, 15]:
+        ranks = np.unique(np.r_[0, N - 1, rng.integers(0, N, 300), np.argsort(pb[b])[-20:]])
+        outs = np.zeros((ranks.size, 24), dtype=np.int32)
+        for i, r in enumerate(ranks):
+            outs[i, list(combos[r])] = 1
+        ref = O.probabilities(widen(wl.U[b]), wl.occ[b], outputs=outs)
+        assert np.abs(pb[b, ranks] - ref).max() <= P_TOL
+
+
+def test_unbunched_backward_is_rejected():
+    rng = np.random.default_rng(1)
+    U, occ = _batch(rng, 4, 6, 3, 3, False)
+    batch = B.Batch(B.Plan(6, 3, unbunched=True), occ)
+    Ud = to_dev_c64(U)
+    g = torch.ones(batch.out_len, dtype=torch.float32, device=DEV)
+    with pytest.raises(B.SlosError):
+        B.fock_probs_backward(batch, Ud, g)
+    layer = QuantumLayer(6, [1, 1, 1, 0, 0, 0], computation_space="unbunched").to(DEV)
+    x = torch.zeros(2, 6, device=DEV)
+    with pytest.raises(RuntimeError):
+        layer(x)
+    with torch.no_grad():
+        p = layer(x)
+    assert p.shape == (2, 20)

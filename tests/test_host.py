@@ -143,3 +143,67 @@ def test_plan_without_device_fails_cleanly():
     h = ctypes.c_void_p()
     assert B.lib().slos_plan_create(6, 3, 0, ctypes.byref(h)) == B.SLOS_EHIP
     assert not h.value
+
+
+def _unbunched_basis(m, k):
+    # the Fock basis order restricted to states with every t_j <= 1
+    return [t for t in O.fock_basis(m, k) if int(np.max(t, initial=0)) <= 1]
+
+
+@pytest.mark.parametrize("m,n", [(1, 1), (4, 2), (6, 3), (8, 8), (24, 8), (32, 5)])
+def test_unbunched_dim(m, n):
+    assert B.slos_unbunched_dim(m, n) == math.comb(m, n)
+    assert B.slos_unbunched_dim(3, 4) == 0  # more photons than modes
+    assert B.slos_unbunched_dim(0, 1) == -1
+
+
+@pytest.mark.parametrize("m,k", [(4, 1), (5, 2), (6, 3), (7, 4), (5, 5)])
+def test_unbunched_transition_tables_against_enumeration(m, k):
+    pred, succ, nrm, minoff = B.slos_transition_tables(m, k, unbunched=True)
+    layer = _unbunched_basis(m, k)
+    prev = _unbunched_basis(m, k - 1)
+    assert pred.shape == (k, len(layer)) == (k, math.comb(m, k))
+    rank = {tuple(int(v) for v in t): r for r, t in enumerate(layer)}
+    rank_prev = {tuple(int(v) for v in t): r for r, t in enumerate(prev)}
+    for r, t in enumerate(layer):
+        modes = [j for j in range(m) if t[j] > 0]
+        for p in range(k):
+            # one entry per occupied mode: no bunching, so none is empty
+            e = int(pred[p, r])
+            assert e >= 0
+            j = e & 31
+            assert j == modes[p]
+            tm = t.copy()
+            tm[j] -= 1
+            assert (e >> 5) == rank_prev[tuple(int(v) for v in tm)]
+        assert nrm[r] == 1.0
+    for r, t in enumerate(prev):
+        for j in range(m):
+            tp = t.copy()
+            tp[j] += 1
+            want = rank.get(tuple(int(v) for v in tp), -1)
+            assert succ[j, r] == want, (t, j)
+            assert (want == -1) == (t[j] == 1)
+    for c in range(m + 1):
+        first = next((r for r, t in enumerate(layer) if min(j for j in range(m) if t[j] > 0) >= c), len(layer))
+        assert minoff[c] == first
+
+
+def test_unbunched_argument_errors_without_device():
+    # argument checks come before any device call
+    L = B.lib()
+    h = ctypes.c_void_p()
+    assert L.slos_plan_create(3, 4, B.PLAN_UNBUNCHED, ctypes.byref(h)) == B.SLOS_EINVAL  # n_max > m
+    assert L.slos_plan_create(3, 2, 4, ctypes.byref(h)) == B.SLOS_EINVAL  # unknown flag
+    with pytest.raises(B.SlosError):
+        B.slos_transition_tables(3, 4, unbunched=True)
+
+
+def test_quantum_layer_computation_space_arguments():
+    from paper_2602_11092_amd import QuantumLayer
+    assert QuantumLayer(6, [1, 1, 1, 0, 0, 0], computation_space="unbunched").output_size == 20
+    assert QuantumLayer(6, [1, 1, 1, 0, 0, 0]).output_size == 56
+    with pytest.raises(ValueError):
+        QuantumLayer(3, [2, 1, 1], computation_space="unbunched")
+    with pytest.raises(ValueError):
+        QuantumLayer(3, [1, 1, 0], computation_space="dual")
