@@ -86,6 +86,15 @@ extern "C" {
  * Input states may be bunched.  Such plans are forward-only: backward calls
  * return SLOS_EUNSUPPORTED.  Requires n_max <= m. */
 #define SLOS_PLAN_UNBUNCHED 2
+/* Dual-rail computation space (Sec. II-B: computation spaces; Sec. II-D:
+ * the qubit-photon bridge): qubit g is the mode pair (2g, 2g+1) and every
+ * state holds at most one photon per pair, C(m/2, n) 2^n states.  With
+ * n = m/2 photons these are the 2^n logical states |q_0 ... q_{n-1}> (the
+ * photon of qubit g in mode 2g + q_g), in big-endian binary order.  The
+ * recursion stays exact (removing a photon keeps the constraint).  Inputs
+ * may be any Fock state.  Forward-only like SLOS_PLAN_UNBUNCHED; requires
+ * an even m and n_max <= m/2; excludes SLOS_PLAN_UNBUNCHED. */
+#define SLOS_PLAN_DUAL_RAIL 4
 
 /* Kernel variants for slos_batch_set_config. */
 #define SLOS_VARIANT_AUTO 0    /* library heuristic (or the last value set) */
@@ -104,6 +113,11 @@ SLOS_API int64_t slos_fock_dim(int m, int n);
 /* C(m, n), the number of unbunched n-photon states (t_j <= 1) over m modes;
  * -1 if m < 1 or n < 0. */
 SLOS_API int64_t slos_unbunched_dim(int m, int n);
+
+/* Number of n-photon states of the space a plan with these flags uses:
+ * slos_fock_dim, slos_unbunched_dim or C(m/2, n) 2^n for dual-rail.  -1 for
+ * bad flags, m or n (dual-rail with an odd m included); 0 when no state fits. */
+SLOS_API int64_t slos_space_dim(int m, int n, int flags);
 
 /* Occupation vector (occ[0..m-1], host) of the state of the given rank in
  * the basis order above.  Returns SLOS_EINVAL for a bad m, n, rank or NULL. */
@@ -124,9 +138,10 @@ SLOS_API int64_t slos_fock_rank(int m, int n, const int32_t* occ);
  * Returns SLOS_EINVAL for bad m or k, SLOS_EUNSUPPORTED if N_k >= 2^26. */
 SLOS_API int slos_transition_tables(int m, int k, int32_t* pred, int32_t* succ, float* nrm, int32_t* minoff);
 
-/* The same with plan flags: SLOS_PLAN_UNBUNCHED gives the tables of the
- * unbunched space (N_k = C(m, k), k <= m; succ is -1 where t' + e_j would
- * be bunched).  SLOS_EINVAL for unknown flags or k > m when unbunched. */
+/* The same with plan flags: SLOS_PLAN_UNBUNCHED or SLOS_PLAN_DUAL_RAIL give
+ * the tables of that space (N_k = slos_space_dim(m, k, flags); succ is -1
+ * where t' + e_j leaves the space).  SLOS_EINVAL for unknown or conflicting
+ * flags, or k beyond what the space holds. */
 SLOS_API int slos_transition_tables_ex(int m, int k, int flags, int32_t* pred, int32_t* succ, float* nrm,
                                        int32_t* minoff);
 

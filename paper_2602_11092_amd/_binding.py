@@ -32,6 +32,7 @@ OP_PROBS_BACKWARD = 3
 PLAN_DEFAULT = 0
 PLAN_FORWARD_ONLY = 1
 PLAN_UNBUNCHED = 2
+PLAN_DUAL_RAIL = 4
 
 VARIANT_AUTO = 0
 VARIANT_FUSED = 1
@@ -43,6 +44,7 @@ _vp = _c.c_void_p
 SIGNATURES = {
     "slos_fock_dim": (_c.c_int64, [_c.c_int, _c.c_int]),
     "slos_unbunched_dim": (_c.c_int64, [_c.c_int, _c.c_int]),
+    "slos_space_dim": (_c.c_int64, [_c.c_int, _c.c_int, _c.c_int]),
     "slos_fock_unrank": (_c.c_int, [_c.c_int, _c.c_int, _c.c_int64, _vp]),
     "slos_fock_rank": (_c.c_int64, [_c.c_int, _c.c_int, _vp]),
     "slos_last_error": (_c.c_char_p, []),
@@ -128,6 +130,15 @@ def slos_unbunched_dim(m: int, n: int) -> int:
     return int(lib().slos_unbunched_dim(m, n))
 
 
+def space_flags(unbunched: bool = False, dual_rail: bool = False) -> int:
+    return (PLAN_UNBUNCHED if unbunched else 0) | (PLAN_DUAL_RAIL if dual_rail else 0)
+
+
+def slos_space_dim(m: int, n: int, flags: int = PLAN_DEFAULT) -> int:
+    """Size of the n-photon layer of the space that plans with `flags` use (-1 if invalid)."""
+    return int(lib().slos_space_dim(m, n, flags))
+
+
 def slos_fock_unrank(m: int, n: int, rank: int) -> np.ndarray:
     occ = np.zeros(m, dtype=np.int32)
     _check("slos_fock_unrank", lib().slos_fock_unrank(m, n, rank, occ.ctypes.data_as(_vp)))
@@ -144,14 +155,16 @@ def slos_fock_rank(m: int, n: int, occ) -> int:
 class Plan:
     """Transition graph for m modes and up to n_max photons (slos_plan_create)."""
 
-    def __init__(self, m: int, n_max: int, forward_only: bool = False, unbunched: bool = False):
+    def __init__(self, m: int, n_max: int, forward_only: bool = False, unbunched: bool = False,
+                 dual_rail: bool = False):
         h = _vp()
-        flags = (PLAN_FORWARD_ONLY if forward_only else PLAN_DEFAULT) | (PLAN_UNBUNCHED if unbunched else 0)
+        flags = space_flags(unbunched, dual_rail) | (PLAN_FORWARD_ONLY if forward_only else PLAN_DEFAULT)
         _check("slos_plan_create", lib().slos_plan_create(m, n_max, flags, ctypes.byref(h)))
         self._h = h
         self.m = m
         self.n_max = n_max
         self.unbunched = unbunched
+        self.dual_rail = dual_rail
 
     @property
     def handle(self):
@@ -360,13 +373,14 @@ def mesh_to_unitary_backward(theta: torch.Tensor, x: Optional[torch.Tensor], enc
     return gt, gx
 
 
-def slos_transition_tables(m: int, k: int, want_succ: bool = True, unbunched: bool = False):
+def slos_transition_tables(m: int, k: int, want_succ: bool = True, unbunched: bool = False,
+                           dual_rail: bool = False):
     """Host copy of layer k's transition tables: (pred [k, N_k], succ [m, N_{k-1}]
-    or None, nrm [N_k], minoff [m+1]).  With `unbunched`, the tables of the
-    space of states with at most one photon per mode (N_k = C(m, k))."""
-    dim = slos_unbunched_dim if unbunched else slos_fock_dim
-    Nk = dim(m, k)
-    Nkm1 = dim(m, k - 1)
+    or None, nrm [N_k], minoff [m+1]).  With `unbunched` or `dual_rail`, the
+    tables of that restricted space."""
+    flags = space_flags(unbunched, dual_rail)
+    Nk = slos_space_dim(m, k, flags)
+    Nkm1 = slos_space_dim(m, k - 1, flags)
     if Nk < 0 or Nkm1 < 0:
         raise SlosError("slos_transition_tables", SLOS_EINVAL, "bad m=%d k=%d" % (m, k))
     pred = np.zeros((k, Nk), dtype=np.int32)
@@ -374,7 +388,7 @@ def slos_transition_tables(m: int, k: int, want_succ: bool = True, unbunched: bo
     nrm = np.zeros(Nk, dtype=np.float32)
     minoff = np.zeros(m + 1, dtype=np.int32)
     _check("slos_transition_tables_ex",
-           lib().slos_transition_tables_ex(m, k, PLAN_UNBUNCHED if unbunched else PLAN_DEFAULT,
+           lib().slos_transition_tables_ex(m, k, flags,
                                            pred.ctypes.data_as(_vp),
                                            succ.ctypes.data_as(_vp) if succ is not None else None,
                                            nrm.ctypes.data_as(_vp), minoff.ctypes.data_as(_vp)))

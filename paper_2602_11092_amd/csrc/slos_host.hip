@@ -36,19 +36,21 @@ int64_t binom(int64_t a, int64_t b) {
 }
 
 // Counting helper for the basis order: sorted mode lists in lexicographic
-// order, non-decreasing (every Fock state) or, with `strict`, strictly
-// increasing (the unbunched states, t_j <= 1: the same order restricted to
-// them).  below[r][c] = number of lists of length r + 1 whose first entry is
-// < c: the rank offset contributed by a position holding c when r more
-// entries follow it.
+// order.  group = 0: non-decreasing lists (every Fock state).  group = G >= 1:
+// at most one photon in each block of G consecutive modes, so the list is
+// strictly increasing in mode / G (G = 1: the unbunched states, t_j <= 1;
+// G = 2: dual-rail, at most one photon per qubit's pair of modes).  The
+// restricted orders are the full order restricted to those states.
+// below[r][c] = number of lists of length r + 1 whose first entry is < c: the
+// rank offset contributed by a position holding c when r more entries follow.
 struct Counter {
     int m = 0;
     int K = 0;
-    bool strict = false;
+    int group = 0;
     std::vector<std::vector<int64_t>> below;  // [r][c], r = 0..K, c = 0..m
 
-    Counter(int m_, int K_, bool strict_ = false)
-        : m(m_), K(K_), strict(strict_), below(K_ + 1, std::vector<int64_t>(m_ + 1, 0)) {
+    Counter(int m_, int K_, int group_ = 0)
+        : m(m_), K(K_), group(group_), below(K_ + 1, std::vector<int64_t>(m_ + 1, 0)) {
         for (int r = 0; r <= K; ++r) {
             int64_t acc = 0;
             for (int c = 0; c <= m; ++c) {
@@ -61,10 +63,18 @@ struct Counter {
     int64_t count_from(int c, int r) const {
         if (r == 0) return 1;
         if (c >= m) return 0;
-        return strict ? binom((int64_t)(m - c), r) : binom((int64_t)(m - c) + r - 1, r);
+        if (group == 0) return binom((int64_t)(m - c) + r - 1, r);
+        // the first entry either sits in c's own block (from c on) or in one
+        // of the F whole blocks after it; each later entry picks a later block
+        const int G = group, g0 = c / G, F = m / G - g0 - 1;
+        const int64_t head = (int64_t)(g0 + 1) * G - c;
+        auto pw = [&](int e) { int64_t v = 1; for (int i = 0; i < e; ++i) v *= G; return v; };
+        return head * pw(r - 1) * binom(F, r - 1) + pw(r) * binom(F, r);
     }
+    // smallest entry allowed after an entry c
+    int next_lo(int c) const { return group == 0 ? c : (c / group + 1) * group; }
     // completions of length r after an entry c
-    int64_t count_after(int c, int r) const { return count_from(strict ? c + 1 : c, r); }
+    int64_t count_after(int c, int r) const { return count_from(next_lo(c), r); }
     // rank of sorted list L[0..len) skipping index `skip` (-1: none)
     int64_t rank(const int* L, int len, int skip = -1) const {
         const int K2 = (skip >= 0) ? len - 1 : len;
@@ -75,7 +85,7 @@ struct Counter {
             if (q == skip) continue;
             const int rem = K2 - pos - 1;
             r += below[rem][L[q]] - below[rem][lo];
-            lo = strict ? L[q] + 1 : L[q];
+            lo = next_lo(L[q]);
             ++pos;
         }
         return r;
@@ -92,26 +102,58 @@ struct Counter {
                 ++j;
             }
             L[pos] = j;
-            lo = strict ? j + 1 : j;
+            lo = next_lo(j);
         }
+    }
+    // next list in the order; false after the last one
+    bool next(int* L, int len) const {
+        for (int q = len - 1; q >= 0; --q) {
+            const int v = L[q] + 1;
+            if (v >= m) continue;
+            if (group > 0 && m / group - v / group - 1 < len - q - 1) continue;  // no room for the rest
+            L[q] = v;
+            for (int r = q + 1; r < len; ++r) L[r] = next_lo(L[r - 1]);
+            return true;
+        }
+        return false;
+    }
+    // whether inserting mode j into L keeps the list in the space
+    bool admits(const int* L, int len, int j) const {
+        if (group == 0) return true;
+        for (int p = 0; p < len; ++p)
+            if (L[p] / group == j / group) return false;
+        return true;
     }
 };
 
-// next sorted list in lexicographic order; false after the last one
-bool next_list(int* L, int len, int m, bool strict = false) {
-    if (!strict) {
-        int q = len - 1;
-        while (q >= 0 && L[q] == m - 1) --q;
-        if (q < 0) return false;
-        ++L[q];
-        for (int r = q + 1; r < len; ++r) L[r] = L[q];
-        return true;
-    }
-    int q = len - 1;
-    while (q >= 0 && L[q] == m - len + q) --q;
-    if (q < 0) return false;
-    ++L[q];
-    for (int r = q + 1; r < len; ++r) L[r] = L[r - 1] + 1;
+// Size of layer n of a space (group as in Counter); -1 if invalid.
+int64_t space_dim(int m, int n, int group) {
+    if (m < 1 || n < 0) return -1;
+    if (group == 0) return binom((int64_t)m + n - 1, n);
+    if (m % group) return -1;
+    const int64_t c = binom((int64_t)(m / group), n);
+    if (c <= 0) return c;
+    __int128 v = c;
+    for (int i = 0; i < n; ++i) v *= group;
+    return v > (__int128)INT64_MAX ? -1 : (int64_t)v;
+}
+
+constexpr int kPlanFlags = SLOS_PLAN_FORWARD_ONLY | SLOS_PLAN_UNBUNCHED | SLOS_PLAN_DUAL_RAIL;
+
+// group size of a plan's flags
+int flags_group(int flags) {
+    return (flags & SLOS_PLAN_DUAL_RAIL) ? 2 : (flags & SLOS_PLAN_UNBUNCHED) ? 1 : 0;
+}
+
+// flags known and consistent with m modes and n photons
+bool space_flags_ok(int m, int n, int flags, std::string* why) {
+    if (flags & ~kPlanFlags) return *why = "unknown flags", false;
+    if ((flags & SLOS_PLAN_UNBUNCHED) && (flags & SLOS_PLAN_DUAL_RAIL))
+        return *why = "SLOS_PLAN_UNBUNCHED and SLOS_PLAN_DUAL_RAIL exclude each other", false;
+    const int G = flags_group(flags);
+    if (G > 1 && m % G) return *why = "dual-rail needs an even number of modes", false;
+    if (G > 0 && n > m / G)
+        return *why = G == 1 ? "unbunched spaces need at most m photons" : "dual-rail needs at most m/2 photons", false;
     return true;
 }
 
@@ -158,7 +200,7 @@ void build_layer(int m, int k, const Counter& Ck, const Counter& Ckm1, int64_t N
                 }
             }
             H.nrm[t] = (float)std::sqrt(f);
-            next_list(L, k, m, Ck.strict);
+            Ck.next(L, k);
         }
     });
     if (want_succ) {
@@ -168,19 +210,21 @@ void build_layer(int m, int k, const Counter& Ck, const Counter& Ckm1, int64_t N
             if (k - 1 > 0) Ckm1.unrank(lo, k - 1, L);
             for (int64_t t = lo; t < hi; ++t) {
                 for (int j = 0; j < m; ++j) {
-                    // insert j into the sorted list (-1 when it leaves an unbunched space)
-                    int q = 0, o = 0;
-                    bool done = false, twice = false;
+                    // insert j into the sorted list (-1 when the result leaves a restricted space)
+                    if (!Ck.admits(L, k - 1, j)) {
+                        H.succ[(size_t)j * Nkm1 + t] = -1;
+                        continue;
+                    }
+                    int o = 0;
+                    bool done = false;
                     for (int p = 0; p < k - 1; ++p) {
-                        if (L[p] == j) twice = true;
                         if (!done && j < L[p]) { T[o++] = j; done = true; }
                         T[o++] = L[p];
-                        ++q;
                     }
                     if (!done) T[o++] = j;
-                    H.succ[(size_t)j * Nkm1 + t] = (Ck.strict && twice) ? -1 : (int32_t)Ck.rank(T, k);
+                    H.succ[(size_t)j * Nkm1 + t] = (int32_t)Ck.rank(T, k);
                 }
-                if (k - 1 > 0) next_list(L, k - 1, m, Ckm1.strict);
+                if (k - 1 > 0) Ckm1.next(L, k - 1);
             }
         });
     }
@@ -229,9 +273,11 @@ extern "C" int64_t slos_fock_rank(int m, int n, const int32_t* occ) {
     return C.rank(L.data(), n);
 }
 
-extern "C" int64_t slos_unbunched_dim(int m, int n) {
-    if (m < 1 || n < 0) return -1;
-    return binom((int64_t)m, n);
+extern "C" int64_t slos_unbunched_dim(int m, int n) { return space_dim(m, n, 1); }
+
+extern "C" int64_t slos_space_dim(int m, int n, int flags) {
+    if (flags & ~kPlanFlags || (flags & SLOS_PLAN_UNBUNCHED && flags & SLOS_PLAN_DUAL_RAIL)) return -1;
+    return space_dim(m, n, flags_group(flags));
 }
 
 extern "C" int slos_transition_tables(int m, int k, int32_t* pred, int32_t* succ, float* nrm, int32_t* minoff) {
@@ -242,15 +288,14 @@ extern "C" int slos_transition_tables_ex(int m, int k, int flags, int32_t* pred,
                                          int32_t* minoff) {
     if (m < 1 || m > kMaxModes) return fail(SLOS_EINVAL, "slos_transition_tables: m must be in [1, 32]");
     if (k < 1 || k > kMaxPhotons) return fail(SLOS_EINVAL, "slos_transition_tables: k must be in [1, 16]");
-    if (flags & ~(SLOS_PLAN_FORWARD_ONLY | SLOS_PLAN_UNBUNCHED))
-        return fail(SLOS_EINVAL, "slos_transition_tables: unknown flags");
-    const bool strict = (flags & SLOS_PLAN_UNBUNCHED) != 0;
-    if (strict && k > m) return fail(SLOS_EINVAL, "slos_transition_tables: unbunched layers need k <= m");
-    const int64_t Nk = strict ? slos_unbunched_dim(m, k) : slos_fock_dim(m, k);
-    const int64_t Nkm1 = strict ? slos_unbunched_dim(m, k - 1) : slos_fock_dim(m, k - 1);
+    std::string why;
+    if (!space_flags_ok(m, k, flags, &why)) return fail(SLOS_EINVAL, "slos_transition_tables: " + why);
+    const int group = flags_group(flags);
+    const int64_t Nk = space_dim(m, k, group);
+    const int64_t Nkm1 = space_dim(m, k - 1, group);
     if (Nk < 0 || Nk >= ((int64_t)1 << (31 - kModeBits)))
         return fail(SLOS_EUNSUPPORTED, "slos_transition_tables: layer too large for 32-bit tables");
-    Counter Ck(m, k, strict), Ckm1(m, k - 1, strict);
+    Counter Ck(m, k, group), Ckm1(m, k - 1, group);
     HostLayer H;
     build_layer(m, k, Ck, Ckm1, Nk, Nkm1, succ != nullptr, H);
     if (pred) std::memcpy(pred, H.pred.data(), H.pred.size() * 4);
@@ -265,14 +310,12 @@ extern "C" int slos_plan_create(int m, int n_max, int flags, slos_plan_t* out) {
     *out = nullptr;
     if (m < 1 || m > kMaxModes) return fail(SLOS_EINVAL, "slos_plan_create: m must be in [1, 32]");
     if (n_max < 1 || n_max > kMaxPhotons) return fail(SLOS_EINVAL, "slos_plan_create: n_max must be in [1, 16]");
-    if (flags & ~(SLOS_PLAN_FORWARD_ONLY | SLOS_PLAN_UNBUNCHED))
-        return fail(SLOS_EINVAL, "slos_plan_create: unknown flags");
-    const bool strict = (flags & SLOS_PLAN_UNBUNCHED) != 0;
-    if (strict && n_max > m) return fail(SLOS_EINVAL, "slos_plan_create: unbunched plans need n_max <= m");
-    const int64_t Ntop = strict ? slos_unbunched_dim(m, n_max) : slos_fock_dim(m, n_max);
+    std::string why;
+    if (!space_flags_ok(m, n_max, flags, &why)) return fail(SLOS_EINVAL, "slos_plan_create: " + why);
+    const int group = flags_group(flags);
+    const int64_t Ntop = space_dim(m, n_max, group);
     // successor byte offsets (rank * 8) must fit 32 bits, predecessor ranks the wide entry
-    if (Ntop < 0 || Ntop >= ((int64_t)1 << 29) ||
-        (strict ? slos_unbunched_dim(m, n_max - 1) : slos_fock_dim(m, n_max - 1)) >= kPredWideStates)
+    if (Ntop < 0 || Ntop >= ((int64_t)1 << 29) || space_dim(m, n_max - 1, group) >= kPredWideStates)
         return fail(SLOS_EUNSUPPORTED, "slos_plan_create: Fock space too large for 32-bit tables");
 
     auto* P = new slos_plan_s();
@@ -280,7 +323,7 @@ extern "C" int slos_plan_create(int m, int n_max, int flags, slos_plan_t* out) {
     P->n_max = n_max;
     P->flags = flags;
     P->N.resize(n_max + 1);
-    for (int k = 0; k <= n_max; ++k) P->N[k] = strict ? slos_unbunched_dim(m, k) : slos_fock_dim(m, k);
+    for (int k = 0; k <= n_max; ++k) P->N[k] = space_dim(m, k, group);
 
     if (hipGetDevice(&P->device) != hipSuccess) {
         delete P;
@@ -292,13 +335,13 @@ extern "C" int slos_plan_create(int m, int n_max, int flags, slos_plan_t* out) {
     P->num_cu = cu;
     P->max_lds = (size_t)lds;
 
-    // the unbunched space has no successor tables (t' + e_j can leave it): forward only
-    const bool want_succ = !(flags & (SLOS_PLAN_FORWARD_ONLY | SLOS_PLAN_UNBUNCHED));
+    // restricted spaces have no adjoint (t' + e_j can leave them): forward only
+    const bool want_succ = !(flags & SLOS_PLAN_FORWARD_ONLY) && group == 0;
     std::vector<HostLayer> H(n_max + 1);
     std::vector<int> shifts(n_max + 1, kPredShiftCompact);
     std::vector<Counter> C;
     C.reserve(n_max + 1);
-    for (int k = 0; k <= n_max; ++k) C.emplace_back(m, k, strict);
+    for (int k = 0; k <= n_max; ++k) C.emplace_back(m, k, group);
     for (int k = 1; k <= n_max; ++k) {
         build_layer(m, k, C[k], C[k - 1], P->N[k], P->N[k - 1], want_succ, H[k]);
         // device layout: groups of four predecessor entries per state, [group][state][4],
@@ -556,8 +599,8 @@ int run(slos_batch_t batch, int op, const float* U, const void* gin, void* out, 
     if (bwd && !gin) return fail(SLOS_EINVAL, nm + ": gradient input is NULL");
     if (bwd && (batch->plan->flags & SLOS_PLAN_FORWARD_ONLY))
         return fail(SLOS_EUNSUPPORTED, nm + ": plan was created forward-only");
-    if (bwd && (batch->plan->flags & SLOS_PLAN_UNBUNCHED))
-        return fail(SLOS_EUNSUPPORTED, nm + ": unbunched plans are forward-only");
+    if (bwd && flags_group(batch->plan->flags) != 0)
+        return fail(SLOS_EUNSUPPORTED, nm + ": unbunched and dual-rail plans are forward-only");
     int v, blk;
     resolve(*batch, op, &v, &blk);
     const bool probs = (op == SLOS_OP_PROBS || op == SLOS_OP_PROBS_BACKWARD);

@@ -20,8 +20,10 @@ class QuantumLayer(nn.Module):
     state.  Trainable parameters: the m(m-1) mesh phases.
 
     computation_space="unbunched" keeps only the output states with at most
-    one photon per mode (C(m, n) of them, in the same relative order); it is
-    forward-only, so it needs torch.no_grad() or a theta without grad."""
+    one photon per mode (C(m, n) of them, in the same relative order);
+    "dual_rail" keeps those with at most one photon per mode pair (2g, 2g+1)
+    (the 2^n logical states when n = m/2).  Both are forward-only, so they
+    need torch.no_grad() or a theta without grad."""
 
     def __init__(self, m: int, input_state: Sequence[int], enc_scale: float = math.pi,
                  measurement: str = "probs", seed: int = 0, computation_space: str = "fock"):
@@ -31,10 +33,12 @@ class QuantumLayer(nn.Module):
             raise ValueError("input_state must have m entries")
         if measurement not in ("probs", "amplitudes"):
             raise ValueError("measurement must be 'probs' or 'amplitudes'")
-        if computation_space not in ("fock", "unbunched"):
-            raise ValueError("computation_space must be 'fock' or 'unbunched'")
+        if computation_space not in ("fock", "unbunched", "dual_rail"):
+            raise ValueError("computation_space must be 'fock', 'unbunched' or 'dual_rail'")
         if computation_space == "unbunched" and int(occ.sum()) > m:
             raise ValueError("the unbunched space needs at most m photons")
+        if computation_space == "dual_rail" and (m % 2 or 2 * int(occ.sum()) > m):
+            raise ValueError("the dual-rail space needs an even m and at most m/2 photons")
         self.m = m
         self.n = int(occ.sum())
         self.occ = occ
@@ -48,13 +52,15 @@ class QuantumLayer(nn.Module):
 
     @property
     def output_size(self) -> int:
-        if self.computation_space == "unbunched":
-            return B.slos_unbunched_dim(self.m, self.n)
-        return B.slos_fock_dim(self.m, self.n)
+        return B.slos_space_dim(self.m, self.n, self._flags())
+
+    def _flags(self) -> int:
+        return B.space_flags(self.computation_space == "unbunched", self.computation_space == "dual_rail")
 
     def _batch(self, nb: int) -> B.Batch:
         if self._plan is None:
-            self._plan = B.Plan(self.m, max(self.n, 1), unbunched=self.computation_space == "unbunched")
+            self._plan = B.Plan(self.m, max(self.n, 1), unbunched=self.computation_space == "unbunched",
+                                dual_rail=self.computation_space == "dual_rail")
         bt = self._batches.get(nb)
         if bt is None:
             bt = B.Batch(self._plan, np.tile(self.occ, (nb, 1)))
@@ -62,8 +68,8 @@ class QuantumLayer(nn.Module):
         return bt
 
     def forward(self, x: torch.Tensor) -> torch.Tensor:
-        if self.computation_space == "unbunched" and torch.is_grad_enabled() and self.theta.requires_grad:
-            raise RuntimeError("the unbunched computation space is forward-only: use torch.no_grad()")
+        if self.computation_space != "fock" and torch.is_grad_enabled() and self.theta.requires_grad:
+            raise RuntimeError("the %s computation space is forward-only: use torch.no_grad()" % self.computation_space)
         U = mesh_to_unitary(self.theta, x.to(torch.float32), self.enc_scale, self.m)
         bt = self._batch(x.shape[0])
         if self.measurement == "probs":

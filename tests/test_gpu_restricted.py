@@ -1,7 +1,8 @@
-"""GPU parity of the unbunched computation space: the HIP kernels on an
-unbunched plan against the FP64 Ryser oracle evaluated on the output states
-with at most one photon per mode, in the Fock basis order restricted to them
-(lexicographic order of the occupied-mode lists).  Inputs may be bunched."""
+"""GPU parity of the restricted computation spaces: the HIP kernels on an
+unbunched plan (at most one photon per mode) or a dual-rail plan (at most one
+photon per mode pair) against the FP64 Ryser oracle evaluated on those output
+states, in the Fock basis order restricted to them (lexicographic order of
+the occupied-mode lists).  Inputs may be any Fock state."""
 import itertools
 import math
 
@@ -147,3 +148,93 @@ def test_unbunched_backward_is_rejected():
     with torch.no_grad():
         p = layer(x)
     assert p.shape == (2, 20)
+
+
+# ------------------------------------------------------------------ dual-rail
+
+def _dual_outputs(m, n):
+    return np.stack([t for t in O.fock_basis(m, n) if int(t.reshape(-1, 2).sum(1).max(initial=0)) <= 1]) \
+        if n > 0 else np.zeros((1, m), dtype=np.int32)
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("amplitudes", [False, True])
+def test_dual_rail_mixed_batch_m12(variant, amplitudes):
+    rng = np.random.default_rng(44)
+    m, B_ = 12, 24
+    U = W.haar_unitaries(rng, B_, m).astype(np.complex64)
+    occ = np.zeros((B_, m), dtype=np.int32)
+    for b in range(B_):
+        n = int(rng.integers(1, 7))
+        if b % 3 == 0:
+            np.add.at(occ[b], rng.choice(m, size=n, replace=True), 1)  # any Fock input
+        else:
+            qubits = rng.choice(m // 2, size=n, replace=False)
+            occ[b, 2 * qubits + rng.integers(0, 2, size=n)] = 1  # logical-style input
+    say("dual-rail m12 variant", variant, "amplitudes", amplitudes)
+    batch = B.Batch(B.Plan(m, int(occ.sum(1).max()), dual_rail=True), occ)
+    op = B.OP_AMPLITUDES if amplitudes else B.OP_PROBS
+    batch.set_config(op, variant, 256)
+    out = run_forward(batch, to_dev_c64(U), amplitudes)
+    worst = 0.0
+    for b in range(B_):
+        n = int(occ[b].sum())
+        o0, o1 = batch.offsets[b], batch.offsets[b + 1]
+        outs = _dual_outputs(m, n)
+        assert o1 - o0 == len(outs) == math.comb(m // 2, n) * 2 ** n
+        ref = (O.amplitudes if amplitudes else O.probabilities)(widen(U[b]), occ[b], outputs=outs)
+        worst = max(worst, float(np.abs(out[o0:o1] - ref).max()))
+    assert worst <= (A_TOL if amplitudes else P_TOL), worst
+
+
+def test_dual_rail_logical_states_m8_q4():
+    # |0000> in, the 16 logical outputs |q0 q1 q2 q3> in big-endian order
+    m, q = 8, 4
+    rng = np.random.default_rng(8)
+    U = W.haar_unitaries(rng, 6, m).astype(np.complex64)
+    occ = np.tile(np.array([1, 0] * q, dtype=np.int32), (6, 1))
+    batch = B.Batch(B.Plan(m, q, dual_rail=True), occ)
+    a = run_forward(batch, to_dev_c64(U), True).reshape(6, 16)
+    outs = np.zeros((16, m), dtype=np.int32)
+    for idx in range(16):
+        for g in range(q):
+            outs[idx, 2 * g + ((idx >> (q - 1 - g)) & 1)] = 1
+    for b in range(6):
+        ref = O.amplitudes(widen(U[b]), occ[b], outputs=outs)
+        assert np.abs(a[b] - ref).max() <= A_TOL
+
+
+def test_dual_rail_m24_q12_sampled():
+    # 12 qubits on 24 modes: 4096 logical outputs; layer 11 (24576 states) exceeds LDS
+    m, q = 24, 12
+    rng = np.random.default_rng(21)
+    U = W.haar_unitaries(rng, 4, m).astype(np.complex64)
+    occ = np.zeros((4, m), dtype=np.int32)
+    for b in range(4):
+        occ[b, 2 * np.arange(q) + rng.integers(0, 2, size=q)] = 1
+    say("dual-rail m24 q12")
+    batch = B.Batch(B.Plan(m, q, dual_rail=True), occ)
+    assert batch.get_config(B.OP_PROBS)[0] == B.VARIANT_LAYERED
+    p = run_forward(batch, to_dev_c64(U), False).reshape(4, 4096)
+    for b in range(4):
+        idx = np.unique(np.r_[0, 4095, rng.integers(0, 4096, 120), np.argsort(p[b])[-10:]])
+        outs = np.zeros((idx.size, m), dtype=np.int32)
+        for i, r in enumerate(idx):
+            for g in range(q):
+                outs[i, 2 * g + ((int(r) >> (q - 1 - g)) & 1)] = 1
+        ref = O.probabilities(widen(U[b]), occ[b], outputs=outs)
+        assert np.abs(p[b, idx] - ref).max() <= P_TOL
+
+
+def test_dual_rail_is_the_fock_subvector_and_forward_only():
+    m, n = 10, 3
+    rng = np.random.default_rng(13)
+    U, occ = _batch(rng, 12, m, n, n, True)
+    Ud = to_dev_c64(U)
+    bd = B.Batch(B.Plan(m, n, dual_rail=True), occ)
+    pd = run_forward(bd, Ud, False).reshape(12, -1)
+    pf = run_forward(B.Batch(B.Plan(m, n), occ), Ud, False).reshape(12, -1)
+    keep = np.array([int(t.reshape(-1, 2).sum(1).max()) <= 1 for t in O.fock_basis(m, n)])
+    assert np.abs(pd - pf[:, keep]).max() <= 1e-6
+    with pytest.raises(B.SlosError):
+        B.fock_probs_backward(bd, Ud, torch.ones(bd.out_len, dtype=torch.float32, device=DEV))

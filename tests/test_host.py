@@ -150,6 +150,11 @@ def _unbunched_basis(m, k):
     return [t for t in O.fock_basis(m, k) if int(np.max(t, initial=0)) <= 1]
 
 
+def _dual_rail_basis(m, k):
+    # the Fock basis order restricted to states with at most one photon per pair (2g, 2g+1)
+    return [t for t in O.fock_basis(m, k) if int(np.max(t.reshape(-1, 2).sum(1), initial=0)) <= 1]
+
+
 @pytest.mark.parametrize("m,n", [(1, 1), (4, 2), (6, 3), (8, 8), (24, 8), (32, 5)])
 def test_unbunched_dim(m, n):
     assert B.slos_unbunched_dim(m, n) == math.comb(m, n)
@@ -157,12 +162,18 @@ def test_unbunched_dim(m, n):
     assert B.slos_unbunched_dim(0, 1) == -1
 
 
-@pytest.mark.parametrize("m,k", [(4, 1), (5, 2), (6, 3), (7, 4), (5, 5)])
-def test_unbunched_transition_tables_against_enumeration(m, k):
-    pred, succ, nrm, minoff = B.slos_transition_tables(m, k, unbunched=True)
-    layer = _unbunched_basis(m, k)
-    prev = _unbunched_basis(m, k - 1)
-    assert pred.shape == (k, len(layer)) == (k, math.comb(m, k))
+@pytest.mark.parametrize("space,m,k", [("unbunched", 4, 1), ("unbunched", 5, 2), ("unbunched", 6, 3),
+                                        ("unbunched", 7, 4), ("unbunched", 5, 5), ("dual_rail", 4, 1),
+                                        ("dual_rail", 4, 2), ("dual_rail", 6, 2), ("dual_rail", 8, 3),
+                                        ("dual_rail", 10, 5)])
+def test_restricted_transition_tables_against_enumeration(space, m, k):
+    dual = space == "dual_rail"
+    pred, succ, nrm, minoff = B.slos_transition_tables(m, k, unbunched=not dual, dual_rail=dual)
+    basis = _dual_rail_basis if dual else _unbunched_basis
+    layer = basis(m, k)
+    prev = basis(m, k - 1)
+    assert pred.shape == (k, len(layer))
+    assert len(layer) == (math.comb(m // 2, k) * 2 ** k if dual else math.comb(m, k))
     rank = {tuple(int(v) for v in t): r for r, t in enumerate(layer)}
     rank_prev = {tuple(int(v) for v in t): r for r, t in enumerate(prev)}
     for r, t in enumerate(layer):
@@ -183,10 +194,33 @@ def test_unbunched_transition_tables_against_enumeration(m, k):
             tp[j] += 1
             want = rank.get(tuple(int(v) for v in tp), -1)
             assert succ[j, r] == want, (t, j)
-            assert (want == -1) == (t[j] == 1)
     for c in range(m + 1):
         first = next((r for r, t in enumerate(layer) if min(j for j in range(m) if t[j] > 0) >= c), len(layer))
         assert minoff[c] == first
+
+
+@pytest.mark.parametrize("q", [1, 2, 3, 5])
+def test_dual_rail_logical_order(q):
+    # with one photon per pair, state index = the qubit string read big-endian
+    m = 2 * q
+    assert B.slos_space_dim(m, q, B.PLAN_DUAL_RAIL) == 2 ** q
+    layer = _dual_rail_basis(m, q)
+    for idx, t in enumerate(layer):
+        bits = [int(t[2 * g + 1]) for g in range(q)]
+        assert int("".join(map(str, bits)), 2) == idx
+    # and the library's tables agree on the size
+    pred, _, _, _ = B.slos_transition_tables(m, q, want_succ=False, dual_rail=True)
+    assert pred.shape == (q, 2 ** q)
+
+
+def test_space_dim_flags():
+    assert B.slos_space_dim(6, 3) == math.comb(8, 3)
+    assert B.slos_space_dim(6, 3, B.PLAN_UNBUNCHED) == 20
+    assert B.slos_space_dim(6, 3, B.PLAN_DUAL_RAIL) == 8
+    assert B.slos_space_dim(6, 4, B.PLAN_DUAL_RAIL) == 0
+    assert B.slos_space_dim(5, 2, B.PLAN_DUAL_RAIL) == -1  # odd m
+    assert B.slos_space_dim(6, 2, B.PLAN_UNBUNCHED | B.PLAN_DUAL_RAIL) == -1
+    assert B.slos_space_dim(6, 2, 8) == -1
 
 
 def test_unbunched_argument_errors_without_device():
@@ -194,7 +228,10 @@ def test_unbunched_argument_errors_without_device():
     L = B.lib()
     h = ctypes.c_void_p()
     assert L.slos_plan_create(3, 4, B.PLAN_UNBUNCHED, ctypes.byref(h)) == B.SLOS_EINVAL  # n_max > m
-    assert L.slos_plan_create(3, 2, 4, ctypes.byref(h)) == B.SLOS_EINVAL  # unknown flag
+    assert L.slos_plan_create(3, 2, 8, ctypes.byref(h)) == B.SLOS_EINVAL  # unknown flag
+    assert L.slos_plan_create(5, 2, B.PLAN_DUAL_RAIL, ctypes.byref(h)) == B.SLOS_EINVAL  # odd m
+    assert L.slos_plan_create(6, 4, B.PLAN_DUAL_RAIL, ctypes.byref(h)) == B.SLOS_EINVAL  # n_max > m/2
+    assert L.slos_plan_create(6, 2, B.PLAN_DUAL_RAIL | B.PLAN_UNBUNCHED, ctypes.byref(h)) == B.SLOS_EINVAL
     with pytest.raises(B.SlosError):
         B.slos_transition_tables(3, 4, unbunched=True)
 
@@ -205,5 +242,8 @@ def test_quantum_layer_computation_space_arguments():
     assert QuantumLayer(6, [1, 1, 1, 0, 0, 0]).output_size == 56
     with pytest.raises(ValueError):
         QuantumLayer(3, [2, 1, 1], computation_space="unbunched")
+    assert QuantumLayer(6, [1, 0, 1, 0, 1, 0], computation_space="dual_rail").output_size == 8
+    with pytest.raises(ValueError):
+        QuantumLayer(5, [1, 0, 1, 0, 0], computation_space="dual_rail")
     with pytest.raises(ValueError):
         QuantumLayer(3, [1, 1, 0], computation_space="dual")
