@@ -20,6 +20,8 @@ Contents, each following the passage it cites (arXiv 2602.11092):
   Mach-Zehnder interferometers, with the data-encoding layer
   U(x, theta) = W2(theta2) S(x) W1(theta1) of Sec. II-C-1, and its gradient
   by the product rule, in float64 NumPy.
+* Per-mode photon-number expectations <n_j> = sum_t t_j p_t over a set of
+  output states (the measurement strategy of Sec. II-B), by that definition.
 * FP64 replicas of the two losses used by the benchmark workloads.
 """
 from __future__ import annotations
@@ -182,6 +184,20 @@ def amplitudes(U: np.ndarray, s: Sequence[int], outputs: Optional[np.ndarray] = 
 def probabilities(U: np.ndarray, s: Sequence[int], outputs: Optional[np.ndarray] = None) -> np.ndarray:
     """p_t = |a_t|^2 (no renormalisation)."""
     return np.abs(amplitudes(U, s, outputs)) ** 2
+
+
+def mode_expectations(U: np.ndarray, s: Sequence[int], outputs: Optional[np.ndarray] = None) -> np.ndarray:
+    """<n_j> = sum_t t_j p_t over `outputs` (default: the whole basis), the
+    per-mode photon-number expectation of Sec. II-B, no renormalisation."""
+    U = np.ascontiguousarray(U, dtype=np.complex128)
+    m = U.shape[0]
+    n = int(np.sum(s))
+    if outputs is None:
+        outputs = fock_basis(m, n)
+    outputs = np.asarray(outputs, dtype=np.float64).reshape(-1, m)
+    if n == 0:
+        return np.zeros(m)
+    return probabilities(U, s, outputs.astype(np.int32)) @ outputs
 
 
 def amplitude_grad(U: np.ndarray, s: Sequence[int], G_a: np.ndarray,

@@ -408,3 +408,30 @@ def test_readout_cross_entropy_gradient():
     # against the textbook value for uniform logits
     L0, _ = O.readout_cross_entropy(np.zeros((2, N)), np.zeros((C, N)), np.zeros(C), np.array([0, 1]))
     assert abs(L0 - math.log(C)) < 1e-14
+
+
+def test_mode_expectations_closed_form():
+    # full space: <n_j> = sum_i s_i |U_ji|^2 (each photon leaves input mode i
+    # towards j with probability |U_ji|^2), including bunched inputs
+    rng = np.random.default_rng(17)
+    for m, s in [(4, [1, 0, 2, 0]), (5, [1, 1, 1, 0, 0]), (6, [0, 3, 0, 0, 1, 0])]:
+        U = _haar(rng, m)
+        e = O.mode_expectations(U, s)
+        want = np.array([sum(s[i] * abs(U[j, i]) ** 2 for i in range(m)) for j in range(m)])
+        assert np.abs(e - want).max() < 1e-13
+        assert abs(e.sum() - sum(s)) < 1e-12
+    assert np.all(O.mode_expectations(_haar(rng, 3), [0, 0, 0]) == 0)
+
+
+def test_mode_expectations_unbunched_two_photons_by_hand():
+    # two photons in modes 0 and 1 of 3, outputs restricted to t_j <= 1:
+    # p(a, b) = |U_a0 U_b1 + U_a1 U_b0|^2 for output modes a < b
+    rng = np.random.default_rng(18)
+    U = _haar(rng, 3)
+    outs = np.array([[1, 1, 0], [1, 0, 1], [0, 1, 1]], dtype=np.int32)
+    e = O.mode_expectations(U, [1, 1, 0], outputs=outs)
+    pair = {}
+    for a, b in [(0, 1), (0, 2), (1, 2)]:
+        pair[(a, b)] = abs(U[a, 0] * U[b, 1] + U[a, 1] * U[b, 0]) ** 2
+    want = [pair[(0, 1)] + pair[(0, 2)], pair[(0, 1)] + pair[(1, 2)], pair[(0, 2)] + pair[(1, 2)]]
+    assert np.abs(e - want).max() < 1e-14
