@@ -75,6 +75,8 @@ extern "C" {
 #define SLOS_OP_PROBS 1
 #define SLOS_OP_AMPLITUDES_BACKWARD 2
 #define SLOS_OP_PROBS_BACKWARD 3
+#define SLOS_OP_MODE_EXPECTATIONS 4
+#define SLOS_OP_MODE_EXPECTATIONS_BACKWARD 5
 
 /* Plan flags. */
 #define SLOS_PLAN_DEFAULT 0
@@ -217,6 +219,26 @@ SLOS_API int fock_amplitudes_backward(slos_batch_t batch, const float* U, const 
  * (device, float, [out_len]). */
 SLOS_API int fock_probs_backward(slos_batch_t batch, const float* U, const float* grad_probs,
                         float* grad_U, void* ws, size_t ws_bytes, void* stream);
+
+/* ---- Measurement: per-mode photon-number expectations (Sec. II-B) ------- */
+
+/* out (device, float, [B][m], sample order) <- <n_j> = sum_t t_j p_t over the
+ * plan's output states (no renormalisation; for the full Fock space this
+ * equals sum_i s_i |U[j][i]|^2).  The fused variant accumulates inside the
+ * last photon layer and never writes p; the layered one writes p into the
+ * workspace first.  ws: slos_workspace_bytes(batch, SLOS_OP_MODE_EXPECTATIONS)
+ * bytes (the layered variant needs out_len * 4 bytes more than fock_probs).
+ * Works on restricted plans (SLOS_PLAN_UNBUNCHED, SLOS_PLAN_DUAL_RAIL). */
+SLOS_API int fock_mode_expectations(slos_batch_t batch, const float* U, float* out,
+                                    void* ws, size_t ws_bytes, void* stream);
+
+/* grad_U (device, complex, [B][m][m]) <- dL/dU given grad_out = dL/d<n_j>
+ * (device, float, [B][m]).  Forms dL/dp_t = sum_j t_j grad_out[b][j] in the
+ * workspace (out_len floats) and runs the probability adjoint with the
+ * configuration set for SLOS_OP_MODE_EXPECTATIONS_BACKWARD.  Full-space
+ * plans with successor tables only (SLOS_EUNSUPPORTED otherwise). */
+SLOS_API int fock_mode_expectations_backward(slos_batch_t batch, const float* U, const float* grad_out,
+                                             float* grad_U, void* ws, size_t ws_bytes, void* stream);
 
 /* ---- Interferometer mesh U(x, theta) (Sec. II-A-3, Sec. II-C-1) ---------- */
 /*

@@ -28,6 +28,8 @@ OP_AMPLITUDES = 0
 OP_PROBS = 1
 OP_AMPLITUDES_BACKWARD = 2
 OP_PROBS_BACKWARD = 3
+OP_MODE_EXPECTATIONS = 4
+OP_MODE_EXPECTATIONS_BACKWARD = 5
 
 PLAN_DEFAULT = 0
 PLAN_FORWARD_ONLY = 1
@@ -63,6 +65,8 @@ SIGNATURES = {
     "fock_probs": (_c.c_int, [_vp, _vp, _vp, _vp, _c.c_size_t, _vp]),
     "fock_amplitudes_backward": (_c.c_int, [_vp, _vp, _vp, _vp, _vp, _c.c_size_t, _vp]),
     "fock_probs_backward": (_c.c_int, [_vp, _vp, _vp, _vp, _vp, _c.c_size_t, _vp]),
+    "fock_mode_expectations": (_c.c_int, [_vp, _vp, _vp, _vp, _c.c_size_t, _vp]),
+    "fock_mode_expectations_backward": (_c.c_int, [_vp, _vp, _vp, _vp, _vp, _c.c_size_t, _vp]),
     "mesh_workspace_bytes": (_c.c_int, [_c.c_int, _c.c_int, _c.POINTER(_c.c_size_t)]),
     "mesh_to_unitary": (_c.c_int, [_c.c_int, _c.c_int, _vp, _vp, _c.c_float, _vp, _vp, _c.c_size_t, _vp]),
     "mesh_to_unitary_backward": (_c.c_int, [_c.c_int, _c.c_int, _vp, _vp, _c.c_float, _vp, _vp, _vp, _vp,
@@ -308,6 +312,38 @@ def fock_probs_backward(batch: Batch, U: torch.Tensor, grad_probs: torch.Tensor,
     _check("fock_probs_backward",
            lib().fock_probs_backward(batch.handle, _ptr(U), _ptr(grad_probs), _ptr(out), wp, wn,
                                      _stream_ptr(U.device)))
+    return out
+
+
+def fock_mode_expectations(batch: Batch, U: torch.Tensor, out: Optional[torch.Tensor] = None,
+                           ws: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Per-mode photon-number expectations <n_j> = sum_t t_j p_t, float32 [B, m]."""
+    _require(U, "U", torch.complex64, (batch.B, batch.m, batch.m))
+    if out is None:
+        out = torch.empty((batch.B, batch.m), dtype=torch.float32, device=U.device)
+    _require(out, "out", torch.float32, (batch.B, batch.m))
+    if ws is None:
+        ws = batch.workspace(OP_MODE_EXPECTATIONS, U.device)
+    wp, wn = _ws_args(ws)
+    _check("fock_mode_expectations",
+           lib().fock_mode_expectations(batch.handle, _ptr(U), _ptr(out), wp, wn, _stream_ptr(U.device)))
+    return out
+
+
+def fock_mode_expectations_backward(batch: Batch, U: torch.Tensor, grad_out: torch.Tensor,
+                                    out: Optional[torch.Tensor] = None,
+                                    ws: Optional[torch.Tensor] = None) -> torch.Tensor:
+    _require(U, "U", torch.complex64, (batch.B, batch.m, batch.m))
+    _require(grad_out, "grad_out", torch.float32, (batch.B, batch.m))
+    if out is None:
+        out = torch.empty_like(U)
+    _require(out, "grad_U", torch.complex64, (batch.B, batch.m, batch.m))
+    if ws is None:
+        ws = batch.workspace(OP_MODE_EXPECTATIONS_BACKWARD, U.device)
+    wp, wn = _ws_args(ws)
+    _check("fock_mode_expectations_backward",
+           lib().fock_mode_expectations_backward(batch.handle, _ptr(U), _ptr(grad_out), _ptr(out), wp, wn,
+                                                 _stream_ptr(U.device)))
     return out
 
 

@@ -46,6 +46,23 @@ class FockAmplitudes(torch.autograd.Function):
         return gU, None
 
 
+class FockModeExpectations(torch.autograd.Function):
+    """U [B, m, m] complex64 -> per-mode photon-number expectations float32 [B, m]."""
+
+    @staticmethod
+    def forward(ctx, U: torch.Tensor, batch: B.Batch):
+        U = U.contiguous()
+        ctx.batch = batch
+        ctx.save_for_backward(U)
+        return B.fock_mode_expectations(batch, U)
+
+    @staticmethod
+    def backward(ctx, grad_e):
+        (U,) = ctx.saved_tensors
+        gU = B.fock_mode_expectations_backward(ctx.batch, U, grad_e.contiguous().to(torch.float32))
+        return gU, None
+
+
 class MeshToUnitary(torch.autograd.Function):
     """theta [m(m-1)] float32 and features x [B, m] float32 (or None) ->
     U [B, m, m] complex64."""
@@ -77,6 +94,10 @@ def fock_probs(U: torch.Tensor, batch: B.Batch) -> torch.Tensor:
 
 def fock_amplitudes(U: torch.Tensor, batch: B.Batch) -> torch.Tensor:
     return FockAmplitudes.apply(U, batch)
+
+
+def fock_mode_expectations(U: torch.Tensor, batch: B.Batch) -> torch.Tensor:
+    return FockModeExpectations.apply(U, batch)
 
 
 def mesh_to_unitary(theta: torch.Tensor, x: Optional[torch.Tensor], enc_scale: float = math.pi,

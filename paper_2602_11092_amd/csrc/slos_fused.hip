@@ -204,12 +204,52 @@ __device__ __forceinline__ LayerDev layer(const LayerDev* Ls, int k) {
 
 // ------------------------------------------------------------------ forward
 
-template <int BLOCK, bool PROBS>
+// Adds pv[u] to the accumulator of each photon's mode of state t0 + u*BLOCK
+// (lane tid's column of the [m][BLOCK] float array at accb).  The state's
+// photons come from its predecessor entries: an empty entry repeats the
+// previous slot's mode.  The group loads of all SU states are issued
+// together.  The lane's own column needs no atomics (LDS float atomics are
+// several times slower here than a read and a write).
+template <int BLOCK, int SU>
+__device__ __forceinline__ void photons_into_lds(const LayerDev& L, int k, int t0, int N, const float (&pv)[SU],
+                                                 uint32_t accb) {
+    const uint32_t gstride = (uint32_t)N * 16u;
+    const __amdgpu_buffer_rsrc_t r = buf_rsrc(L.predv, (uint32_t)L.ngrp * gstride);
+    const uint32_t col = accb + 4u * threadIdx.x;
+    int cur[SU];
+#pragma unroll
+    for (int u = 0; u < SU; ++u) cur[u] = 0;
+    for (int g = 0; g < L.ngrp; ++g) {
+        uint4 e[SU];
+#pragma unroll
+        for (int u = 0; u < SU; ++u) e[u] = buf_ld4(r, (uint32_t)min(t0 + u * BLOCK, N - 1) * 16u, (uint32_t)g * gstride);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (4 * g + q >= k) break;
+#pragma unroll
+            for (int u = 0; u < SU; ++u) {
+                const int md = (int)(comp(e[u], q) >> L.pred_shift);
+                cur[u] = md == 32 ? cur[u] : md;
+                const uint32_t a = col + 4u * (uint32_t)(cur[u] * BLOCK);
+                lds_stf(a, lds_ldf(a) + pv[u]);
+            }
+        }
+    }
+}
+
+// EPI 0: amplitudes, 1: probabilities (both [out_len]); 2: per-mode photon
+// expectations, out[b][j] = sum_t t_j p_t ([B][m]): p_t is added to a
+// per-lane LDS accumulator for each photon's mode (lane tid owns column tid
+// of the [m][BLOCK] array after the state buffers, so no atomics), and the
+// columns are summed once per sample; p is never written.
+template <int BLOCK, int EPI>
 __global__ __launch_bounds__(BLOCK) void fused_fwd_kernel(int m, const LayerDev* __restrict__ Ls, BatchDev Bt,
                                                           const float2* __restrict__ U, void* __restrict__ out,
                                                           int S) {
-    extern __shared__ float2 lds[];  // ucol at kUcolAddr, photon layers from kXAddr
+    constexpr bool PROBS = EPI >= 1;
+    extern __shared__ float2 lds[];  // ucol at kUcolAddr, photon layers from kXAddr, accumulators after them
     const int tid = threadIdx.x;
+    const uint32_t accb = kXAddr + 8u * (uint32_t)S;
     if (tid < kUcolSlots) lds_st(kUcolAddr + 8 * tid, c_zero());  // slots m..32 stay zero
     for (int item = blockIdx.x; item < Bt.B; item += gridDim.x) {
         const int b = ldc(Bt.order + item);
@@ -219,12 +259,16 @@ __global__ __launch_bounds__(BLOCK) void fused_fwd_kernel(int m, const LayerDev*
         const float2* Ub = U + (size_t)b * m * m;
         const int32_t* modes = Bt.modes + (size_t)b * kMaxPhotons;  // read through ldg
         if (n == 0) {
-            if (tid == 0) {
+            if (EPI == 2) {
+                if (tid < m) ((float*)out)[(size_t)b * m + tid] = 0.f;  // the vacuum has no photons
+            } else if (tid == 0) {
                 if (PROBS) ((float*)out)[off] = 1.f;
                 else ((float2*)out)[off] = make_float2(1.f, 0.f);
             }
             continue;
         }
+        if (EPI == 2)
+            for (int j = 0; j < m; ++j) lds_stf(accb + 4u * (uint32_t)(j * BLOCK + tid), 0.f);
         for (int k = 1; k <= n; ++k) {
             if (tid < m) lds_st(kUcolAddr + 8 * tid, Ub[tid * m + ldc(modes + (k - 1))]);
             __syncthreads();
@@ -240,7 +284,7 @@ __global__ __launch_bounds__(BLOCK) void fused_fwd_kernel(int m, const LayerDev*
                 const __amdgpu_buffer_rsrc_t rn = buf_rsrc(L.nrm, (uint32_t)N * 4u);
                 const __amdgpu_buffer_rsrc_t ro =
                     buf_rsrc(PROBS ? (const void*)((float*)out + off) : (const void*)((float2*)out + off),
-                             (uint32_t)N * (PROBS ? 4u : 8u));
+                             EPI == 2 ? 0u : (uint32_t)N * (PROBS ? 4u : 8u));
                 for (int t0 = tid; t0 < N; t0 += BLOCK * kLU) {
                     float c[kLU];
 #pragma unroll
@@ -251,7 +295,7 @@ __global__ __launch_bounds__(BLOCK) void fused_fwd_kernel(int m, const LayerDev*
 #pragma unroll
                     for (int u = 0; u < kLU; ++u) {
                         const int t = t0 + u * BLOCK;
-                        if (t < N) {
+                        if (EPI != 2 && t < N) {
                             if (PROBS) {
                                 const float p = c[u] * c[u] * (acc[u].x * acc[u].x + acc[u].y * acc[u].y);
                                 __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(p), ro, t * 4, 0, kCpolStream);
@@ -262,9 +306,27 @@ __global__ __launch_bounds__(BLOCK) void fused_fwd_kernel(int m, const LayerDev*
                             }
                         }
                     }
+                    if (EPI == 2) {
+                        float pv[kLU];
+#pragma unroll
+                        for (int u = 0; u < kLU; ++u)  // lanes past N add zero
+                            pv[u] = t0 + u * BLOCK < N ? c[u] * c[u] * (acc[u].x * acc[u].x + acc[u].y * acc[u].y) : 0.f;
+                        photons_into_lds<BLOCK, kLU>(L, k, t0, N, pv, accb);
+                    }
                 }
             }
             __syncthreads();
+        }
+        if (EPI == 2) {
+            // column sums: wave w takes modes w, w + BLOCK/64, ...; fixed order
+            const int w = tid >> 6, lane = tid & 63;
+            for (int j = w; j < m; j += BLOCK / 64) {
+                float v = 0.f;
+                for (int i = lane; i < BLOCK; i += 64) v += lds_ldf(accb + 4u * (uint32_t)(j * BLOCK + i));
+                v = wave_sum63(v);
+                if (lane == 63) ((float*)out)[(size_t)b * m + j] = v;
+            }
+            __syncthreads();  // before the next sample clears the accumulators
         }
     }
 }
@@ -671,16 +733,26 @@ bool compact_tables(const slos_plan_s& P, int n_max) {
     return true;
 }
 
-template <int BLOCK, bool PROBS>
-void* fwd_fn() { return (void*)&fused_fwd_kernel<BLOCK, PROBS>; }
+template <int BLOCK>
+void* fwd_fn(int epi) {
+    return epi == 0 ? (void*)&fused_fwd_kernel<BLOCK, 0>
+                    : epi == 1 ? (void*)&fused_fwd_kernel<BLOCK, 1> : (void*)&fused_fwd_kernel<BLOCK, 2>;
+}
 
-void* pick_fwd(int block, bool probs) {
+void* pick_fwd(int block, int epi) {
     switch (block) {
-        case 256: return probs ? fwd_fn<256, true>() : fwd_fn<256, false>();
-        case 512: return probs ? fwd_fn<512, true>() : fwd_fn<512, false>();
-        case 1024: return probs ? fwd_fn<1024, true>() : fwd_fn<1024, false>();
+        case 256: return fwd_fn<256>(epi);
+        case 512: return fwd_fn<512>(epi);
+        case 1024: return fwd_fn<1024>(epi);
         default: return nullptr;
     }
+}
+
+// LDS bytes of the fused forward: the coefficient column, the state
+// buffers and, for the expectation epilogue, [m][block] float accumulators
+size_t fwd_lds_for(const slos_plan_s& P, int n_max, int block, bool expect) {
+    return (size_t)(lds_fwd_states(P, n_max) + kUcolSlots) * sizeof(float2) +
+           (expect ? (size_t)P.m * block * sizeof(float) : 0);
 }
 
 int mmax_for(int m) { return m <= 8 ? 8 : m <= 12 ? 12 : m <= 16 ? 16 : m <= 20 ? 20 : m <= 24 ? 24 : 32; }
@@ -748,12 +820,12 @@ size_t fused_fwd_lds_bytes(const slos_plan_s& P, int n_max) {
 
 size_t fused_bwd_lds_bytes(const slos_plan_s& P, int n_max) { return bwd_lds_for_block(P, n_max, 512); }
 
-bool fused_fwd_supported(const slos_plan_s& P, int n_max, int block, std::string* why) {
+bool fused_fwd_supported(const slos_plan_s& P, int n_max, int block, std::string* why, bool expect) {
     if (block != 256 && block != 512 && block != 1024) {
         if (why) *why = "block must be 256, 512 or 1024";
         return false;
     }
-    if (fused_fwd_lds_bytes(P, n_max) > P.max_lds) {
+    if (fwd_lds_for(P, n_max, block, expect) > P.max_lds) {
         if (why) *why = "photon layers do not fit in LDS";
         return false;
     }
@@ -801,13 +873,14 @@ int fused_default_block(const slos_plan_s& P, int n_max, bool backward) {
     return Nbig >= 8192 ? 1024 : 256;
 }
 
-int launch_fused_fwd(const slos_batch_s& Bt, int block, const float2* U, void* out, bool probs,
+int launch_fused_fwd(const slos_batch_s& Bt, int block, const float2* U, void* out, int epi,
                      hipStream_t stream) {
     const slos_plan_s& P = *Bt.plan;
     std::string why;
-    if (!fused_fwd_supported(P, Bt.n_max, block, &why)) return fail(SLOS_EUNSUPPORTED, "fused forward: " + why);
-    void* fn = pick_fwd(block, probs);
-    const size_t lds = fused_fwd_lds_bytes(P, Bt.n_max);
+    if (!fused_fwd_supported(P, Bt.n_max, block, &why, epi == 2))
+        return fail(SLOS_EUNSUPPORTED, "fused forward: " + why);
+    void* fn = pick_fwd(block, epi);
+    const size_t lds = fwd_lds_for(P, Bt.n_max, block, epi == 2);
     hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     const int grid = grid_for(P, fn, block, lds, Bt.B);
     const int S = (int)lds_fwd_states(P, Bt.n_max);

@@ -522,8 +522,25 @@ extern "C" int slos_batch_out_offsets(slos_batch_t batch, int64_t* off_host) {
 
 namespace {
 
-bool op_valid(int op) { return op >= SLOS_OP_AMPLITUDES && op <= SLOS_OP_PROBS_BACKWARD; }
-bool op_backward(int op) { return op >= SLOS_OP_AMPLITUDES_BACKWARD; }
+bool op_valid(int op) { return op >= SLOS_OP_AMPLITUDES && op <= SLOS_OP_MODE_EXPECTATIONS_BACKWARD; }
+bool op_backward(int op) {
+    return op == SLOS_OP_AMPLITUDES_BACKWARD || op == SLOS_OP_PROBS_BACKWARD || op == SLOS_OP_MODE_EXPECTATIONS_BACKWARD;
+}
+bool op_expect(int op) { return op == SLOS_OP_MODE_EXPECTATIONS || op == SLOS_OP_MODE_EXPECTATIONS_BACKWARD; }
+
+// the expectation ops keep dL/dp or p (out_len floats) at the start of their workspace
+size_t expect_head_bytes(const slos_batch_s& Bt) { return align256((size_t)Bt.off_host[Bt.B] * sizeof(float)); }
+
+// Default fused block size of an op: the expectation epilogue's [m][block]
+// accumulators share LDS with the photon layers, so it steps down to the
+// largest size that fits.
+int fused_block_for(const slos_batch_s& Bt, int op) {
+    const bool bwd = op_backward(op);
+    int blk = fused_default_block(*Bt.plan, Bt.n_max, bwd);
+    if (op == SLOS_OP_MODE_EXPECTATIONS)
+        while (blk > 256 && !fused_fwd_supported(*Bt.plan, Bt.n_max, blk, nullptr, true)) blk /= 2;
+    return blk;
+}
 
 // Resolves AUTO and the default block size for one op.
 int resolve(const slos_batch_s& Bt, int op, int* variant, int* block) {
@@ -532,14 +549,14 @@ int resolve(const slos_batch_s& Bt, int op, int* variant, int* block) {
     Config c = Bt.cfg[op];
     int v = c.variant;
     if (v == SLOS_VARIANT_AUTO) {
-        const int blk = fused_default_block(P, Bt.n_max, bwd);
+        const int blk = fused_block_for(Bt, op);
         const bool ok = bwd ? fused_bwd_supported(P, Bt.n_max, blk, nullptr)
-                            : fused_fwd_supported(P, Bt.n_max, blk, nullptr);
+                            : fused_fwd_supported(P, Bt.n_max, blk, nullptr, op_expect(op));
         v = ok ? SLOS_VARIANT_FUSED : SLOS_VARIANT_LAYERED;
     }
     int blk = c.block;
     if (blk == 0)
-        blk = (v == SLOS_VARIANT_FUSED) ? fused_default_block(P, Bt.n_max, bwd) : layered_default_block(Bt);
+        blk = (v == SLOS_VARIANT_FUSED) ? fused_block_for(Bt, op) : layered_default_block(Bt);
     *variant = v;
     *block = blk;
     return SLOS_OK;
@@ -553,6 +570,11 @@ extern "C" int slos_workspace_bytes(slos_batch_t batch, int op, size_t* bytes) {
     int v, blk;
     resolve(*batch, op, &v, &blk);
     *bytes = (v == SLOS_VARIANT_FUSED) ? 0 : layered_ws_bytes(*batch, op_backward(op));
+    // the expectation forward keeps p and partial sums in the workspace only
+    // when layered; the backward always keeps dL/dp
+    if (op == SLOS_OP_MODE_EXPECTATIONS_BACKWARD) *bytes += expect_head_bytes(*batch);
+    if (op == SLOS_OP_MODE_EXPECTATIONS && v != SLOS_VARIANT_FUSED)
+        *bytes += expect_head_bytes(*batch) + align256(mode_expect_part_bytes(*batch));
     return SLOS_OK;
 }
 
@@ -568,9 +590,9 @@ extern "C" int slos_batch_set_config(slos_batch_t batch, int op, int variant, in
         return fail(SLOS_EUNSUPPORTED, "slos_batch_set_config: 768 is a fused-adjoint workgroup size only");
     if (variant == SLOS_VARIANT_FUSED) {
         std::string why;
-        const int blk = block ? block : fused_default_block(*batch->plan, batch->n_max, bwd);
+        const int blk = block ? block : fused_block_for(*batch, op);
         const bool ok = bwd ? fused_bwd_supported(*batch->plan, batch->n_max, blk, &why)
-                            : fused_fwd_supported(*batch->plan, batch->n_max, blk, &why);
+                            : fused_fwd_supported(*batch->plan, batch->n_max, blk, &why, op_expect(op));
         if (!ok) return fail(SLOS_EUNSUPPORTED, "slos_batch_set_config: fused variant unavailable: " + why);
     }
     batch->cfg[op].variant = variant;
@@ -586,10 +608,40 @@ extern "C" int slos_batch_get_config(slos_batch_t batch, int op, int* variant, i
 
 namespace {
 
+// Per-mode expectations and their adjoint: the fused forward accumulates in
+// its last-layer epilogue; the layered forward writes p into the workspace
+// and reduces it; the adjoint expands dL/d<n_j> into dL/dp in the workspace
+// and runs the probability adjoint on it.
+int run_expect(const slos_batch_s& Bt, int op, int v, int blk, const float* U, const void* gin, void* out,
+               void* ws, size_t ws_bytes, hipStream_t s, const std::string& nm) {
+    const bool bwd = op == SLOS_OP_MODE_EXPECTATIONS_BACKWARD;
+    const bool fused = v == SLOS_VARIANT_FUSED;
+    if (!bwd && fused) return launch_fused_fwd(Bt, blk, (const float2*)U, out, 2, s);
+    // workspace: [p or dL/dp][partial sums (forward)][layered workspace]
+    const size_t head = expect_head_bytes(Bt);
+    const size_t parts = bwd ? 0 : align256(mode_expect_part_bytes(Bt));
+    const size_t need = head + parts + (fused ? 0 : layered_ws_bytes(Bt, bwd));
+    if (!ws || ws_bytes < need)
+        return fail(SLOS_EWORKSPACE, nm + ": workspace missing or too small (need " + std::to_string(need) + " bytes)");
+    float* pv = (float*)ws;
+    void* rest = (char*)ws + head + parts;
+    int rc;
+    if (!bwd) {
+        rc = launch_layered_fwd(Bt, blk, (const float2*)U, pv, true, rest, s);
+        if (rc == SLOS_OK) rc = launch_mode_expect(Bt, pv, (float*)((char*)ws + head), (float*)out, s);
+        return rc;
+    }
+    rc = launch_expand_mode_weights(Bt, (const float*)gin, pv, s);
+    if (rc != SLOS_OK) return rc;
+    return fused ? launch_fused_bwd(Bt, blk, (const float2*)U, pv, true, (float2*)out, s)
+                 : launch_layered_bwd(Bt, blk, (const float2*)U, pv, true, (float2*)out, rest, s);
+}
+
 int run(slos_batch_t batch, int op, const float* U, const void* gin, void* out, void* ws, size_t ws_bytes,
         void* stream) {
-    static const char* names[4] = {"fock_amplitudes", "fock_probs", "fock_amplitudes_backward",
-                                   "fock_probs_backward"};
+    static const char* names[6] = {"fock_amplitudes", "fock_probs", "fock_amplitudes_backward",
+                                   "fock_probs_backward", "fock_mode_expectations",
+                                   "fock_mode_expectations_backward"};
     const std::string nm = names[op];
     if (!batch) return fail(SLOS_EINVAL, nm + ": batch is NULL");
     if (batch->B == 0) return SLOS_OK;
@@ -605,10 +657,11 @@ int run(slos_batch_t batch, int op, const float* U, const void* gin, void* out, 
     resolve(*batch, op, &v, &blk);
     const bool probs = (op == SLOS_OP_PROBS || op == SLOS_OP_PROBS_BACKWARD);
     hipStream_t s = (hipStream_t)stream;
+    if (op_expect(op)) return run_expect(*batch, op, v, blk, U, gin, out, ws, ws_bytes, s, nm);
     int rc;
     if (v == SLOS_VARIANT_FUSED) {
         rc = bwd ? launch_fused_bwd(*batch, blk, (const float2*)U, gin, probs, (float2*)out, s)
-                 : launch_fused_fwd(*batch, blk, (const float2*)U, out, probs, s);
+                 : launch_fused_fwd(*batch, blk, (const float2*)U, out, probs ? 1 : 0, s);
     } else {
         const size_t need = layered_ws_bytes(*batch, bwd);
         if (need > 0 && (!ws || ws_bytes < need))
@@ -640,4 +693,14 @@ extern "C" int fock_amplitudes_backward(slos_batch_t batch, const float* U, cons
 extern "C" int fock_probs_backward(slos_batch_t batch, const float* U, const float* grad_probs, float* grad_U,
                                    void* ws, size_t ws_bytes, void* stream) {
     return run(batch, SLOS_OP_PROBS_BACKWARD, U, grad_probs, grad_U, ws, ws_bytes, stream);
+}
+
+extern "C" int fock_mode_expectations(slos_batch_t batch, const float* U, float* out, void* ws, size_t ws_bytes,
+                                      void* stream) {
+    return run(batch, SLOS_OP_MODE_EXPECTATIONS, U, nullptr, out, ws, ws_bytes, stream);
+}
+
+extern "C" int fock_mode_expectations_backward(slos_batch_t batch, const float* U, const float* grad_out,
+                                               float* grad_U, void* ws, size_t ws_bytes, void* stream) {
+    return run(batch, SLOS_OP_MODE_EXPECTATIONS_BACKWARD, U, grad_out, grad_U, ws, ws_bytes, stream);
 }

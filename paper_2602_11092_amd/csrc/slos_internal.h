@@ -88,7 +88,7 @@ struct slos_batch_s {
     std::vector<int64_t> off_host;
     void* dmem = nullptr;
     slos::BatchDev dev{};
-    slos::Config cfg[4];
+    slos::Config cfg[6];
 };
 
 namespace slos {
@@ -99,10 +99,12 @@ int fail(int code, const std::string& msg);
 // ---- fused (LDS-resident) kernels: slos_fused.hip ----
 size_t fused_fwd_lds_bytes(const slos_plan_s& P, int n_max);
 size_t fused_bwd_lds_bytes(const slos_plan_s& P, int n_max);
-bool fused_fwd_supported(const slos_plan_s& P, int n_max, int block, std::string* why);
+// expect: the per-mode expectation epilogue (per-lane LDS accumulators)
+bool fused_fwd_supported(const slos_plan_s& P, int n_max, int block, std::string* why, bool expect = false);
 bool fused_bwd_supported(const slos_plan_s& P, int n_max, int block, std::string* why);
 int fused_default_block(const slos_plan_s& P, int n_max, bool backward);
-int launch_fused_fwd(const slos_batch_s& Bt, int block, const float2* U, void* out, bool probs,
+// epi: 0 amplitudes, 1 probabilities, 2 per-mode expectations ([B][m] floats)
+int launch_fused_fwd(const slos_batch_s& Bt, int block, const float2* U, void* out, int epi,
                      hipStream_t stream);
 int launch_fused_bwd(const slos_batch_s& Bt, int block, const float2* U, const void* gin, bool probs,
                      float2* gU, hipStream_t stream);
@@ -114,6 +116,14 @@ int launch_layered_fwd(const slos_batch_s& Bt, int block, const float2* U, void*
                        void* ws, hipStream_t stream);
 int launch_layered_bwd(const slos_batch_s& Bt, int block, const float2* U, const void* gin, bool probs,
                        float2* gU, void* ws, hipStream_t stream);
+
+// ---- measurement kernels: slos_measure.hip ----
+// out[b][j] = sum_t t_j p[off_b + t] (p: the batch's probabilities), via
+// per-chunk partial sums in `part` (mode_expect_part_bytes bytes)
+size_t mode_expect_part_bytes(const slos_batch_s& Bt);
+int launch_mode_expect(const slos_batch_s& Bt, const float* p, float* part, float* out, hipStream_t stream);
+// gp[off_b + t] = sum_j t_j w[b][j]
+int launch_expand_mode_weights(const slos_batch_s& Bt, const float* w, float* gp, hipStream_t stream);
 
 }  // namespace slos
 
@@ -184,4 +194,30 @@ __device__ __forceinline__ float buf_ldf(__amdgpu_buffer_rsrc_t r, uint32_t voff
 constexpr int kCpolStream = 2;
 __device__ __forceinline__ float buf_ldf_stream(__amdgpu_buffer_rsrc_t r, uint32_t voff) {
     return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, 0, kCpolStream));
+}
+
+typedef __attribute__((address_space(3))) float lds_f32;
+__device__ __forceinline__ float lds_ldf(uint32_t a) { return *(const lds_f32*)(size_t)a; }
+__device__ __forceinline__ void lds_stf(uint32_t a, float v) { *(lds_f32*)(size_t)a = v; }
+
+
+// Calls f(mode) once per photon of state t of photon layer L (k photons).
+// The state's predecessor entries list its sorted modes, one slot per
+// photon; an empty entry (mode field 32) repeats the previous slot's mode,
+// and slots past k are padding.  64-bit indexing: any layer size.
+template <class F>
+__device__ __forceinline__ void for_each_photon(const slos::LayerDev& L, int k, int64_t t, F&& f) {
+    int cur = 0;
+    for (int g = 0; g < L.ngrp; ++g) {
+        typedef __attribute__((ext_vector_type(4))) unsigned int u32x4;
+        const u32x4 e = *(__attribute__((address_space(1))) const u32x4*)(L.predv + (int64_t)g * L.N + t);
+        const uint32_t ev[4] = {e.x, e.y, e.z, e.w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (4 * g + q >= k) break;
+            const int md = (int)(ev[q] >> L.pred_shift);
+            if (md != 32) cur = md;
+            f(cur);
+        }
+    }
 }

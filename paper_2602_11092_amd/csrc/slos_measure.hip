@@ -1,0 +1,130 @@
+// Measurement kernels over a batch's output states (Sec. II-B, measurement
+// strategies): per-mode photon-number expectations from probabilities, and
+// the weight expansion of their adjoint.
+//
+//   <n_j>_b      = sum_t t_j p_b[t]     (mode_expect_partial_kernel, then
+//                                         mode_expect_final_kernel)
+//   dL/dp_b[t]   = sum_j t_j dL/d<n_j>_b  (expand_kernel)
+//
+// A state's photons are read from its predecessor entries in the transition
+// table of its photon layer (for_each_photon).  Workgroup b * C + c takes
+// chunk c (kChunkStates states) of sample b, so large samples spread over
+// many workgroups; partial sums are combined in chunk order, so results are
+// deterministic.
+#include "slos_internal.h"
+
+namespace slos {
+namespace {
+
+constexpr int kMeasureBlock = 256;
+constexpr int kParts = kMeasureBlock / kMaxModes;  // partial sums per mode in the final reduction
+constexpr int64_t kChunkStates = (int64_t)kMeasureBlock * 64;  // states per workgroup in the expectation sums
+static_assert(kParts * kMaxModes == kMeasureBlock, "one thread per (mode, part)");
+
+// Stage 1: workgroup (b, c) sums states [c*kChunkStates, (c+1)*kChunkStates)
+// of sample b into part[b][c][j] (zero where the chunk holds no state).
+__global__ __launch_bounds__(kMeasureBlock) void mode_expect_partial_kernel(int m, const LayerDev* __restrict__ Ls,
+                                                                            BatchDev Bt, const float* __restrict__ p,
+                                                                            float* __restrict__ part, int C) {
+    // lane tid owns column tid: acc[j][tid] = sum of p over its states, per photon in mode j
+    __shared__ float acc[kMaxModes][kMeasureBlock];
+    const int tid = threadIdx.x;
+    const int b = blockIdx.x / C, c = blockIdx.x % C;
+    for (int j = 0; j < kMaxModes; ++j) acc[j][tid] = 0.f;
+    const int n = ldg(Bt.n + b);
+    if (n > 0) {
+        const int64_t off = ldg(Bt.off + b);
+        const LayerDev L = Ls[n];
+        const int64_t lo = (int64_t)c * kChunkStates, hi = lo + kChunkStates < L.N ? lo + kChunkStates : L.N;
+        for (int64_t t = lo + tid; t < hi; t += kMeasureBlock) {
+            const float v = p[off + t];
+            for_each_photon(L, n, t, [&](int j) { acc[j][tid] += v; });
+        }
+    }
+    __syncthreads();
+    // thread (j, part) sums a strip of kMeasureBlock / kParts columns, then the parts combine
+    const int j = tid / kParts, q = tid % kParts;
+    constexpr int strip = kMeasureBlock / kParts;
+    float v = 0.f;
+    for (int i = 0; i < strip; ++i) v += acc[j][q * strip + i];
+    for (int s = kParts / 2; s >= 1; s >>= 1) v += __shfl_xor(v, s, kParts);
+    if (q == 0 && j < m) part[((size_t)b * C + c) * m + j] = v;
+}
+
+// Stage 2: out[b][j] = sum_c part[b][c][j], in chunk order.
+__global__ __launch_bounds__(kMeasureBlock) void mode_expect_final_kernel(int m, int B, int C,
+                                                                          const float* __restrict__ part,
+                                                                          float* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * kMeasureBlock + threadIdx.x;
+    if (i >= (int64_t)B * m) return;
+    const int64_t b = i / m, j = i % m;
+    float v = 0.f;
+    for (int c = 0; c < C; ++c) v += part[(b * C + c) * m + j];
+    out[i] = v;
+}
+
+// gp[off_b + t] = sum_j t_j w[b][j] for the states of chunk c of sample b
+// (workgroup b * C + c).
+__global__ __launch_bounds__(kMeasureBlock) void expand_kernel(int m, const LayerDev* __restrict__ Ls, BatchDev Bt,
+                                                               const float* __restrict__ w,
+                                                               float* __restrict__ gp, int C) {
+    __shared__ float wb[kMaxModes];
+    const int tid = threadIdx.x;
+    const int b = blockIdx.x / C, c = blockIdx.x % C;
+    if (tid < m) wb[tid] = w[(size_t)b * m + tid];
+    __syncthreads();
+    const int n = ldg(Bt.n + b);
+    const int64_t off = ldg(Bt.off + b);
+    if (n == 0) {
+        if (c == 0 && tid == 0) gp[off] = 0.f;  // <n_j> does not depend on the vacuum's probability
+        return;
+    }
+    const LayerDev L = Ls[n];
+    const int64_t lo = (int64_t)c * kChunkStates, hi = lo + kChunkStates < L.N ? lo + kChunkStates : L.N;
+    for (int64_t t = lo + tid; t < hi; t += kMeasureBlock) {
+        float g = 0.f;
+        for_each_photon(L, n, t, [&](int j) { g += wb[j]; });
+        gp[off + t] = g;
+    }
+}
+
+}  // namespace
+
+int64_t mode_expect_chunks(const slos_batch_s& Bt) {
+    const int64_t N = Bt.n_max >= 0 ? Bt.plan->N[Bt.n_max] : 1;
+    return std::max<int64_t>(1, (N + kChunkStates - 1) / kChunkStates);
+}
+
+size_t mode_expect_part_bytes(const slos_batch_s& Bt) {
+    return (size_t)Bt.B * mode_expect_chunks(Bt) * Bt.plan->m * sizeof(float);
+}
+
+int launch_mode_expect(const slos_batch_s& Bt, const float* p, float* part, float* out, hipStream_t stream) {
+    const slos_plan_s& P = *Bt.plan;
+    int m = P.m, B = Bt.B;
+    int C = (int)mode_expect_chunks(Bt);
+    if ((int64_t)B * C >= ((int64_t)1 << 31)) return fail(SLOS_EUNSUPPORTED, "mode expectations: batch too large");
+    void* a1[] = {(void*)&m, (void*)&P.d_layers, (void*)&Bt.dev, (void*)&p, (void*)&part, (void*)&C};
+    hipError_t e = hipLaunchKernel((void*)&mode_expect_partial_kernel, dim3((unsigned)(B * C)), dim3(kMeasureBlock),
+                                   a1, 0, stream);
+    if (e != hipSuccess) return fail(SLOS_EHIP, std::string("mode expectation launch: ") + hipGetErrorString(e));
+    void* a2[] = {(void*)&m, (void*)&B, (void*)&C, (void*)&part, (void*)&out};
+    const unsigned g2 = (unsigned)(((int64_t)B * m + kMeasureBlock - 1) / kMeasureBlock);
+    e = hipLaunchKernel((void*)&mode_expect_final_kernel, dim3(g2), dim3(kMeasureBlock), a2, 0, stream);
+    if (e != hipSuccess) return fail(SLOS_EHIP, std::string("mode expectation launch: ") + hipGetErrorString(e));
+    return SLOS_OK;
+}
+
+int launch_expand_mode_weights(const slos_batch_s& Bt, const float* w, float* gp, hipStream_t stream) {
+    const slos_plan_s& P = *Bt.plan;
+    int m = P.m;
+    int C = (int)mode_expect_chunks(Bt);
+    if ((int64_t)Bt.B * C >= ((int64_t)1 << 31)) return fail(SLOS_EUNSUPPORTED, "mode weight expansion: batch too large");
+    void* args[] = {(void*)&m, (void*)&P.d_layers, (void*)&Bt.dev, (void*)&w, (void*)&gp, (void*)&C};
+    hipError_t e = hipLaunchKernel((void*)&expand_kernel, dim3((unsigned)(Bt.B * C)), dim3(kMeasureBlock), args, 0,
+                                   stream);
+    if (e != hipSuccess) return fail(SLOS_EHIP, std::string("mode weight expansion launch: ") + hipGetErrorString(e));
+    return SLOS_OK;
+}
+
+}  // namespace slos

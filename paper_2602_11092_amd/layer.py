@@ -11,13 +11,14 @@ import torch
 from torch import nn
 
 from . import _binding as B
-from .autograd import fock_amplitudes, fock_probs, mesh_to_unitary
+from .autograd import fock_amplitudes, fock_mode_expectations, fock_probs, mesh_to_unitary
 
 
 class QuantumLayer(nn.Module):
     """x [batch, m] float32 -> probabilities [batch, C(m+n-1, n)] (or
-    complex amplitudes with measurement="amplitudes") for one input Fock
-    state.  Trainable parameters: the m(m-1) mesh phases.
+    complex amplitudes with measurement="amplitudes", or the per-mode photon
+    number expectations [batch, m] with measurement="mode_expectations") for
+    one input Fock state.  Trainable parameters: the m(m-1) mesh phases.
 
     computation_space="unbunched" keeps only the output states with at most
     one photon per mode (C(m, n) of them, in the same relative order);
@@ -31,8 +32,8 @@ class QuantumLayer(nn.Module):
         occ = np.asarray(input_state, dtype=np.int32)
         if occ.shape != (m,):
             raise ValueError("input_state must have m entries")
-        if measurement not in ("probs", "amplitudes"):
-            raise ValueError("measurement must be 'probs' or 'amplitudes'")
+        if measurement not in ("probs", "amplitudes", "mode_expectations"):
+            raise ValueError("measurement must be 'probs', 'amplitudes' or 'mode_expectations'")
         if computation_space not in ("fock", "unbunched", "dual_rail"):
             raise ValueError("computation_space must be 'fock', 'unbunched' or 'dual_rail'")
         if computation_space == "unbunched" and int(occ.sum()) > m:
@@ -52,6 +53,8 @@ class QuantumLayer(nn.Module):
 
     @property
     def output_size(self) -> int:
+        if self.measurement == "mode_expectations":
+            return self.m
         return B.slos_space_dim(self.m, self.n, self._flags())
 
     def _flags(self) -> int:
@@ -74,4 +77,6 @@ class QuantumLayer(nn.Module):
         bt = self._batch(x.shape[0])
         if self.measurement == "probs":
             return fock_probs(U, bt).view(x.shape[0], -1)
+        if self.measurement == "mode_expectations":
+            return fock_mode_expectations(U, bt)
         return fock_amplitudes(U, bt).view(x.shape[0], -1)

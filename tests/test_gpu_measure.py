@@ -1,0 +1,153 @@
+"""GPU parity of the per-mode photon-number expectations <n_j> = sum_t t_j p_t
+(fused last-layer epilogue and the layered reduction) and of their adjoint,
+against the FP64 oracle on the GPU's own complex64 inputs.
+
+Tolerance: p carries FP32 rounding (relative ~1e-6 per state after the
+recursion), so |<n_j>_gpu - <n_j>| <= ~1e-6 * n; E_TOL = 2e-5 covers n <= 16
+with margin."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import oracle as O
+from paper_2602_11092_amd import QuantumLayer
+from paper_2602_11092_amd import _binding as B
+from tests.gpu_util import DEV, G_RTOL, rel_err, say, to_dev_c64, widen
+
+pytestmark = pytest.mark.gpu
+
+E_TOL = 2e-5
+VARIANTS = [B.VARIANT_FUSED, B.VARIANT_LAYERED]
+
+
+def _mixed(seed, B_, m, n_hi, vacuum=True):
+    rng = np.random.default_rng(seed)
+    U = W.haar_unitaries(rng, B_, m).astype(np.complex64)
+    occ = np.zeros((B_, m), dtype=np.int32)
+    for b in range(B_):
+        n = 0 if (vacuum and b == 3) else int(rng.integers(1, n_hi + 1))
+        np.add.at(occ[b], rng.choice(m, size=n, replace=True), 1)
+    return U, occ
+
+
+def _closed_form(U, occ):
+    # <n_j> = sum_i s_i |U_ji|^2, FP64 from the complex64 inputs
+    return np.einsum("bji,bi->bj", np.abs(U.astype(np.complex128)) ** 2, occ.astype(np.float64))
+
+
+def _expect(batch, Ud, variant, block):
+    batch.set_config(B.OP_MODE_EXPECTATIONS, variant, block)
+    e = B.fock_mode_expectations(batch, Ud)
+    torch.cuda.synchronize()
+    return e.cpu().numpy()
+
+
+@pytest.mark.parametrize("variant,block", [(B.VARIANT_FUSED, 256), (B.VARIANT_FUSED, 512),
+                                           (B.VARIANT_FUSED, 1024), (B.VARIANT_LAYERED, 256)])
+def test_mode_expectations_mixed_batch(variant, block):
+    U, occ = _mixed(5, 40, 8, 6)
+    say("mode expectations m8 variant", variant, "block", block)
+    batch = B.Batch(B.Plan(8, int(occ.sum(1).max())), occ)
+    e = _expect(batch, to_dev_c64(U), variant, block)
+    assert e.shape == (40, 8)
+    for b in range(40):
+        ref = O.mode_expectations(widen(U[b]), occ[b])
+        assert np.abs(e[b] - ref).max() <= E_TOL, (b, np.abs(e[b] - ref).max())
+    assert np.all(e[3] == 0)  # the vacuum sample
+    assert np.abs(e - _closed_form(U, occ)).max() <= E_TOL
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_mode_expectations_clements_m20_n5_b512(variant):
+    # the benchmark's shapes: every sample against the closed form
+    wl = W.make("clements_m20_n5_b512")
+    say("mode expectations clements_m20_n5_b512 variant", variant)
+    batch = B.Batch(B.Plan(20, 5), wl.occ)
+    U = O.encoded_unitaries(wl.theta.astype(np.float64), wl.x.astype(np.float64), math.pi).astype(np.complex64)
+    e = _expect(batch, to_dev_c64(U), variant, 0)
+    assert np.abs(e - _closed_form(U, wl.occ)).max() <= E_TOL
+    # and a few samples against the definition
+    for b in (0, 255, 511):
+        assert np.abs(e[b] - O.mode_expectations(widen(U[b]), wl.occ[b])).max() <= E_TOL
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("space", ["unbunched", "dual_rail"])
+def test_mode_expectations_restricted_spaces(variant, space):
+    m = 10
+    U, occ = _mixed(9, 16, m, 5, vacuum=False)
+    dual = space == "dual_rail"
+    batch = B.Batch(B.Plan(m, 5, unbunched=not dual, dual_rail=dual), occ)
+    e = _expect(batch, to_dev_c64(U), variant, 256)
+    for b in range(16):
+        n = int(occ[b].sum())
+        outs = O.fock_basis(m, n)
+        keep = outs.reshape(len(outs), -1, 2).sum(2).max(1) <= 1 if dual else outs.max(1) <= 1
+        ref = O.mode_expectations(widen(U[b]), occ[b], outputs=outs[keep])
+        assert np.abs(e[b] - ref).max() <= E_TOL
+
+
+def test_fused_expectations_match_layered_and_probabilities():
+    U, occ = _mixed(6, 24, 12, 5)
+    Ud = to_dev_c64(U)
+    batch = B.Batch(B.Plan(12, 5), occ)
+    ef = _expect(batch, Ud, B.VARIANT_FUSED, 256)
+    el = _expect(batch, Ud, B.VARIANT_LAYERED, 256)
+    assert np.abs(ef - el).max() <= 1e-5
+    # and both match sum_t t_j p_t formed from the library's own probabilities
+    p = B.fock_probs(batch, Ud).cpu().numpy().astype(np.float64)
+    for b in range(24):
+        n = int(occ[b].sum())
+        o0, o1 = batch.offsets[b], batch.offsets[b + 1]
+        assert np.abs(ef[b] - p[o0:o1] @ O.fock_basis(12, n)).max() <= 1e-5
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_mode_expectations_backward(variant):
+    U, occ = _mixed(7, 24, 8, 5)
+    Ud = to_dev_c64(U)
+    batch = B.Batch(B.Plan(8, int(occ.sum(1).max())), occ)
+    batch.set_config(B.OP_MODE_EXPECTATIONS_BACKWARD, variant, 256)
+    rng = np.random.default_rng(1)
+    w = rng.standard_normal((24, 8)).astype(np.float32)
+    say("mode expectations backward variant", variant)
+    gU = B.fock_mode_expectations_backward(batch, Ud, torch.from_numpy(w).to(DEV))
+    torch.cuda.synchronize()
+    gU = gU.cpu().numpy()
+    for b in range(24):
+        n = int(occ[b].sum())
+        if n == 0:
+            assert np.all(gU[b] == 0)
+            continue
+        basis = O.fock_basis(8, n).astype(np.float64)
+        ref = O.probs_grad(widen(U[b]), occ[b], basis @ w[b].astype(np.float64))
+        assert rel_err(gU[b], ref) <= G_RTOL, (b, rel_err(gU[b], ref))
+        # (the closed form sum_i s_i |U_ji|^2 holds only on unitaries, so its
+        # unconstrained derivative differs; it is checked through the mesh below)
+
+
+def test_layer_mode_expectations_autograd():
+    m, occ = 6, [1, 0, 1, 0, 1, 0]
+    layer = QuantumLayer(m, occ, measurement="mode_expectations").to(DEV)
+    rng = np.random.default_rng(4)
+    x = torch.from_numpy(rng.standard_normal((5, m)).astype(np.float32)).to(DEV).requires_grad_(True)
+    w = torch.from_numpy(rng.standard_normal((5, m)).astype(np.float32)).to(DEV)
+    e = layer(x)
+    assert e.shape == (5, m)
+    (e * w).sum().backward()
+    torch.cuda.synchronize()
+    th = layer.theta.detach().cpu().numpy().astype(np.float64)
+    xx = x.detach().cpu().numpy().astype(np.float64)
+    Us = O.encoded_unitaries(th, xx, math.pi)
+    ref = np.stack([O.mode_expectations(U, occ) for U in Us])
+    assert np.abs(e.detach().cpu().numpy() - ref).max() <= E_TOL
+    # through the mesh every direction is tangent to the unitary group, where
+    # <n_j> = sum_i s_i |U_ji|^2: its derivative 2 w_j s_i U_ji gives the same chain
+    wn = w.cpu().numpy().astype(np.float64)
+    GU = np.stack([2.0 * wn[b][:, None] * np.asarray(occ)[None, :] * Us[b] for b in range(5)])
+    rt, rx = O.mesh_grad(th, xx, math.pi, GU)
+    assert rel_err(layer.theta.grad.cpu().numpy(), rt) <= G_RTOL
+    assert rel_err(x.grad.cpu().numpy(), rx) <= G_RTOL

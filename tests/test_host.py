@@ -247,3 +247,4 @@ def test_quantum_layer_computation_space_arguments():
         QuantumLayer(5, [1, 0, 1, 0, 0], computation_space="dual_rail")
     with pytest.raises(ValueError):
         QuantumLayer(3, [1, 1, 0], computation_space="dual")
+    assert QuantumLayer(6, [1, 1, 1, 0, 0, 0], measurement="mode_expectations").output_size == 6
