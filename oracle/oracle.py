@@ -22,6 +22,9 @@ Contents, each following the passage it cites (arXiv 2602.11092):
   by the product rule, in float64 NumPy.
 * Per-mode photon-number expectations <n_j> = sum_t t_j p_t over a set of
   output states (the measurement strategy of Sec. II-B), by that definition.
+* The fidelity kernel k(x1, x2) = |<phi(x1)|phi(x2)>|^2 with
+  |phi(x)> = U(x)|s> (the kernel-methods reproduction of Sec. III-A), as the
+  inner product of the two full amplitude vectors.
 * FP64 replicas of the two losses used by the benchmark workloads.
 """
 from __future__ import annotations
@@ -198,6 +201,13 @@ def mode_expectations(U: np.ndarray, s: Sequence[int], outputs: Optional[np.ndar
     if n == 0:
         return np.zeros(m)
     return probabilities(U, s, outputs.astype(np.int32)) @ outputs
+
+
+def fidelity(U1: np.ndarray, U2: np.ndarray, s: Sequence[int]) -> float:
+    """|sum_t conj(a_t(U1)) a_t(U2)|^2 over the whole n-photon basis."""
+    a1 = amplitudes(U1, s)
+    a2 = amplitudes(U2, s)
+    return float(abs(np.vdot(a1, a2)) ** 2)
 
 
 def amplitude_grad(U: np.ndarray, s: Sequence[int], G_a: np.ndarray,

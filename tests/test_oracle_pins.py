@@ -435,3 +435,29 @@ def test_mode_expectations_unbunched_two_photons_by_hand():
         pair[(a, b)] = abs(U[a, 0] * U[b, 1] + U[a, 1] * U[b, 0]) ** 2
     want = [pair[(0, 1)] + pair[(0, 2)], pair[(0, 1)] + pair[(1, 2)], pair[(0, 2)] + pair[(1, 2)]]
     assert np.abs(e - want).max() < 1e-14
+
+
+def _perm_brute(A):
+    n = A.shape[0]
+    return sum(np.prod([A[i, p[i]] for i in range(n)]) for p in itertools.permutations(range(n)))
+
+
+def test_fidelity_permanent_identity_and_invariants():
+    # <phi1|phi2> = Perm(U1[:,C]^H U2[:,C]) / prod s!, C the input modes with
+    # multiplicity (Cauchy-Binet over the output basis), by brute-force permanents
+    rng = np.random.default_rng(19)
+    for m, s in [(3, [1, 1, 0]), (4, [2, 0, 1, 0]), (5, [1, 0, 1, 1, 0]), (4, [0, 3, 0, 1])]:
+        U1, U2 = _haar(rng, m), _haar(rng, m)
+        C = [i for i in range(m) for _ in range(s[i])]
+        M = U1[:, C].conj().T @ U2[:, C]
+        f = abs(_perm_brute(M) / np.prod([math.factorial(v) for v in s])) ** 2
+        F = O.fidelity(U1, U2, s)
+        assert abs(F - f) < 1e-13
+        assert 0.0 <= F <= 1.0 + 1e-13
+        assert abs(F - O.fidelity(U2, U1, s)) < 1e-13           # symmetric
+        assert abs(O.fidelity(U1, U1, s) - 1.0) < 1e-12         # a state with itself
+        V = _haar(rng, m)
+        assert abs(O.fidelity(V @ U1, V @ U2, s) - F) < 1e-12   # common output unitary
+    # one photon in mode i: |(U1^H U2)_ii|^2
+    U1, U2 = _haar(rng, 4), _haar(rng, 4)
+    assert abs(O.fidelity(U1, U2, [0, 0, 1, 0]) - abs((U1.conj().T @ U2)[2, 2]) ** 2) < 1e-14
