@@ -240,6 +240,19 @@ SLOS_API int fock_mode_expectations(slos_batch_t batch, const float* U, float* o
 SLOS_API int fock_mode_expectations_backward(slos_batch_t batch, const float* U, const float* grad_out,
                                              float* grad_U, void* ws, size_t ws_bytes, void* stream);
 
+/* ---- Fidelity kernel (Sec. III-A: kernel methods) ------------------------ */
+
+/* K (device, float, [B1][B2], row-major) <- |<phi(U1_a)|phi(U2_b)>|^2 with
+ * |phi(U)> = U|s>, s = occ (host, m non-negative ints, n = sum <= 16):
+ * |Perm(U1_a[:, C]^H U2_b[:, C])|^2 / (prod s!)^2, C the input modes with
+ * multiplicity (one n x n permanent per pair instead of two Fock vectors).
+ * U1 (device, complex, [B1][m][m]) and U2 ([B2][m][m]) may be the same
+ * buffer (a Gram matrix).  FP64 arithmetic on the complex64 inputs; the
+ * vacuum (n = 0) gives 1.  Asynchronous on `stream`; no plan needed.
+ * SLOS_EINVAL for bad sizes or NULL pointers, SLOS_EUNSUPPORTED for n > 16. */
+SLOS_API int fock_fidelity_kernel(int m, const int32_t* occ, const float* U1, int B1, const float* U2, int B2,
+                                  float* K, void* stream);
+
 /* ---- Interferometer mesh U(x, theta) (Sec. II-A-3, Sec. II-C-1) ---------- */
 /*
  * Rectangular mesh of m(m-1)/2 Mach-Zehnder interferometers.  Column

@@ -67,6 +67,7 @@ SIGNATURES = {
     "fock_probs_backward": (_c.c_int, [_vp, _vp, _vp, _vp, _vp, _c.c_size_t, _vp]),
     "fock_mode_expectations": (_c.c_int, [_vp, _vp, _vp, _vp, _c.c_size_t, _vp]),
     "fock_mode_expectations_backward": (_c.c_int, [_vp, _vp, _vp, _vp, _vp, _c.c_size_t, _vp]),
+    "fock_fidelity_kernel": (_c.c_int, [_c.c_int, _vp, _vp, _c.c_int, _vp, _c.c_int, _vp, _vp]),
     "mesh_workspace_bytes": (_c.c_int, [_c.c_int, _c.c_int, _c.POINTER(_c.c_size_t)]),
     "mesh_to_unitary": (_c.c_int, [_c.c_int, _c.c_int, _vp, _vp, _c.c_float, _vp, _vp, _c.c_size_t, _vp]),
     "mesh_to_unitary_backward": (_c.c_int, [_c.c_int, _c.c_int, _vp, _vp, _c.c_float, _vp, _vp, _vp, _vp,
@@ -344,6 +345,30 @@ def fock_mode_expectations_backward(batch: Batch, U: torch.Tensor, grad_out: tor
     _check("fock_mode_expectations_backward",
            lib().fock_mode_expectations_backward(batch.handle, _ptr(U), _ptr(grad_out), _ptr(out), wp, wn,
                                                  _stream_ptr(U.device)))
+    return out
+
+
+def fock_fidelity_kernel(occ, U1: torch.Tensor, U2: Optional[torch.Tensor] = None,
+                         out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """K[a][b] = |<phi(U1_a)|phi(U2_b)>|^2 for input state occ, float32 [B1, B2]
+    (U2 = None: the Gram matrix of U1)."""
+    occ = np.ascontiguousarray(np.asarray(occ, dtype=np.int32).ravel())
+    m = occ.size
+    _require(U1, "U1", torch.complex64)
+    if U1.dim() != 3 or tuple(U1.shape[1:]) != (m, m):
+        raise ValueError("U1 must be [B1, m, m]")
+    if U2 is None:
+        U2 = U1
+    _require(U2, "U2", torch.complex64)
+    if U2.dim() != 3 or tuple(U2.shape[1:]) != (m, m):
+        raise ValueError("U2 must be [B2, m, m]")
+    B1, B2 = U1.shape[0], U2.shape[0]
+    if out is None:
+        out = torch.empty((B1, B2), dtype=torch.float32, device=U1.device)
+    _require(out, "out", torch.float32, (B1, B2))
+    _check("fock_fidelity_kernel",
+           lib().fock_fidelity_kernel(m, occ.ctypes.data_as(_vp), _ptr(U1), B1, _ptr(U2), B2, _ptr(out),
+                                      _stream_ptr(U1.device)))
     return out
 
 
