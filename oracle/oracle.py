@@ -22,6 +22,9 @@ Contents, each following the passage it cites (arXiv 2602.11092):
   by the product rule, in float64 NumPy.
 * Per-mode photon-number expectations <n_j> = sum_t t_j p_t over a set of
   output states (the measurement strategy of Sec. II-B), by that definition.
+* Threshold-detector click probabilities P(c) = sum of p_t over the states
+  t whose occupied modes are exactly c (the detector model of Sec. II-B),
+  patterns ordered by click count, then lexicographically.
 * The fidelity kernel k(x1, x2) = |<phi(x1)|phi(x2)>|^2 with
   |phi(x)> = U(x)|s> (the kernel-methods reproduction of Sec. III-A), as the
   inner product of the two full amplitude vectors.
@@ -201,6 +204,28 @@ def mode_expectations(U: np.ndarray, s: Sequence[int], outputs: Optional[np.ndar
     if n == 0:
         return np.zeros(m)
     return probabilities(U, s, outputs.astype(np.int32)) @ outputs
+
+
+def click_patterns(m: int, n: int) -> list:
+    """Click patterns of n photons over m modes: the non-empty sets of at most
+    n modes, by size, then in lexicographic order (n = 0: the empty pattern)."""
+    if n == 0:
+        return [()]
+    return [c for k in range(1, min(n, m) + 1) for c in itertools.combinations(range(m), k)]
+
+
+def threshold_probs(U: np.ndarray, s: Sequence[int]) -> np.ndarray:
+    """P(c) = sum_{t : {j : t_j > 0} = c} p_t for every click pattern c."""
+    U = np.ascontiguousarray(U, dtype=np.complex128)
+    m = U.shape[0]
+    n = int(np.sum(s))
+    basis = fock_basis(m, n)
+    p = probabilities(U, s, basis)
+    index = {c: i for i, c in enumerate(click_patterns(m, n))}
+    out = np.zeros(len(index))
+    for t, pt in zip(basis, p):
+        out[index[tuple(int(j) for j in np.nonzero(t)[0])]] += pt
+    return out
 
 
 def fidelity(U1: np.ndarray, U2: np.ndarray, s: Sequence[int]) -> float:

@@ -461,3 +461,24 @@ def test_fidelity_permanent_identity_and_invariants():
     # one photon in mode i: |(U1^H U2)_ii|^2
     U1, U2 = _haar(rng, 4), _haar(rng, 4)
     assert abs(O.fidelity(U1, U2, [0, 0, 1, 0]) - abs((U1.conj().T @ U2)[2, 2]) ** 2) < 1e-14
+
+
+def test_threshold_probs_closed_forms():
+    rng = np.random.default_rng(21)
+    m = 4
+    U = _haar(rng, m)
+    pats = O.click_patterns(m, 2)
+    assert len(pats) == 4 + 6 and pats[:4] == [(0,), (1,), (2,), (3,)] and pats[4] == (0, 1)
+    # one photon in mode 1: P({j}) = |U_j1|^2
+    P1 = O.threshold_probs(U, [0, 1, 0, 0])
+    assert np.abs(P1 - np.abs(U[:, 1]) ** 2).max() < 1e-14
+    # two photons in mode 2: P({j}) = |U_j2|^4, P({j,k}) = 2 |U_j2 U_k2|^2
+    P2 = O.threshold_probs(U, [0, 0, 2, 0])
+    u = U[:, 2]
+    want = [abs(u[j]) ** 4 for j in range(m)] + [2 * abs(u[j] * u[k]) ** 2 for j, k in pats[4:]]
+    assert np.abs(P2 - want).max() < 1e-14
+    assert abs(O.threshold_probs(U, [1, 1, 1, 0]).sum() - 1) < 1e-12
+    # Hong-Ou-Mandel: |1,1> through a 50:50 splitter never clicks both detectors
+    bs = np.array([[1, 1j], [1j, 1]]) / np.sqrt(2)
+    assert np.abs(O.threshold_probs(bs, [1, 1]) - [0.5, 0.5, 0.0]).max() < 1e-15
+    assert np.all(O.threshold_probs(U, [0, 0, 0, 0]) == [1.0])
