@@ -25,6 +25,9 @@ Contents, each following the passage it cites (arXiv 2602.11092):
 * Threshold-detector click probabilities P(c) = sum of p_t over the states
   t whose occupied modes are exactly c (the detector model of Sec. II-B),
   patterns ordered by click count, then lexicographically.
+* Shot sampling from the output distribution by inverse transform: with a
+  uniform u in [0, 1), the first state t whose cumulative probability (in
+  basis order, normalised over the output states) exceeds u.
 * The fidelity kernel k(x1, x2) = |<phi(x1)|phi(x2)>|^2 with
   |phi(x)> = U(x)|s> (the kernel-methods reproduction of Sec. III-A), as the
   inner product of the two full amplitude vectors.
@@ -226,6 +229,15 @@ def threshold_probs(U: np.ndarray, s: Sequence[int]) -> np.ndarray:
     for t, pt in zip(basis, p):
         out[index[tuple(int(j) for j in np.nonzero(t)[0])]] += pt
     return out
+
+
+def sample_shots(U: np.ndarray, s: Sequence[int], u: np.ndarray, outputs: Optional[np.ndarray] = None) -> np.ndarray:
+    """Output-state indices (into `outputs`, default the whole basis) drawn
+    from p / sum(p) by inverse transform of the uniforms u in [0, 1)."""
+    p = probabilities(U, s, outputs)
+    cdf = np.cumsum(p)
+    idx = np.searchsorted(cdf, np.asarray(u, dtype=np.float64) * cdf[-1], side="right")
+    return np.minimum(idx, p.size - 1).astype(np.int64)
 
 
 def fidelity(U1: np.ndarray, U2: np.ndarray, s: Sequence[int]) -> float:

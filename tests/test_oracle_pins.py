@@ -482,3 +482,25 @@ def test_threshold_probs_closed_forms():
     bs = np.array([[1, 1j], [1j, 1]]) / np.sqrt(2)
     assert np.abs(O.threshold_probs(bs, [1, 1]) - [0.5, 0.5, 0.0]).max() < 1e-15
     assert np.all(O.threshold_probs(U, [0, 0, 0, 0]) == [1.0])
+
+
+def test_sample_shots_pins():
+    rng = np.random.default_rng(23)
+    # identity: the output is the input state with certainty
+    s = [0, 2, 1, 0]
+    r = O.fock_rank(4, 3, s)
+    assert np.all(O.sample_shots(np.eye(4), s, rng.random(100)) == r)
+    # Hong-Ou-Mandel: p = (1/2, 0, 1/2) over |2,0>, |1,1>, |0,2>
+    bs = np.array([[1, 1j], [1j, 1]]) / np.sqrt(2)
+    u = np.array([0.0, 0.25, 0.4999, 0.5001, 0.75, 0.999999])
+    assert list(O.sample_shots(bs, [1, 1], u)) == [0, 0, 0, 2, 2, 2]
+    # empirical frequencies follow p (chi-square, 6 sigma for its degrees of freedom)
+    U = _haar(rng, 4)
+    s = [1, 1, 0, 0]
+    p = O.probabilities(U, s)
+    S = 40000
+    counts = np.bincount(O.sample_shots(U, s, rng.random(S)), minlength=p.size)
+    keep = p * S > 5
+    chi2 = (((counts - p * S) ** 2) / (p * S))[keep].sum()
+    dof = int(keep.sum()) - 1
+    assert chi2 < dof + 6 * math.sqrt(2 * dof)
