@@ -77,6 +77,8 @@ extern "C" {
 #define SLOS_OP_PROBS_BACKWARD 3
 #define SLOS_OP_MODE_EXPECTATIONS 4
 #define SLOS_OP_MODE_EXPECTATIONS_BACKWARD 5
+#define SLOS_OP_THRESHOLD_PROBS 6
+#define SLOS_OP_THRESHOLD_PROBS_BACKWARD 7
 
 /* Plan flags. */
 #define SLOS_PLAN_DEFAULT 0
@@ -97,6 +99,10 @@ extern "C" {
  * may be any Fock state.  Forward-only like SLOS_PLAN_UNBUNCHED; requires
  * an even m and n_max <= m/2; excludes SLOS_PLAN_UNBUNCHED. */
 #define SLOS_PLAN_DUAL_RAIL 4
+/* Also build the threshold-detector tables (Sec. II-B: detector models)
+ * used by fock_threshold_probs: per photon layer, the states of each click
+ * pattern.  Costs about 4 bytes per state. */
+#define SLOS_PLAN_THRESHOLD 8
 
 /* Kernel variants for slos_batch_set_config. */
 #define SLOS_VARIANT_AUTO 0    /* library heuristic (or the last value set) */
@@ -239,6 +245,35 @@ SLOS_API int fock_mode_expectations(slos_batch_t batch, const float* U, float* o
  * plans with successor tables only (SLOS_EUNSUPPORTED otherwise). */
 SLOS_API int fock_mode_expectations_backward(slos_batch_t batch, const float* U, const float* grad_out,
                                              float* grad_U, void* ws, size_t ws_bytes, void* stream);
+
+/* ---- Measurement: threshold detectors (Sec. II-B: detector models) ------- */
+
+/* Number of click patterns of n photons over m modes: the non-empty sets of
+ * at most n modes, sum_{k=1}^{min(n,m)} C(m, k); 1 (the empty pattern) for
+ * n = 0; -1 for a bad m or n.  Patterns are ordered by click count, then by
+ * the lexicographic order of the clicked modes. */
+SLOS_API int64_t slos_threshold_dim(int m, int n);
+
+/* Total length of the batch's click-pattern outputs, and their B+1 offsets
+ * (host memory): sample b owns [off[b], off[b+1]). */
+SLOS_API int64_t slos_batch_threshold_len(slos_batch_t batch);
+SLOS_API int slos_batch_threshold_offsets(slos_batch_t batch, int64_t* off_host);
+
+/* out (device, float, [threshold_len]) <- P(c) = sum of p_t over the states
+ * t whose occupied modes are exactly c (threshold detectors register
+ * presence, not number).  Needs a plan created with SLOS_PLAN_THRESHOLD
+ * (else SLOS_EUNSUPPORTED).  Forms p in the workspace with the
+ * configuration set for SLOS_OP_THRESHOLD_PROBS, then sums each pattern's
+ * states in ascending order (deterministic).  ws: slos_workspace_bytes(batch,
+ * SLOS_OP_THRESHOLD_PROBS) bytes. */
+SLOS_API int fock_threshold_probs(slos_batch_t batch, const float* U, float* out,
+                                  void* ws, size_t ws_bytes, void* stream);
+
+/* grad_U <- dL/dU given grad_out = dL/dP (device, float, [threshold_len]):
+ * dL/dp_t = dL/dP(pattern of t) in the workspace, then the probability
+ * adjoint.  Full-space plans with successor tables only. */
+SLOS_API int fock_threshold_probs_backward(slos_batch_t batch, const float* U, const float* grad_out,
+                                           float* grad_U, void* ws, size_t ws_bytes, void* stream);
 
 /* ---- Fidelity kernel (Sec. III-A: kernel methods) ------------------------ */
 

@@ -30,11 +30,14 @@ OP_AMPLITUDES_BACKWARD = 2
 OP_PROBS_BACKWARD = 3
 OP_MODE_EXPECTATIONS = 4
 OP_MODE_EXPECTATIONS_BACKWARD = 5
+OP_THRESHOLD_PROBS = 6
+OP_THRESHOLD_PROBS_BACKWARD = 7
 
 PLAN_DEFAULT = 0
 PLAN_FORWARD_ONLY = 1
 PLAN_UNBUNCHED = 2
 PLAN_DUAL_RAIL = 4
+PLAN_THRESHOLD = 8
 
 VARIANT_AUTO = 0
 VARIANT_FUSED = 1
@@ -67,6 +70,11 @@ SIGNATURES = {
     "fock_probs_backward": (_c.c_int, [_vp, _vp, _vp, _vp, _vp, _c.c_size_t, _vp]),
     "fock_mode_expectations": (_c.c_int, [_vp, _vp, _vp, _vp, _c.c_size_t, _vp]),
     "fock_mode_expectations_backward": (_c.c_int, [_vp, _vp, _vp, _vp, _vp, _c.c_size_t, _vp]),
+    "slos_threshold_dim": (_c.c_int64, [_c.c_int, _c.c_int]),
+    "slos_batch_threshold_len": (_c.c_int64, [_vp]),
+    "slos_batch_threshold_offsets": (_c.c_int, [_vp, _vp]),
+    "fock_threshold_probs": (_c.c_int, [_vp, _vp, _vp, _vp, _c.c_size_t, _vp]),
+    "fock_threshold_probs_backward": (_c.c_int, [_vp, _vp, _vp, _vp, _vp, _c.c_size_t, _vp]),
     "fock_fidelity_kernel": (_c.c_int, [_c.c_int, _vp, _vp, _c.c_int, _vp, _c.c_int, _vp, _vp]),
     "mesh_workspace_bytes": (_c.c_int, [_c.c_int, _c.c_int, _c.POINTER(_c.c_size_t)]),
     "mesh_to_unitary": (_c.c_int, [_c.c_int, _c.c_int, _vp, _vp, _c.c_float, _vp, _vp, _c.c_size_t, _vp]),
@@ -139,6 +147,11 @@ def space_flags(unbunched: bool = False, dual_rail: bool = False) -> int:
     return (PLAN_UNBUNCHED if unbunched else 0) | (PLAN_DUAL_RAIL if dual_rail else 0)
 
 
+def slos_threshold_dim(m: int, n: int) -> int:
+    """Number of click patterns of n photons over m modes (-1 if invalid)."""
+    return int(lib().slos_threshold_dim(m, n))
+
+
 def slos_space_dim(m: int, n: int, flags: int = PLAN_DEFAULT) -> int:
     """Size of the n-photon layer of the space that plans with `flags` use (-1 if invalid)."""
     return int(lib().slos_space_dim(m, n, flags))
@@ -161,9 +174,10 @@ class Plan:
     """Transition graph for m modes and up to n_max photons (slos_plan_create)."""
 
     def __init__(self, m: int, n_max: int, forward_only: bool = False, unbunched: bool = False,
-                 dual_rail: bool = False):
+                 dual_rail: bool = False, threshold: bool = False):
         h = _vp()
         flags = space_flags(unbunched, dual_rail) | (PLAN_FORWARD_ONLY if forward_only else PLAN_DEFAULT)
+        flags |= PLAN_THRESHOLD if threshold else 0
         _check("slos_plan_create", lib().slos_plan_create(m, n_max, flags, ctypes.byref(h)))
         self._h = h
         self.m = m
@@ -205,6 +219,10 @@ class Batch:
         off = np.zeros(self.B + 1, dtype=np.int64)
         _check("slos_batch_out_offsets", lib().slos_batch_out_offsets(h, off.ctypes.data_as(_vp)))
         self.offsets = off
+        toff = np.zeros(self.B + 1, dtype=np.int64)
+        _check("slos_batch_threshold_offsets", lib().slos_batch_threshold_offsets(h, toff.ctypes.data_as(_vp)))
+        self.threshold_offsets = toff
+        self.threshold_len = int(toff[-1])
         self._ws = {}
 
     @property
@@ -345,6 +363,38 @@ def fock_mode_expectations_backward(batch: Batch, U: torch.Tensor, grad_out: tor
     _check("fock_mode_expectations_backward",
            lib().fock_mode_expectations_backward(batch.handle, _ptr(U), _ptr(grad_out), _ptr(out), wp, wn,
                                                  _stream_ptr(U.device)))
+    return out
+
+
+def fock_threshold_probs(batch: Batch, U: torch.Tensor, out: Optional[torch.Tensor] = None,
+                         ws: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Threshold-detector click probabilities, float32 [threshold_len] (ragged per sample)."""
+    _require(U, "U", torch.complex64, (batch.B, batch.m, batch.m))
+    if out is None:
+        out = torch.empty(batch.threshold_len, dtype=torch.float32, device=U.device)
+    _require(out, "out", torch.float32, (batch.threshold_len,))
+    if ws is None:
+        ws = batch.workspace(OP_THRESHOLD_PROBS, U.device)
+    wp, wn = _ws_args(ws)
+    _check("fock_threshold_probs",
+           lib().fock_threshold_probs(batch.handle, _ptr(U), _ptr(out), wp, wn, _stream_ptr(U.device)))
+    return out
+
+
+def fock_threshold_probs_backward(batch: Batch, U: torch.Tensor, grad_out: torch.Tensor,
+                                  out: Optional[torch.Tensor] = None,
+                                  ws: Optional[torch.Tensor] = None) -> torch.Tensor:
+    _require(U, "U", torch.complex64, (batch.B, batch.m, batch.m))
+    _require(grad_out, "grad_out", torch.float32, (batch.threshold_len,))
+    if out is None:
+        out = torch.empty_like(U)
+    _require(out, "grad_U", torch.complex64, (batch.B, batch.m, batch.m))
+    if ws is None:
+        ws = batch.workspace(OP_THRESHOLD_PROBS_BACKWARD, U.device)
+    wp, wn = _ws_args(ws)
+    _check("fock_threshold_probs_backward",
+           lib().fock_threshold_probs_backward(batch.handle, _ptr(U), _ptr(grad_out), _ptr(out), wp, wn,
+                                               _stream_ptr(U.device)))
     return out
 
 

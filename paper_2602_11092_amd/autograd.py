@@ -63,6 +63,23 @@ class FockModeExpectations(torch.autograd.Function):
         return gU, None
 
 
+class FockThresholdProbs(torch.autograd.Function):
+    """U [B, m, m] complex64 -> threshold-detector click probabilities float32 [threshold_len]."""
+
+    @staticmethod
+    def forward(ctx, U: torch.Tensor, batch: B.Batch):
+        U = U.contiguous()
+        ctx.batch = batch
+        ctx.save_for_backward(U)
+        return B.fock_threshold_probs(batch, U)
+
+    @staticmethod
+    def backward(ctx, grad_P):
+        (U,) = ctx.saved_tensors
+        gU = B.fock_threshold_probs_backward(ctx.batch, U, grad_P.contiguous().to(torch.float32))
+        return gU, None
+
+
 class MeshToUnitary(torch.autograd.Function):
     """theta [m(m-1)] float32 and features x [B, m] float32 (or None) ->
     U [B, m, m] complex64."""
@@ -98,6 +115,10 @@ def fock_amplitudes(U: torch.Tensor, batch: B.Batch) -> torch.Tensor:
 
 def fock_mode_expectations(U: torch.Tensor, batch: B.Batch) -> torch.Tensor:
     return FockModeExpectations.apply(U, batch)
+
+
+def fock_threshold_probs(U: torch.Tensor, batch: B.Batch) -> torch.Tensor:
+    return FockThresholdProbs.apply(U, batch)
 
 
 def mesh_to_unitary(theta: torch.Tensor, x: Optional[torch.Tensor], enc_scale: float = math.pi,

@@ -138,7 +138,7 @@ int64_t space_dim(int m, int n, int group) {
     return v > (__int128)INT64_MAX ? -1 : (int64_t)v;
 }
 
-constexpr int kPlanFlags = SLOS_PLAN_FORWARD_ONLY | SLOS_PLAN_UNBUNCHED | SLOS_PLAN_DUAL_RAIL;
+constexpr int kPlanFlags = SLOS_PLAN_FORWARD_ONLY | SLOS_PLAN_UNBUNCHED | SLOS_PLAN_DUAL_RAIL | SLOS_PLAN_THRESHOLD;
 
 // group size of a plan's flags
 int flags_group(int flags) {
@@ -174,6 +174,7 @@ void parallel_ranges(int64_t total, F&& body) {
 struct HostLayer {
     std::vector<int32_t> pred, succ, minoff;
     std::vector<float> nrm;
+    std::vector<int32_t> thr_ptr, thr_idx;  // click-pattern tables (SLOS_PLAN_THRESHOLD)
 };
 
 // Transition graph of layer k (k >= 1): predecessor entries for every
@@ -234,7 +235,49 @@ void build_layer(int m, int k, const Counter& Ck, const Counter& Ckm1, int64_t N
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Click-pattern tables of layer k (Counter Ck of the plan's space): pattern
+// q's states, ascending, in idx[ptr[q] .. ptr[q+1]).  Pattern index of a
+// state: offset of its click count j plus the rank of its occupied modes
+// among the j-sets (unbunched order).
+void build_threshold(int m, int k, const Counter& Ck, int64_t Nk, std::vector<int32_t>& ptr,
+                     std::vector<int32_t>& idx) {
+    const int jmax = std::min(k, m);
+    std::vector<int64_t> off(jmax + 2, 0);
+    std::vector<Counter> sets;
+    sets.reserve(jmax + 1);
+    for (int j = 0; j <= jmax; ++j) sets.emplace_back(m, j, 1);
+    for (int j = 1; j <= jmax; ++j) off[j + 1] = off[j] + binom(m, j);
+    const int64_t Q = off[jmax + 1];
+    std::vector<int32_t> pat(Nk);
+    parallel_ranges(Nk, [&](int64_t lo, int64_t hi) {
+        int L[kMaxPhotons], D[kMaxPhotons];
+        Ck.unrank(lo, k, L);
+        for (int64_t t = lo; t < hi; ++t) {
+            int j = 0;
+            for (int p = 0; p < k; ++p)
+                if (p == 0 || L[p] != L[p - 1]) D[j++] = L[p];
+            pat[t] = (int32_t)(off[j] + sets[j].rank(D, j));
+            Ck.next(L, k);
+        }
+    });
+    ptr.assign(Q + 1, 0);
+    for (int64_t t = 0; t < Nk; ++t) ++ptr[pat[t] + 1];
+    for (int64_t q = 0; q < Q; ++q) ptr[q + 1] += ptr[q];
+    std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
+    idx.assign(Nk, 0);
+    for (int64_t t = 0; t < Nk; ++t) idx[fill[pat[t]]++] = (int32_t)t;
+}
+
 }  // namespace
+
+int64_t threshold_dim(int m, int n) {
+    if (m < 1 || n < 0) return -1;
+    if (n == 0) return 1;
+    int64_t q = 0;
+    for (int j = 1; j <= std::min(n, m); ++j) q += binom(m, j);
+    return q;
+}
+
 }  // namespace slos
 
 using namespace slos;
@@ -359,6 +402,7 @@ extern "C" int slos_plan_create(int m, int n_max, int flags, slos_plan_t* out) {
             }
         H[k].pred.swap(packed);
         shifts[k] = shift;
+        if (flags & SLOS_PLAN_THRESHOLD) build_threshold(m, k, C[k], Nk, H[k].thr_ptr, H[k].thr_idx);
         // device successors: groups of four modes, [j/4][t'][4], byte offsets rank * 8
         if (want_succ) {
             const int64_t Nkm1 = P->N[k - 1];
@@ -375,11 +419,14 @@ extern "C" int slos_plan_create(int m, int n_max, int flags, slos_plan_t* out) {
     // one device allocation for every table
     size_t total = align256(sizeof(LayerDev) * (n_max + 1));
     std::vector<size_t> o_pred(n_max + 1), o_succ(n_max + 1), o_nrm(n_max + 1), o_min(n_max + 1);
+    std::vector<size_t> o_tp(n_max + 1), o_ti(n_max + 1);
     for (int k = 1; k <= n_max; ++k) {
         o_pred[k] = total; total += align256(H[k].pred.size() * 4);
         o_succ[k] = total; total += align256(H[k].succ.size() * 4);
         o_nrm[k] = total;  total += align256(H[k].nrm.size() * 4);
         o_min[k] = total;  total += align256(H[k].minoff.size() * 4);
+        o_tp[k] = total;   total += align256(H[k].thr_ptr.size() * 4);
+        o_ti[k] = total;   total += align256(H[k].thr_idx.size() * 4);
     }
     if (hipMalloc(&P->dmem, total) != hipSuccess) {
         delete P;
@@ -400,7 +447,15 @@ extern "C" int slos_plan_create(int m, int n_max, int flags, slos_plan_t* out) {
         L.succ = want_succ ? (const uint32_t*)(base + o_succ[k]) : nullptr;
         L.nrm = (const float*)(base + o_nrm[k]);
         L.minoff = (const int32_t*)(base + o_min[k]);
+        const bool thr = !H[k].thr_ptr.empty();
+        L.thr_ptr = thr ? (const int32_t*)(base + o_tp[k]) : nullptr;
+        L.thr_idx = thr ? (const int32_t*)(base + o_ti[k]) : nullptr;
+        L.Q = thr ? (int64_t)H[k].thr_ptr.size() - 1 : 0;
         e = hipMemcpy(base + o_pred[k], H[k].pred.data(), H[k].pred.size() * 4, hipMemcpyHostToDevice);
+        if (e == hipSuccess && thr)
+            e = hipMemcpy(base + o_tp[k], H[k].thr_ptr.data(), H[k].thr_ptr.size() * 4, hipMemcpyHostToDevice);
+        if (e == hipSuccess && thr)
+            e = hipMemcpy(base + o_ti[k], H[k].thr_idx.data(), H[k].thr_idx.size() * 4, hipMemcpyHostToDevice);
         if (e == hipSuccess && want_succ)
             e = hipMemcpy(base + o_succ[k], H[k].succ.data(), H[k].succ.size() * 4, hipMemcpyHostToDevice);
         if (e == hipSuccess)
@@ -440,6 +495,7 @@ extern "C" int slos_batch_create(slos_plan_t plan, int B, const int32_t* occ_hos
     Bt->B = B;
     Bt->n_host.resize(B);
     Bt->off_host.assign(B + 1, 0);
+    Bt->thr_off_host.assign(B + 1, 0);
     std::vector<int32_t> modes((size_t)std::max(B, 1) * kMaxPhotons, 0);
     std::vector<float> innorm(std::max(B, 1), 1.f);
     for (int b = 0; b < B; ++b) {
@@ -461,6 +517,7 @@ extern "C" int slos_batch_create(slos_plan_t plan, int B, const int32_t* occ_hos
         Bt->n_host[b] = n;
         innorm[b] = (float)(1.0 / std::sqrt(f));
         Bt->off_host[b + 1] = Bt->off_host[b] + plan->N[n];
+        Bt->thr_off_host[b + 1] = Bt->thr_off_host[b] + threshold_dim(m, n);
         Bt->n_max = std::max(Bt->n_max, n);
     }
     std::vector<int32_t> order(B);
@@ -471,7 +528,8 @@ extern "C" int slos_batch_create(slos_plan_t plan, int B, const int32_t* occ_hos
     const size_t Bs = std::max(B, 1);
     size_t o_n = 0, o_modes = align256(Bs * 4), o_off = o_modes + align256(Bs * kMaxPhotons * 4);
     size_t o_in = o_off + align256((Bs + 1) * 8), o_ord = o_in + align256(Bs * 4);
-    size_t total = o_ord + align256(Bs * 4);
+    size_t o_thr = o_ord + align256(Bs * 4);
+    size_t total = o_thr + align256((Bs + 1) * 8);
     if (hipMalloc(&Bt->dmem, total) != hipSuccess) {
         delete Bt;
         return fail(SLOS_ENOMEM, "slos_batch_create: hipMalloc failed");
@@ -485,6 +543,7 @@ extern "C" int slos_batch_create(slos_plan_t plan, int B, const int32_t* occ_hos
         if (e == hipSuccess) e = hipMemcpy(base + o_ord, order.data(), B * 4, hipMemcpyHostToDevice);
     }
     if (e == hipSuccess) e = hipMemcpy(base + o_off, Bt->off_host.data(), (B + 1) * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(base + o_thr, Bt->thr_off_host.data(), (B + 1) * 8, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         hipFree(Bt->dmem);
         delete Bt;
@@ -497,6 +556,7 @@ extern "C" int slos_batch_create(slos_plan_t plan, int B, const int32_t* occ_hos
     Bt->dev.off = (const int64_t*)(base + o_off);
     Bt->dev.innorm = (const float*)(base + o_in);
     Bt->dev.order = (const int32_t*)(base + o_ord);
+    Bt->dev.thr_off = (const int64_t*)(base + o_thr);
     *out = Bt;
     return SLOS_OK;
 }
@@ -522,10 +582,12 @@ extern "C" int slos_batch_out_offsets(slos_batch_t batch, int64_t* off_host) {
 
 namespace {
 
-bool op_valid(int op) { return op >= SLOS_OP_AMPLITUDES && op <= SLOS_OP_MODE_EXPECTATIONS_BACKWARD; }
+bool op_valid(int op) { return op >= SLOS_OP_AMPLITUDES && op <= SLOS_OP_THRESHOLD_PROBS_BACKWARD; }
 bool op_backward(int op) {
-    return op == SLOS_OP_AMPLITUDES_BACKWARD || op == SLOS_OP_PROBS_BACKWARD || op == SLOS_OP_MODE_EXPECTATIONS_BACKWARD;
+    return op == SLOS_OP_AMPLITUDES_BACKWARD || op == SLOS_OP_PROBS_BACKWARD ||
+           op == SLOS_OP_MODE_EXPECTATIONS_BACKWARD || op == SLOS_OP_THRESHOLD_PROBS_BACKWARD;
 }
+bool op_threshold(int op) { return op == SLOS_OP_THRESHOLD_PROBS || op == SLOS_OP_THRESHOLD_PROBS_BACKWARD; }
 bool op_expect(int op) { return op == SLOS_OP_MODE_EXPECTATIONS || op == SLOS_OP_MODE_EXPECTATIONS_BACKWARD; }
 
 // the expectation ops keep dL/dp or p (out_len floats) at the start of their workspace
@@ -575,6 +637,8 @@ extern "C" int slos_workspace_bytes(slos_batch_t batch, int op, size_t* bytes) {
     if (op == SLOS_OP_MODE_EXPECTATIONS_BACKWARD) *bytes += expect_head_bytes(*batch);
     if (op == SLOS_OP_MODE_EXPECTATIONS && v != SLOS_VARIANT_FUSED)
         *bytes += expect_head_bytes(*batch) + align256(mode_expect_part_bytes(*batch));
+    // the threshold ops keep p or dL/dp in the workspace
+    if (op_threshold(op)) *bytes += expect_head_bytes(*batch);
     return SLOS_OK;
 }
 
@@ -637,11 +701,40 @@ int run_expect(const slos_batch_s& Bt, int op, int v, int blk, const float* U, c
                  : launch_layered_bwd(Bt, blk, (const float2*)U, pv, true, (float2*)out, rest, s);
 }
 
+// Threshold-detector click probabilities and their adjoint: p (or dL/dp)
+// lives at the start of the workspace; the forward gathers each pattern's
+// states, the adjoint scatters dL/dP back onto them.
+int run_threshold(const slos_batch_s& Bt, int op, int v, int blk, const float* U, const void* gin, void* out,
+                  void* ws, size_t ws_bytes, hipStream_t s, const std::string& nm) {
+    if (!(Bt.plan->flags & SLOS_PLAN_THRESHOLD))
+        return fail(SLOS_EUNSUPPORTED, nm + ": plan was created without SLOS_PLAN_THRESHOLD");
+    const bool bwd = op == SLOS_OP_THRESHOLD_PROBS_BACKWARD;
+    const bool fused = v == SLOS_VARIANT_FUSED;
+    const size_t head = expect_head_bytes(Bt);
+    const size_t need = head + (fused ? 0 : layered_ws_bytes(Bt, bwd));
+    if (!ws || ws_bytes < need)
+        return fail(SLOS_EWORKSPACE, nm + ": workspace missing or too small (need " + std::to_string(need) + " bytes)");
+    float* pv = (float*)ws;
+    void* rest = (char*)ws + head;
+    int rc;
+    if (!bwd) {
+        rc = fused ? launch_fused_fwd(Bt, blk, (const float2*)U, pv, 1, s)
+                   : launch_layered_fwd(Bt, blk, (const float2*)U, pv, true, rest, s);
+        if (rc == SLOS_OK) rc = launch_threshold_gather(Bt, pv, (float*)out, s);
+        return rc;
+    }
+    rc = launch_threshold_scatter(Bt, (const float*)gin, pv, s);
+    if (rc != SLOS_OK) return rc;
+    return fused ? launch_fused_bwd(Bt, blk, (const float2*)U, pv, true, (float2*)out, s)
+                 : launch_layered_bwd(Bt, blk, (const float2*)U, pv, true, (float2*)out, rest, s);
+}
+
 int run(slos_batch_t batch, int op, const float* U, const void* gin, void* out, void* ws, size_t ws_bytes,
         void* stream) {
-    static const char* names[6] = {"fock_amplitudes", "fock_probs", "fock_amplitudes_backward",
+    static const char* names[8] = {"fock_amplitudes", "fock_probs", "fock_amplitudes_backward",
                                    "fock_probs_backward", "fock_mode_expectations",
-                                   "fock_mode_expectations_backward"};
+                                   "fock_mode_expectations_backward", "fock_threshold_probs",
+                                   "fock_threshold_probs_backward"};
     const std::string nm = names[op];
     if (!batch) return fail(SLOS_EINVAL, nm + ": batch is NULL");
     if (batch->B == 0) return SLOS_OK;
@@ -658,6 +751,7 @@ int run(slos_batch_t batch, int op, const float* U, const void* gin, void* out, 
     const bool probs = (op == SLOS_OP_PROBS || op == SLOS_OP_PROBS_BACKWARD);
     hipStream_t s = (hipStream_t)stream;
     if (op_expect(op)) return run_expect(*batch, op, v, blk, U, gin, out, ws, ws_bytes, s, nm);
+    if (op_threshold(op)) return run_threshold(*batch, op, v, blk, U, gin, out, ws, ws_bytes, s, nm);
     int rc;
     if (v == SLOS_VARIANT_FUSED) {
         rc = bwd ? launch_fused_bwd(*batch, blk, (const float2*)U, gin, probs, (float2*)out, s)
@@ -693,6 +787,29 @@ extern "C" int fock_amplitudes_backward(slos_batch_t batch, const float* U, cons
 extern "C" int fock_probs_backward(slos_batch_t batch, const float* U, const float* grad_probs, float* grad_U,
                                    void* ws, size_t ws_bytes, void* stream) {
     return run(batch, SLOS_OP_PROBS_BACKWARD, U, grad_probs, grad_U, ws, ws_bytes, stream);
+}
+
+extern "C" int64_t slos_threshold_dim(int m, int n) { return threshold_dim(m, n); }
+
+extern "C" int64_t slos_batch_threshold_len(slos_batch_t batch) {
+    if (!batch) return -1;
+    return batch->thr_off_host[batch->B];
+}
+
+extern "C" int slos_batch_threshold_offsets(slos_batch_t batch, int64_t* off_host) {
+    if (!batch || !off_host) return fail(SLOS_EINVAL, "slos_batch_threshold_offsets: NULL argument");
+    std::memcpy(off_host, batch->thr_off_host.data(), (batch->B + 1) * sizeof(int64_t));
+    return SLOS_OK;
+}
+
+extern "C" int fock_threshold_probs(slos_batch_t batch, const float* U, float* out, void* ws, size_t ws_bytes,
+                                    void* stream) {
+    return run(batch, SLOS_OP_THRESHOLD_PROBS, U, nullptr, out, ws, ws_bytes, stream);
+}
+
+extern "C" int fock_threshold_probs_backward(slos_batch_t batch, const float* U, const float* grad_out,
+                                             float* grad_U, void* ws, size_t ws_bytes, void* stream) {
+    return run(batch, SLOS_OP_THRESHOLD_PROBS_BACKWARD, U, grad_out, grad_U, ws, ws_bytes, stream);
 }
 
 extern "C" int fock_mode_expectations(slos_batch_t batch, const float* U, float* out, void* ws, size_t ws_bytes,

@@ -49,6 +49,12 @@ struct LayerDev {
     int64_t cum;            // number of states with fewer than k photons (sum of N_0..N_{k-1})
     int32_t ngrp;           // ceil(k / 4)
     int32_t pred_shift;     // kPredShiftCompact or kPredShiftWide
+    // threshold-detector tables (plans created with SLOS_PLAN_THRESHOLD, else nullptr):
+    // click pattern q (by click count, then lexicographic) holds the states
+    // thr_idx[thr_ptr[q] .. thr_ptr[q+1]), ascending
+    const int32_t* thr_ptr; // [Q + 1]
+    const int32_t* thr_idx; // [N]
+    int64_t Q;              // number of click patterns of k photons
 };
 
 // Per-sample description of a batch (device pointers).
@@ -60,6 +66,7 @@ struct BatchDev {
     const int64_t* off;      // [B+1] output offsets
     const float* innorm;     // [B] 1/sqrt(prod_i s_i!)
     const int32_t* order;    // [B] work order (largest photon number first)
+    const int64_t* thr_off;  // [B+1] offsets of the click-pattern outputs
 };
 
 struct Config {
@@ -86,9 +93,10 @@ struct slos_batch_s {
     int n_max = 0;
     std::vector<int32_t> n_host;
     std::vector<int64_t> off_host;
+    std::vector<int64_t> thr_off_host;  // click-pattern output offsets
     void* dmem = nullptr;
     slos::BatchDev dev{};
-    slos::Config cfg[6];
+    slos::Config cfg[8];
 };
 
 namespace slos {
@@ -124,6 +132,11 @@ size_t mode_expect_part_bytes(const slos_batch_s& Bt);
 int launch_mode_expect(const slos_batch_s& Bt, const float* p, float* part, float* out, hipStream_t stream);
 // gp[off_b + t] = sum_j t_j w[b][j]
 int launch_expand_mode_weights(const slos_batch_s& Bt, const float* w, float* gp, hipStream_t stream);
+// out[thr_off_b + q] = sum of p over click pattern q's states
+int launch_threshold_gather(const slos_batch_s& Bt, const float* p, float* out, hipStream_t stream);
+// gp[off_b + t] = gP[thr_off_b + pattern(t)]
+int launch_threshold_scatter(const slos_batch_s& Bt, const float* gP, float* gp, hipStream_t stream);
+int64_t threshold_dim(int m, int n);
 
 }  // namespace slos
 

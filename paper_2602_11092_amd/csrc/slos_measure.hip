@@ -5,6 +5,9 @@
 //   <n_j>_b      = sum_t t_j p_b[t]     (mode_expect_partial_kernel, then
 //                                         mode_expect_final_kernel)
 //   dL/dp_b[t]   = sum_j t_j dL/d<n_j>_b  (expand_kernel)
+//   P_b(c)       = sum of p_b over the states of click pattern c
+//                                         (threshold_gather_kernel)
+//   dL/dp_b[t]   = dL/dP_b(pattern of t)  (threshold_scatter_kernel)
 //
 // A state's photons are read from its predecessor entries in the transition
 // table of its photon layer (for_each_photon).  Workgroup b * C + c takes
@@ -88,7 +91,76 @@ __global__ __launch_bounds__(kMeasureBlock) void expand_kernel(int m, const Laye
     }
 }
 
+// Click patterns per workgroup in the threshold kernels.
+constexpr int64_t kChunkPatterns = (int64_t)kMeasureBlock * 16;
+
+// Workgroup b * C + c: patterns [c * kChunkPatterns, ...) of sample b, one
+// thread per pattern, its states summed in ascending order.
+__global__ __launch_bounds__(kMeasureBlock) void threshold_gather_kernel(const LayerDev* __restrict__ Ls, BatchDev Bt,
+                                                                         const float* __restrict__ p,
+                                                                         float* __restrict__ out, int C) {
+    const int b = blockIdx.x / C, c = blockIdx.x % C;
+    const int n = ldg(Bt.n + b);
+    const int64_t off = ldg(Bt.off + b), toff = ldg(Bt.thr_off + b);
+    if (n == 0) {  // the empty pattern: the vacuum itself
+        if (c == 0 && threadIdx.x == 0) out[toff] = p[off];
+        return;
+    }
+    const LayerDev L = Ls[n];
+    const int64_t q = (int64_t)c * kChunkPatterns + threadIdx.x;
+    for (int64_t r = q; r < L.Q && r < (int64_t)(c + 1) * kChunkPatterns; r += kMeasureBlock) {
+        const int32_t lo = ldg(L.thr_ptr + r), hi = ldg(L.thr_ptr + r + 1);
+        float v = 0.f;
+        for (int32_t i = lo; i < hi; ++i) v += p[off + ldg(L.thr_idx + i)];
+        out[toff + r] = v;
+    }
+}
+
+// The adjoint: every state of pattern r receives dL/dP(r) (each state is in
+// exactly one pattern, so the writes do not overlap).
+__global__ __launch_bounds__(kMeasureBlock) void threshold_scatter_kernel(const LayerDev* __restrict__ Ls, BatchDev Bt,
+                                                                          const float* __restrict__ gP,
+                                                                          float* __restrict__ gp, int C) {
+    const int b = blockIdx.x / C, c = blockIdx.x % C;
+    const int n = ldg(Bt.n + b);
+    const int64_t off = ldg(Bt.off + b), toff = ldg(Bt.thr_off + b);
+    if (n == 0) {
+        if (c == 0 && threadIdx.x == 0) gp[off] = gP[toff];
+        return;
+    }
+    const LayerDev L = Ls[n];
+    const int64_t q = (int64_t)c * kChunkPatterns + threadIdx.x;
+    for (int64_t r = q; r < L.Q && r < (int64_t)(c + 1) * kChunkPatterns; r += kMeasureBlock) {
+        const int32_t lo = ldg(L.thr_ptr + r), hi = ldg(L.thr_ptr + r + 1);
+        const float g = gP[toff + r];
+        for (int32_t i = lo; i < hi; ++i) gp[off + ldg(L.thr_idx + i)] = g;
+    }
+}
+
+int threshold_chunks(const slos_batch_s& Bt) {
+    const int64_t Q = threshold_dim(Bt.plan->m, Bt.n_max);
+    return (int)std::max<int64_t>(1, (Q + kChunkPatterns - 1) / kChunkPatterns);
+}
+
+int launch_threshold(const void* fn, const slos_batch_s& Bt, const float* in, float* out, hipStream_t stream,
+                     const char* what) {
+    int C = threshold_chunks(Bt);
+    if ((int64_t)Bt.B * C >= ((int64_t)1 << 31)) return fail(SLOS_EUNSUPPORTED, std::string(what) + ": batch too large");
+    void* args[] = {(void*)&Bt.plan->d_layers, (void*)&Bt.dev, (void*)&in, (void*)&out, (void*)&C};
+    hipError_t e = hipLaunchKernel(fn, dim3((unsigned)(Bt.B * C)), dim3(kMeasureBlock), args, 0, stream);
+    if (e != hipSuccess) return fail(SLOS_EHIP, std::string(what) + " launch: " + hipGetErrorString(e));
+    return SLOS_OK;
+}
+
 }  // namespace
+
+int launch_threshold_gather(const slos_batch_s& Bt, const float* p, float* out, hipStream_t stream) {
+    return launch_threshold((const void*)&threshold_gather_kernel, Bt, p, out, stream, "threshold gather");
+}
+
+int launch_threshold_scatter(const slos_batch_s& Bt, const float* gP, float* gp, hipStream_t stream) {
+    return launch_threshold((const void*)&threshold_scatter_kernel, Bt, gP, gp, stream, "threshold scatter");
+}
 
 int64_t mode_expect_chunks(const slos_batch_s& Bt) {
     const int64_t N = Bt.n_max >= 0 ? Bt.plan->N[Bt.n_max] : 1;

@@ -11,14 +11,15 @@ import torch
 from torch import nn
 
 from . import _binding as B
-from .autograd import fock_amplitudes, fock_mode_expectations, fock_probs, mesh_to_unitary
+from .autograd import fock_amplitudes, fock_mode_expectations, fock_probs, fock_threshold_probs, mesh_to_unitary
 
 
 class QuantumLayer(nn.Module):
     """x [batch, m] float32 -> probabilities [batch, C(m+n-1, n)] (or
-    complex amplitudes with measurement="amplitudes", or the per-mode photon
-    number expectations [batch, m] with measurement="mode_expectations") for
-    one input Fock state.  Trainable parameters: the m(m-1) mesh phases.
+    complex amplitudes with measurement="amplitudes", the per-mode photon
+    number expectations [batch, m] with measurement="mode_expectations", or
+    threshold-detector click probabilities with measurement="threshold_probs")
+    for one input Fock state.  Trainable parameters: the m(m-1) mesh phases.
 
     computation_space="unbunched" keeps only the output states with at most
     one photon per mode (C(m, n) of them, in the same relative order);
@@ -32,8 +33,8 @@ class QuantumLayer(nn.Module):
         occ = np.asarray(input_state, dtype=np.int32)
         if occ.shape != (m,):
             raise ValueError("input_state must have m entries")
-        if measurement not in ("probs", "amplitudes", "mode_expectations"):
-            raise ValueError("measurement must be 'probs', 'amplitudes' or 'mode_expectations'")
+        if measurement not in ("probs", "amplitudes", "mode_expectations", "threshold_probs"):
+            raise ValueError("measurement must be 'probs', 'amplitudes', 'mode_expectations' or 'threshold_probs'")
         if computation_space not in ("fock", "unbunched", "dual_rail"):
             raise ValueError("computation_space must be 'fock', 'unbunched' or 'dual_rail'")
         if computation_space == "unbunched" and int(occ.sum()) > m:
@@ -55,6 +56,8 @@ class QuantumLayer(nn.Module):
     def output_size(self) -> int:
         if self.measurement == "mode_expectations":
             return self.m
+        if self.measurement == "threshold_probs":
+            return B.slos_threshold_dim(self.m, self.n)
         return B.slos_space_dim(self.m, self.n, self._flags())
 
     def _flags(self) -> int:
@@ -63,7 +66,8 @@ class QuantumLayer(nn.Module):
     def _batch(self, nb: int) -> B.Batch:
         if self._plan is None:
             self._plan = B.Plan(self.m, max(self.n, 1), unbunched=self.computation_space == "unbunched",
-                                dual_rail=self.computation_space == "dual_rail")
+                                dual_rail=self.computation_space == "dual_rail",
+                                threshold=self.measurement == "threshold_probs")
         bt = self._batches.get(nb)
         if bt is None:
             bt = B.Batch(self._plan, np.tile(self.occ, (nb, 1)))
@@ -79,4 +83,6 @@ class QuantumLayer(nn.Module):
             return fock_probs(U, bt).view(x.shape[0], -1)
         if self.measurement == "mode_expectations":
             return fock_mode_expectations(U, bt)
+        if self.measurement == "threshold_probs":
+            return fock_threshold_probs(U, bt).view(x.shape[0], -1)
         return fock_amplitudes(U, bt).view(x.shape[0], -1)

@@ -104,7 +104,7 @@ def test_argument_errors_without_device():
     assert L.slos_plan_create(33, 3, 0, ctypes.byref(h)) == B.SLOS_EINVAL
     assert L.slos_plan_create(6, 0, 0, ctypes.byref(h)) == B.SLOS_EINVAL
     assert L.slos_plan_create(6, 17, 0, ctypes.byref(h)) == B.SLOS_EINVAL
-    assert L.slos_plan_create(6, 3, 8, ctypes.byref(h)) == B.SLOS_EINVAL
+    assert L.slos_plan_create(6, 3, 16, ctypes.byref(h)) == B.SLOS_EINVAL
     assert L.slos_plan_create(6, 3, 0, None) == B.SLOS_EINVAL
     assert b"m must be" in L.slos_last_error() or len(L.slos_last_error()) > 0
     occ = np.zeros(6, np.int32)
@@ -220,7 +220,8 @@ def test_space_dim_flags():
     assert B.slos_space_dim(6, 4, B.PLAN_DUAL_RAIL) == 0
     assert B.slos_space_dim(5, 2, B.PLAN_DUAL_RAIL) == -1  # odd m
     assert B.slos_space_dim(6, 2, B.PLAN_UNBUNCHED | B.PLAN_DUAL_RAIL) == -1
-    assert B.slos_space_dim(6, 2, 8) == -1
+    assert B.slos_space_dim(6, 2, 16) == -1
+    assert B.slos_space_dim(6, 2, B.PLAN_THRESHOLD) == math.comb(7, 2)
 
 
 def test_unbunched_argument_errors_without_device():
@@ -228,7 +229,7 @@ def test_unbunched_argument_errors_without_device():
     L = B.lib()
     h = ctypes.c_void_p()
     assert L.slos_plan_create(3, 4, B.PLAN_UNBUNCHED, ctypes.byref(h)) == B.SLOS_EINVAL  # n_max > m
-    assert L.slos_plan_create(3, 2, 8, ctypes.byref(h)) == B.SLOS_EINVAL  # unknown flag
+    assert L.slos_plan_create(3, 2, 16, ctypes.byref(h)) == B.SLOS_EINVAL  # unknown flag
     assert L.slos_plan_create(5, 2, B.PLAN_DUAL_RAIL, ctypes.byref(h)) == B.SLOS_EINVAL  # odd m
     assert L.slos_plan_create(6, 4, B.PLAN_DUAL_RAIL, ctypes.byref(h)) == B.SLOS_EINVAL  # n_max > m/2
     assert L.slos_plan_create(6, 2, B.PLAN_DUAL_RAIL | B.PLAN_UNBUNCHED, ctypes.byref(h)) == B.SLOS_EINVAL
@@ -248,3 +249,15 @@ def test_quantum_layer_computation_space_arguments():
     with pytest.raises(ValueError):
         QuantumLayer(3, [1, 1, 0], computation_space="dual")
     assert QuantumLayer(6, [1, 1, 1, 0, 0, 0], measurement="mode_expectations").output_size == 6
+
+
+@pytest.mark.parametrize("m,n", [(4, 0), (4, 1), (4, 2), (5, 3), (3, 5), (20, 5), (24, 8)])
+def test_threshold_dim(m, n):
+    want = 1 if n == 0 else sum(math.comb(m, k) for k in range(1, min(n, m) + 1))
+    assert B.slos_threshold_dim(m, n) == want
+    assert B.slos_threshold_dim(0, 2) == -1
+
+
+def test_threshold_layer_output_size():
+    from paper_2602_11092_amd import QuantumLayer
+    assert QuantumLayer(4, [1, 1, 0, 0], measurement="threshold_probs").output_size == 4 + 6
