@@ -79,6 +79,7 @@ extern "C" {
 #define SLOS_OP_MODE_EXPECTATIONS_BACKWARD 5
 #define SLOS_OP_THRESHOLD_PROBS 6
 #define SLOS_OP_THRESHOLD_PROBS_BACKWARD 7
+#define SLOS_OP_SAMPLE 8
 
 /* Plan flags. */
 #define SLOS_PLAN_DEFAULT 0
@@ -274,6 +275,19 @@ SLOS_API int fock_threshold_probs(slos_batch_t batch, const float* U, float* out
  * adjoint.  Full-space plans with successor tables only. */
 SLOS_API int fock_threshold_probs_backward(slos_batch_t batch, const float* U, const float* grad_out,
                                            float* grad_U, void* ws, size_t ws_bytes, void* stream);
+
+/* ---- Measurement: shot sampling (Sec. II-B, finite-shot measurement) ----- */
+
+/* shots (device, int32, [B][S]) <- output-state indices (within each
+ * sample's output block, basis order) drawn from p / sum(p) by inverse
+ * transform of the caller's uniforms u (device, float, [B][S], in [0, 1)):
+ * the first state whose cumulative probability exceeds u * sum(p), the last
+ * state if none does.  p comes from the configuration set for
+ * SLOS_OP_SAMPLE; its cumulative sums are formed in FP64 in the workspace
+ * (slos_workspace_bytes(batch, SLOS_OP_SAMPLE) bytes) in a fixed order, so
+ * equal uniforms give equal shots.  S >= 0. */
+SLOS_API int fock_sample(slos_batch_t batch, const float* U, const float* u, int S, int32_t* shots,
+                         void* ws, size_t ws_bytes, void* stream);
 
 /* ---- Fidelity kernel (Sec. III-A: kernel methods) ------------------------ */
 

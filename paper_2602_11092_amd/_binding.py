@@ -32,6 +32,7 @@ OP_MODE_EXPECTATIONS = 4
 OP_MODE_EXPECTATIONS_BACKWARD = 5
 OP_THRESHOLD_PROBS = 6
 OP_THRESHOLD_PROBS_BACKWARD = 7
+OP_SAMPLE = 8
 
 PLAN_DEFAULT = 0
 PLAN_FORWARD_ONLY = 1
@@ -75,6 +76,7 @@ SIGNATURES = {
     "slos_batch_threshold_offsets": (_c.c_int, [_vp, _vp]),
     "fock_threshold_probs": (_c.c_int, [_vp, _vp, _vp, _vp, _c.c_size_t, _vp]),
     "fock_threshold_probs_backward": (_c.c_int, [_vp, _vp, _vp, _vp, _vp, _c.c_size_t, _vp]),
+    "fock_sample": (_c.c_int, [_vp, _vp, _vp, _c.c_int, _vp, _vp, _c.c_size_t, _vp]),
     "fock_fidelity_kernel": (_c.c_int, [_c.c_int, _vp, _vp, _c.c_int, _vp, _c.c_int, _vp, _vp]),
     "mesh_workspace_bytes": (_c.c_int, [_c.c_int, _c.c_int, _c.POINTER(_c.c_size_t)]),
     "mesh_to_unitary": (_c.c_int, [_c.c_int, _c.c_int, _vp, _vp, _c.c_float, _vp, _vp, _c.c_size_t, _vp]),
@@ -395,6 +397,27 @@ def fock_threshold_probs_backward(batch: Batch, U: torch.Tensor, grad_out: torch
     _check("fock_threshold_probs_backward",
            lib().fock_threshold_probs_backward(batch.handle, _ptr(U), _ptr(grad_out), _ptr(out), wp, wn,
                                                _stream_ptr(U.device)))
+    return out
+
+
+def fock_sample(batch: Batch, U: torch.Tensor, u: torch.Tensor, out: Optional[torch.Tensor] = None,
+                ws: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Shots drawn from p / sum(p) by inverse transform of the uniforms u
+    (float32 [B, S] in [0, 1)): int32 [B, S] state indices within each
+    sample's output block."""
+    _require(U, "U", torch.complex64, (batch.B, batch.m, batch.m))
+    _require(u, "u", torch.float32)
+    if u.dim() != 2 or u.shape[0] != batch.B:
+        raise ValueError("u must be [B, S]")
+    S = u.shape[1]
+    if out is None:
+        out = torch.empty((batch.B, S), dtype=torch.int32, device=U.device)
+    _require(out, "shots", torch.int32, (batch.B, S))
+    if ws is None:
+        ws = batch.workspace(OP_SAMPLE, U.device)
+    wp, wn = _ws_args(ws)
+    _check("fock_sample", lib().fock_sample(batch.handle, _ptr(U), _ptr(u), S, _ptr(out), wp, wn,
+                                            _stream_ptr(U.device)))
     return out
 
 

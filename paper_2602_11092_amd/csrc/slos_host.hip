@@ -582,7 +582,7 @@ extern "C" int slos_batch_out_offsets(slos_batch_t batch, int64_t* off_host) {
 
 namespace {
 
-bool op_valid(int op) { return op >= SLOS_OP_AMPLITUDES && op <= SLOS_OP_THRESHOLD_PROBS_BACKWARD; }
+bool op_valid(int op) { return op >= SLOS_OP_AMPLITUDES && op <= SLOS_OP_SAMPLE; }
 bool op_backward(int op) {
     return op == SLOS_OP_AMPLITUDES_BACKWARD || op == SLOS_OP_PROBS_BACKWARD ||
            op == SLOS_OP_MODE_EXPECTATIONS_BACKWARD || op == SLOS_OP_THRESHOLD_PROBS_BACKWARD;
@@ -592,6 +592,11 @@ bool op_expect(int op) { return op == SLOS_OP_MODE_EXPECTATIONS || op == SLOS_OP
 
 // the expectation ops keep dL/dp or p (out_len floats) at the start of their workspace
 size_t expect_head_bytes(const slos_batch_s& Bt) { return align256((size_t)Bt.off_host[Bt.B] * sizeof(float)); }
+// sampling keeps p, the FP64 cumulative sums and the chunk totals
+size_t sample_head_bytes(const slos_batch_s& Bt) {
+    return expect_head_bytes(Bt) + align256((size_t)Bt.off_host[Bt.B] * sizeof(double)) +
+           align256((size_t)Bt.B * mode_expect_chunks(Bt) * sizeof(double));
+}
 
 // Default fused block size of an op: the expectation epilogue's [m][block]
 // accumulators share LDS with the photon layers, so it steps down to the
@@ -639,6 +644,7 @@ extern "C" int slos_workspace_bytes(slos_batch_t batch, int op, size_t* bytes) {
         *bytes += expect_head_bytes(*batch) + align256(mode_expect_part_bytes(*batch));
     // the threshold ops keep p or dL/dp in the workspace
     if (op_threshold(op)) *bytes += expect_head_bytes(*batch);
+    if (op == SLOS_OP_SAMPLE) *bytes += sample_head_bytes(*batch);
     return SLOS_OK;
 }
 
@@ -787,6 +793,32 @@ extern "C" int fock_amplitudes_backward(slos_batch_t batch, const float* U, cons
 extern "C" int fock_probs_backward(slos_batch_t batch, const float* U, const float* grad_probs, float* grad_U,
                                    void* ws, size_t ws_bytes, void* stream) {
     return run(batch, SLOS_OP_PROBS_BACKWARD, U, grad_probs, grad_U, ws, ws_bytes, stream);
+}
+
+extern "C" int fock_sample(slos_batch_t batch, const float* U, const float* u, int S, int32_t* shots, void* ws,
+                           size_t ws_bytes, void* stream) {
+    const std::string nm = "fock_sample";
+    if (!batch) return fail(SLOS_EINVAL, nm + ": batch is NULL");
+    if (S < 0) return fail(SLOS_EINVAL, nm + ": S must be >= 0");
+    if (batch->B == 0) return SLOS_OK;
+    if (!U) return fail(SLOS_EINVAL, nm + ": U is NULL");
+    if (S > 0 && (!u || !shots)) return fail(SLOS_EINVAL, nm + ": uniforms or shots pointer is NULL");
+    int v, blk;
+    resolve(*batch, SLOS_OP_SAMPLE, &v, &blk);
+    const bool fused = v == SLOS_VARIANT_FUSED;
+    const size_t head = sample_head_bytes(*batch);
+    const size_t need = head + (fused ? 0 : layered_ws_bytes(*batch, false));
+    if (!ws || ws_bytes < need)
+        return fail(SLOS_EWORKSPACE, nm + ": workspace missing or too small (need " + std::to_string(need) + " bytes)");
+    char* base = (char*)ws;
+    float* pv = (float*)base;
+    double* cdf = (double*)(base + expect_head_bytes(*batch));
+    double* part = (double*)(base + expect_head_bytes(*batch) + align256((size_t)batch->off_host[batch->B] * 8));
+    hipStream_t s = (hipStream_t)stream;
+    int rc = fused ? launch_fused_fwd(*batch, blk, (const float2*)U, pv, 1, s)
+                   : launch_layered_fwd(*batch, blk, (const float2*)U, pv, true, base + head, s);
+    if (rc != SLOS_OK) return rc;
+    return launch_sample(*batch, pv, part, cdf, u, S, shots, s);
 }
 
 extern "C" int64_t slos_threshold_dim(int m, int n) { return threshold_dim(m, n); }

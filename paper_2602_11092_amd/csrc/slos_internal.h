@@ -96,7 +96,7 @@ struct slos_batch_s {
     std::vector<int64_t> thr_off_host;  // click-pattern output offsets
     void* dmem = nullptr;
     slos::BatchDev dev{};
-    slos::Config cfg[8];
+    slos::Config cfg[9];
 };
 
 namespace slos {
@@ -137,6 +137,11 @@ int launch_threshold_gather(const slos_batch_s& Bt, const float* p, float* out, 
 // gp[off_b + t] = gP[thr_off_b + pattern(t)]
 int launch_threshold_scatter(const slos_batch_s& Bt, const float* gP, float* gp, hipStream_t stream);
 int64_t threshold_dim(int m, int n);
+// shots[b][s] <- first t with cdf_b[t] > u[b][s] cdf_b[N_b - 1]; part: B * chunks doubles
+// (chunks = mode_expect_chunks), cdf: out_len doubles
+int64_t mode_expect_chunks(const slos_batch_s& Bt);
+int launch_sample(const slos_batch_s& Bt, const float* p, double* part, double* cdf, const float* u, int S,
+                  int32_t* shots, hipStream_t stream);
 
 }  // namespace slos
 

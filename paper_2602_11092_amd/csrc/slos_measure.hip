@@ -8,6 +8,8 @@
 //   P_b(c)       = sum of p_b over the states of click pattern c
 //                                         (threshold_gather_kernel)
 //   dL/dp_b[t]   = dL/dP_b(pattern of t)  (threshold_scatter_kernel)
+//   cdf_b[t]     = sum_{t' <= t} p_b[t'], FP64 (cdf_partial_kernel, cdf_scan_kernel)
+//   shot         = first t with cdf_b[t] > u cdf_b[N-1]  (sample_kernel)
 //
 // A state's photons are read from its predecessor entries in the transition
 // table of its photon layer (for_each_photon).  Workgroup b * C + c takes
@@ -137,6 +139,95 @@ __global__ __launch_bounds__(kMeasureBlock) void threshold_scatter_kernel(const 
     }
 }
 
+// Cumulative sums for sampling, in two passes over (sample, chunk) pairs of
+// kChunkStates states: chunk totals, then each chunk scans its states from
+// the sum of the chunks before it.  FP64 sums, fixed order.
+__global__ __launch_bounds__(kMeasureBlock) void cdf_partial_kernel(BatchDev Bt, const float* __restrict__ p,
+                                                                    double* __restrict__ part, int C) {
+    __shared__ double red[kMeasureBlock / 64];
+    const int b = blockIdx.x / C, c = blockIdx.x % C;
+    const int64_t off = ldg(Bt.off + b), N = ldg(Bt.off + b + 1) - off;
+    const int64_t lo = (int64_t)c * kChunkStates, hi = lo + kChunkStates < N ? lo + kChunkStates : N;
+    double v = 0.0;
+    for (int64_t t = lo + threadIdx.x; t < hi; t += kMeasureBlock) v += p[off + t];
+    for (int s = 32; s >= 1; s >>= 1) v += __shfl_xor(v, s, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < kMeasureBlock / 64; ++w) t += red[w];
+        part[(size_t)b * C + c] = t;
+    }
+}
+
+__global__ __launch_bounds__(kMeasureBlock) void cdf_scan_kernel(BatchDev Bt, const float* __restrict__ p,
+                                                                 const double* __restrict__ part, int C,
+                                                                 double* __restrict__ cdf) {
+    constexpr int V = 4;  // consecutive states per thread per tile
+    constexpr int kWaves = kMeasureBlock / 64;
+    __shared__ double wtot[kWaves];
+    __shared__ double carry_s;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int b = blockIdx.x / C, c = blockIdx.x % C;
+    const int64_t off = ldg(Bt.off + b), N = ldg(Bt.off + b + 1) - off;
+    const int64_t lo = (int64_t)c * kChunkStates, hi = lo + kChunkStates < N ? lo + kChunkStates : N;
+    if (tid == 0) {
+        double s0 = 0.0;
+        for (int q = 0; q < c; ++q) s0 += part[(size_t)b * C + q];
+        carry_s = s0;
+    }
+    __syncthreads();
+    for (int64_t t0 = lo; t0 < hi; t0 += (int64_t)kMeasureBlock * V) {
+        double v[V];
+        const int64_t tb = t0 + (int64_t)tid * V;
+#pragma unroll
+        for (int i = 0; i < V; ++i) v[i] = (tb + i < hi) ? (double)p[off + tb + i] : 0.0;
+#pragma unroll
+        for (int i = 1; i < V; ++i) v[i] += v[i - 1];
+        // inclusive scan of the thread totals within the wave
+        double x = v[V - 1];
+        for (int s = 1; s < 64; s <<= 1) {
+            const double y = __shfl_up(x, s, 64);
+            if (lane >= s) x += y;
+        }
+        if (lane == 63) wtot[w] = x;
+        __syncthreads();
+        double before = carry_s;
+        for (int q = 0; q < w; ++q) before += wtot[q];
+        before += x - v[V - 1];  // exclusive within the wave
+#pragma unroll
+        for (int i = 0; i < V; ++i)
+            if (tb + i < hi) cdf[off + tb + i] = before + v[i];
+        __syncthreads();  // every thread has read carry_s and wtot
+        if (tid == 0) {
+            double t = carry_s;
+            for (int q = 0; q < kWaves; ++q) t += wtot[q];
+            carry_s = t;
+        }
+        __syncthreads();
+    }
+}
+
+// Thread per shot: the first state whose cumulative probability exceeds
+// u * (the sample's total), clamped to the last state.
+__global__ __launch_bounds__(kMeasureBlock) void sample_kernel(BatchDev Bt, const double* __restrict__ cdf,
+                                                               const float* __restrict__ u, int S,
+                                                               int32_t* __restrict__ shots) {
+    const int64_t i = (int64_t)blockIdx.x * kMeasureBlock + threadIdx.x;
+    if (i >= (int64_t)Bt.B * S) return;
+    const int64_t b = i / S;
+    const int64_t off = ldg(Bt.off + b), N = ldg(Bt.off + b + 1) - off;
+    const double* cb = cdf + off;
+    const double target = (double)u[i] * cb[N - 1];
+    int64_t lo = 0, hi = N - 1;  // answer in [lo, hi]
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (cb[mid] > target) hi = mid;
+        else lo = mid + 1;
+    }
+    shots[i] = (int32_t)lo;
+}
+
 int threshold_chunks(const slos_batch_s& Bt) {
     const int64_t Q = threshold_dim(Bt.plan->m, Bt.n_max);
     return (int)std::max<int64_t>(1, (Q + kChunkPatterns - 1) / kChunkPatterns);
@@ -160,6 +251,26 @@ int launch_threshold_gather(const slos_batch_s& Bt, const float* p, float* out, 
 
 int launch_threshold_scatter(const slos_batch_s& Bt, const float* gP, float* gp, hipStream_t stream) {
     return launch_threshold((const void*)&threshold_scatter_kernel, Bt, gP, gp, stream, "threshold scatter");
+}
+
+int launch_sample(const slos_batch_s& Bt, const float* p, double* part, double* cdf, const float* u, int S,
+                  int32_t* shots, hipStream_t stream) {
+    int C = (int)mode_expect_chunks(Bt);
+    if ((int64_t)Bt.B * C >= ((int64_t)1 << 31)) return fail(SLOS_EUNSUPPORTED, "fock_sample: batch too large");
+    void* a1[] = {(void*)&Bt.dev, (void*)&p, (void*)&part, (void*)&C};
+    hipError_t e = hipLaunchKernel((void*)&cdf_partial_kernel, dim3((unsigned)(Bt.B * C)), dim3(kMeasureBlock), a1, 0,
+                                   stream);
+    void* a2[] = {(void*)&Bt.dev, (void*)&p, (void*)&part, (void*)&C, (void*)&cdf};
+    if (e == hipSuccess)
+        e = hipLaunchKernel((void*)&cdf_scan_kernel, dim3((unsigned)(Bt.B * C)), dim3(kMeasureBlock), a2, 0, stream);
+    const int64_t shots_n = (int64_t)Bt.B * S;
+    if (e == hipSuccess && shots_n > 0) {
+        void* a3[] = {(void*)&Bt.dev, (void*)&cdf, (void*)&u, (void*)&S, (void*)&shots};
+        e = hipLaunchKernel((void*)&sample_kernel, dim3((unsigned)((shots_n + kMeasureBlock - 1) / kMeasureBlock)),
+                            dim3(kMeasureBlock), a3, 0, stream);
+    }
+    if (e != hipSuccess) return fail(SLOS_EHIP, std::string("fock_sample launch: ") + hipGetErrorString(e));
+    return SLOS_OK;
 }
 
 int64_t mode_expect_chunks(const slos_batch_s& Bt) {
