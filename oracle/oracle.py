@@ -28,6 +28,9 @@ Contents, each following the passage it cites (arXiv 2602.11092):
 * Shot sampling from the output distribution by inverse transform: with a
   uniform u in [0, 1), the first state t whose cumulative probability (in
   basis order, normalised over the output states) exceeds u.
+* Amplitude-encoded inputs (Sec. II-C-2): a superposition sum_c x_c |s_c>
+  of n-photon Fock states maps to sum_c x_c U|s_c> (linearity of U's
+  action), over the whole n-photon basis.
 * The fidelity kernel k(x1, x2) = |<phi(x1)|phi(x2)>|^2 with
   |phi(x)> = U(x)|s> (the kernel-methods reproduction of Sec. III-A), as the
   inner product of the two full amplitude vectors.
@@ -207,6 +210,18 @@ def mode_expectations(U: np.ndarray, s: Sequence[int], outputs: Optional[np.ndar
     if n == 0:
         return np.zeros(m)
     return probabilities(U, s, outputs.astype(np.int32)) @ outputs
+
+
+def superposition_amplitudes(U: np.ndarray, states: Sequence[Sequence[int]], x: Sequence[complex]) -> np.ndarray:
+    """sum_c x_c a(U, s_c) over the n-photon basis; every s_c has n photons."""
+    states = [np.asarray(st, dtype=np.int32) for st in states]
+    n = int(states[0].sum())
+    if any(int(st.sum()) != n for st in states):
+        raise ValueError("components must have the same photon number")
+    out = np.zeros(fock_dim(np.asarray(U).shape[0], n), dtype=np.complex128)
+    for st, xc in zip(states, x):
+        out += complex(xc) * amplitudes(U, st)
+    return out
 
 
 def click_patterns(m: int, n: int) -> list:

@@ -504,3 +504,23 @@ def test_sample_shots_pins():
     chi2 = (((counts - p * S) ** 2) / (p * S))[keep].sum()
     dof = int(keep.sum()) - 1
     assert chi2 < dof + 6 * math.sqrt(2 * dof)
+
+
+def test_superposition_amplitudes_pins():
+    rng = np.random.default_rng(29)
+    # (|2,0> + |0,2>)/sqrt2 through a 50:50 splitter is i|1,1> (reversed Hong-Ou-Mandel)
+    bs = np.array([[1, 1j], [1j, 1]]) / np.sqrt(2)
+    out = O.superposition_amplitudes(bs, [[2, 0], [0, 2]], [1 / np.sqrt(2), 1 / np.sqrt(2)])
+    assert np.abs(out - [0, 1j, 0]).max() < 1e-15
+    # the identity places the weights at the components' basis positions
+    m, n = 4, 3
+    comps = [[1, 1, 1, 0], [0, 0, 2, 1], [3, 0, 0, 0]]
+    x = rng.standard_normal(3) + 1j * rng.standard_normal(3)
+    want = np.zeros(O.fock_dim(m, n), dtype=complex)
+    for c, xc in zip(comps, x):
+        want[O.fock_rank(m, n, c)] = xc
+    assert np.abs(O.superposition_amplitudes(np.eye(m), comps, x) - want).max() < 1e-15
+    # U acts unitarily on the n-photon space: the norm is kept
+    U = _haar(rng, m)
+    x /= np.linalg.norm(x)
+    assert abs(np.linalg.norm(O.superposition_amplitudes(U, comps, x)) - 1) < 1e-12
