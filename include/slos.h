@@ -247,6 +247,45 @@ SLOS_API int fock_mode_expectations(slos_batch_t batch, const float* U, float* o
 SLOS_API int fock_mode_expectations_backward(slos_batch_t batch, const float* U, const float* grad_out,
                                              float* grad_U, void* ws, size_t ws_bytes, void* stream);
 
+/* ---- Amplitude-encoded inputs (Sec. II-C-2) -------------------------------- */
+/*
+ * An amplitude-encoded input is a superposition sum_c x_c |s_c> of Fock
+ * states of one photon number; U maps it to sum_c x_c U|s_c> (linearity).
+ * The batch's samples are the components s_c; a superposition groups them:
+ * input g holds components [group_off[g], group_off[g+1]) (all with one
+ * photon number n_g) and owns the output block [out_off[g], out_off[g+1])
+ * of length C(m+n_g-1, n_g), basis order.  The components' amplitudes use
+ * the batch's configuration for SLOS_OP_AMPLITUDES (forward) and
+ * SLOS_OP_AMPLITUDES_BACKWARD (adjoint).  Cost: one SLOS per component.
+ */
+typedef struct slos_superposition_s* slos_superposition_t;
+
+/* group_off: host, G+1 non-decreasing offsets from 0 to the batch size.
+ * SLOS_EINVAL if a group mixes photon numbers or the offsets are bad.  The
+ * batch must outlive the superposition. */
+SLOS_API int slos_superposition_create(slos_batch_t components, int G, const int64_t* group_off,
+                                       slos_superposition_t* out);
+SLOS_API int slos_superposition_destroy(slos_superposition_t sup);
+SLOS_API int64_t slos_superposition_out_len(slos_superposition_t sup);
+SLOS_API int slos_superposition_out_offsets(slos_superposition_t sup, int64_t* off_host);
+/* Device workspace of the forward (backward = 0) or the adjoint (1). */
+SLOS_API int slos_superposition_workspace_bytes(slos_superposition_t sup, int backward, size_t* bytes);
+
+/* out (device, complex, [out_len]) <- sum_c x_c a(U_g, s_c) for every group g.
+ * U: device, complex, [G][m][m] (one interferometer per group); x: device,
+ * complex, [C] weights.  Sums run over components in order (deterministic). */
+SLOS_API int fock_superposition_amplitudes(slos_superposition_t sup, const float* U, const float* x, float* out,
+                                           void* ws, size_t ws_bytes, void* stream);
+
+/* Given grad_out = dL/dout (device, complex, [out_len]):
+ * grad_U (device, complex, [G][m][m]) <- dL/dU_g = sum over g's components of
+ * the amplitude adjoint at dL/da_c = conj(x_c) grad_out_g;
+ * grad_x (device, complex, [C], may be NULL) <- dL/dx_c = sum_t conj(a_c[t]) grad_out_g[t].
+ * Gradients use the dL/dRe + i dL/dIm convention. */
+SLOS_API int fock_superposition_amplitudes_backward(slos_superposition_t sup, const float* U, const float* x,
+                                                    const float* grad_out, float* grad_U, float* grad_x,
+                                                    void* ws, size_t ws_bytes, void* stream);
+
 /* ---- Measurement: threshold detectors (Sec. II-B: detector models) ------- */
 
 /* Number of click patterns of n photons over m modes: the non-empty sets of

@@ -76,6 +76,13 @@ SIGNATURES = {
     "slos_batch_threshold_offsets": (_c.c_int, [_vp, _vp]),
     "fock_threshold_probs": (_c.c_int, [_vp, _vp, _vp, _vp, _c.c_size_t, _vp]),
     "fock_threshold_probs_backward": (_c.c_int, [_vp, _vp, _vp, _vp, _vp, _c.c_size_t, _vp]),
+    "slos_superposition_create": (_c.c_int, [_vp, _c.c_int, _vp, _vp]),
+    "slos_superposition_destroy": (_c.c_int, [_vp]),
+    "slos_superposition_out_len": (_c.c_int64, [_vp]),
+    "slos_superposition_out_offsets": (_c.c_int, [_vp, _vp]),
+    "slos_superposition_workspace_bytes": (_c.c_int, [_vp, _c.c_int, _vp]),
+    "fock_superposition_amplitudes": (_c.c_int, [_vp, _vp, _vp, _vp, _vp, _c.c_size_t, _vp]),
+    "fock_superposition_amplitudes_backward": (_c.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _c.c_size_t, _vp]),
     "fock_sample": (_c.c_int, [_vp, _vp, _vp, _c.c_int, _vp, _vp, _c.c_size_t, _vp]),
     "fock_fidelity_kernel": (_c.c_int, [_c.c_int, _vp, _vp, _c.c_int, _vp, _c.c_int, _vp, _vp]),
     "mesh_workspace_bytes": (_c.c_int, [_c.c_int, _c.c_int, _c.POINTER(_c.c_size_t)]),
@@ -130,6 +137,9 @@ def _require(t: torch.Tensor, name: str, dtype, shape=None):
         raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
     if not t.is_contiguous():
         raise ValueError("%s must be contiguous" % name)
+    if t.is_conj() or t.is_neg():
+        # a lazy conjugate/negative view: its memory holds the unconjugated values
+        raise ValueError("%s is a lazy conj/neg view; call resolve_conj()/resolve_neg() first" % name)
     if shape is not None and tuple(t.shape) != tuple(shape):
         raise ValueError("%s must have shape %s, got %s" % (name, tuple(shape), tuple(t.shape)))
 
@@ -398,6 +408,88 @@ def fock_threshold_probs_backward(batch: Batch, U: torch.Tensor, grad_out: torch
            lib().fock_threshold_probs_backward(batch.handle, _ptr(U), _ptr(grad_out), _ptr(out), wp, wn,
                                                _stream_ptr(U.device)))
     return out
+
+
+class Superposition:
+    """Amplitude-encoded inputs (slos_superposition_create): the batch's samples
+    are components; group g holds components [group_off[g], group_off[g+1])."""
+
+    def __init__(self, batch: Batch, group_off):
+        off = np.ascontiguousarray(np.asarray(group_off, dtype=np.int64).ravel())
+        h = _vp()
+        _check("slos_superposition_create",
+               lib().slos_superposition_create(batch.handle, off.size - 1, off.ctypes.data_as(_vp), ctypes.byref(h)))
+        self._h = h
+        self.batch = batch  # keep the batch alive
+        self.G = off.size - 1
+        self.group_off = off
+        self.out_len = int(lib().slos_superposition_out_len(h))
+        oo = np.zeros(self.G + 1, dtype=np.int64)
+        _check("slos_superposition_out_offsets", lib().slos_superposition_out_offsets(h, oo.ctypes.data_as(_vp)))
+        self.out_offsets = oo
+        self._ws = {}
+
+    @property
+    def handle(self):
+        return self._h
+
+    def workspace(self, backward: bool, device) -> torch.Tensor:
+        n = ctypes.c_size_t(0)
+        _check("slos_superposition_workspace_bytes",
+               lib().slos_superposition_workspace_bytes(self._h, int(backward), ctypes.byref(n)))
+        ws = self._ws.get(backward)
+        if ws is None or ws.numel() < n.value or ws.device != torch.device(device):
+            ws = torch.empty(max(int(n.value), 1), dtype=torch.uint8, device=device)
+            self._ws[backward] = ws
+        return ws
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            lib().slos_superposition_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def fock_superposition_amplitudes(sup: Superposition, U: torch.Tensor, x: torch.Tensor,
+                                  out: Optional[torch.Tensor] = None,
+                                  ws: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """sum_c x_c a(U_g, s_c) per group, complex64 [out_len] (ragged per group)."""
+    m = sup.batch.m
+    _require(U, "U", torch.complex64, (sup.G, m, m))
+    _require(x, "x", torch.complex64, (sup.batch.B,))
+    if out is None:
+        out = torch.empty(sup.out_len, dtype=torch.complex64, device=U.device)
+    _require(out, "out", torch.complex64, (sup.out_len,))
+    if ws is None:
+        ws = sup.workspace(False, U.device)
+    wp, wn = _ws_args(ws)
+    _check("fock_superposition_amplitudes",
+           lib().fock_superposition_amplitudes(sup.handle, _ptr(U), _ptr(x), _ptr(out), wp, wn, _stream_ptr(U.device)))
+    return out
+
+
+def fock_superposition_amplitudes_backward(sup: Superposition, U: torch.Tensor, x: torch.Tensor,
+                                           grad_out: torch.Tensor, need_grad_x: bool = True,
+                                           ws: Optional[torch.Tensor] = None):
+    """(dL/dU [G, m, m], dL/dx [C] or None) given dL/dout."""
+    m = sup.batch.m
+    _require(U, "U", torch.complex64, (sup.G, m, m))
+    _require(x, "x", torch.complex64, (sup.batch.B,))
+    _require(grad_out, "grad_out", torch.complex64, (sup.out_len,))
+    gU = torch.empty_like(U)
+    gx = torch.empty_like(x) if need_grad_x else None
+    if ws is None:
+        ws = sup.workspace(True, U.device)
+    wp, wn = _ws_args(ws)
+    _check("fock_superposition_amplitudes_backward",
+           lib().fock_superposition_amplitudes_backward(sup.handle, _ptr(U), _ptr(x), _ptr(grad_out), _ptr(gU),
+                                                        _ptr(gx), wp, wn, _stream_ptr(U.device)))
+    return gU, gx
 
 
 def fock_sample(batch: Batch, U: torch.Tensor, u: torch.Tensor, out: Optional[torch.Tensor] = None,

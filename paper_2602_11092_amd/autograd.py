@@ -12,12 +12,18 @@ import torch
 from . import _binding as B
 
 
+def _dense(t: torch.Tensor, dtype) -> torch.Tensor:
+    """Plain contiguous memory of t's values (autograd may hand over lazy
+    conjugate or negative views, whose memory holds other values)."""
+    return t.resolve_conj().resolve_neg().to(dtype).contiguous()
+
+
 class FockProbs(torch.autograd.Function):
     """U [B, m, m] complex64 -> probabilities float32 [out_len]."""
 
     @staticmethod
     def forward(ctx, U: torch.Tensor, batch: B.Batch):
-        U = U.contiguous()
+        U = _dense(U, torch.complex64)
         ctx.batch = batch
         ctx.save_for_backward(U)
         return B.fock_probs(batch, U)
@@ -25,7 +31,7 @@ class FockProbs(torch.autograd.Function):
     @staticmethod
     def backward(ctx, grad_p):
         (U,) = ctx.saved_tensors
-        gU = B.fock_probs_backward(ctx.batch, U, grad_p.contiguous().to(torch.float32))
+        gU = B.fock_probs_backward(ctx.batch, U, _dense(grad_p, torch.float32))
         return gU, None
 
 
@@ -34,7 +40,7 @@ class FockAmplitudes(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, U: torch.Tensor, batch: B.Batch):
-        U = U.contiguous()
+        U = _dense(U, torch.complex64)
         ctx.batch = batch
         ctx.save_for_backward(U)
         return B.fock_amplitudes(batch, U)
@@ -42,7 +48,7 @@ class FockAmplitudes(torch.autograd.Function):
     @staticmethod
     def backward(ctx, grad_a):
         (U,) = ctx.saved_tensors
-        gU = B.fock_amplitudes_backward(ctx.batch, U, grad_a.contiguous().to(torch.complex64))
+        gU = B.fock_amplitudes_backward(ctx.batch, U, _dense(grad_a, torch.complex64))
         return gU, None
 
 
@@ -51,7 +57,7 @@ class FockModeExpectations(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, U: torch.Tensor, batch: B.Batch):
-        U = U.contiguous()
+        U = _dense(U, torch.complex64)
         ctx.batch = batch
         ctx.save_for_backward(U)
         return B.fock_mode_expectations(batch, U)
@@ -59,7 +65,7 @@ class FockModeExpectations(torch.autograd.Function):
     @staticmethod
     def backward(ctx, grad_e):
         (U,) = ctx.saved_tensors
-        gU = B.fock_mode_expectations_backward(ctx.batch, U, grad_e.contiguous().to(torch.float32))
+        gU = B.fock_mode_expectations_backward(ctx.batch, U, _dense(grad_e, torch.float32))
         return gU, None
 
 
@@ -68,7 +74,7 @@ class FockThresholdProbs(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, U: torch.Tensor, batch: B.Batch):
-        U = U.contiguous()
+        U = _dense(U, torch.complex64)
         ctx.batch = batch
         ctx.save_for_backward(U)
         return B.fock_threshold_probs(batch, U)
@@ -76,8 +82,28 @@ class FockThresholdProbs(torch.autograd.Function):
     @staticmethod
     def backward(ctx, grad_P):
         (U,) = ctx.saved_tensors
-        gU = B.fock_threshold_probs_backward(ctx.batch, U, grad_P.contiguous().to(torch.float32))
+        gU = B.fock_threshold_probs_backward(ctx.batch, U, _dense(grad_P, torch.float32))
         return gU, None
+
+
+class FockSuperposition(torch.autograd.Function):
+    """U [G, m, m] and component weights x [C] (complex64) -> sum_c x_c U|s_c>
+    per group, complex64 [out_len]."""
+
+    @staticmethod
+    def forward(ctx, U: torch.Tensor, x: torch.Tensor, sup: B.Superposition):
+        U = _dense(U, torch.complex64)
+        x = _dense(x, torch.complex64)
+        ctx.sup = sup
+        ctx.save_for_backward(U, x)
+        return B.fock_superposition_amplitudes(sup, U, x)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        U, x = ctx.saved_tensors
+        gU, gx = B.fock_superposition_amplitudes_backward(ctx.sup, U, x, _dense(grad_out, torch.complex64),
+                                                          need_grad_x=ctx.needs_input_grad[1])
+        return gU, gx, None
 
 
 class MeshToUnitary(torch.autograd.Function):
@@ -101,7 +127,7 @@ class MeshToUnitary(torch.autograd.Function):
             (theta,) = ctx.saved_tensors
             x = None
         need_gx = ctx.has_x and ctx.needs_input_grad[1]
-        gt, gx = B.mesh_to_unitary_backward(theta, x, ctx.enc_scale, gU.contiguous(), need_grad_x=need_gx)
+        gt, gx = B.mesh_to_unitary_backward(theta, x, ctx.enc_scale, _dense(gU, torch.complex64), need_grad_x=need_gx)
         return gt, gx, None, None
 
 
@@ -119,6 +145,10 @@ def fock_mode_expectations(U: torch.Tensor, batch: B.Batch) -> torch.Tensor:
 
 def fock_threshold_probs(U: torch.Tensor, batch: B.Batch) -> torch.Tensor:
     return FockThresholdProbs.apply(U, batch)
+
+
+def fock_superposition_amplitudes(U: torch.Tensor, x: torch.Tensor, sup: B.Superposition) -> torch.Tensor:
+    return FockSuperposition.apply(U, x, sup)
 
 
 def mesh_to_unitary(theta: torch.Tensor, x: Optional[torch.Tensor], enc_scale: float = math.pi,

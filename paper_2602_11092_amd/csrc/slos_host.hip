@@ -795,6 +795,169 @@ extern "C" int fock_probs_backward(slos_batch_t batch, const float* U, const flo
     return run(batch, SLOS_OP_PROBS_BACKWARD, U, grad_probs, grad_U, ws, ws_bytes, stream);
 }
 
+// ------------------------------------------------------------ superpositions
+
+struct slos_superposition_s {
+    slos_batch_s* batch = nullptr;
+    std::vector<int64_t> goff, ooff;
+    void* dmem = nullptr;
+    SupDev dev;
+};
+
+namespace {
+
+size_t sup_ws_parts(const slos_superposition_s& S, bool bwd, size_t* uc, size_t* a, size_t* ga, size_t* guc,
+                    size_t* amp) {
+    const slos_batch_s& Bt = *S.batch;
+    const size_t mm = (size_t)Bt.plan->m * Bt.plan->m;
+    *uc = align256((size_t)Bt.B * mm * 8);
+    *a = align256((size_t)Bt.off_host[Bt.B] * 8);
+    *ga = bwd ? *a : 0;
+    *guc = bwd ? *uc : 0;
+    size_t w = 0;
+    slos_workspace_bytes(S.batch, SLOS_OP_AMPLITUDES, &w);
+    *amp = w;
+    if (bwd) {
+        slos_workspace_bytes(S.batch, SLOS_OP_AMPLITUDES_BACKWARD, &w);
+        *amp = std::max(*amp, w);
+    }
+    return *uc + *a + *ga + *guc + align256(*amp);
+}
+
+}  // namespace
+
+extern "C" int slos_superposition_create(slos_batch_t components, int G, const int64_t* group_off,
+                                         slos_superposition_t* out) {
+    if (!out) return fail(SLOS_EINVAL, "slos_superposition_create: out is NULL");
+    *out = nullptr;
+    if (!components || !group_off || G < 0) return fail(SLOS_EINVAL, "slos_superposition_create: bad argument");
+    const slos_batch_s& Bt = *components;
+    if (group_off[0] != 0 || group_off[G] != Bt.B)
+        return fail(SLOS_EINVAL, "slos_superposition_create: offsets must run from 0 to the batch size");
+    auto* S = new slos_superposition_s();
+    S->batch = components;
+    S->goff.assign(group_off, group_off + G + 1);
+    S->ooff.assign(G + 1, 0);
+    std::vector<int32_t> group(std::max(Bt.B, 1), 0);
+    int64_t maxN = 1;
+    for (int g = 0; g < G; ++g) {
+        const int64_t c0 = group_off[g], c1 = group_off[g + 1];
+        if (c1 < c0 || c1 - c0 < 1) {
+            delete S;
+            return fail(SLOS_EINVAL, "slos_superposition_create: every group needs at least one component");
+        }
+        const int n = Bt.n_host[c0];
+        for (int64_t c = c0; c < c1; ++c) {
+            if (Bt.n_host[c] != n) {
+                delete S;
+                return fail(SLOS_EINVAL, "slos_superposition_create: a group mixes photon numbers");
+            }
+            group[c] = g;
+        }
+        const int64_t N = Bt.plan->N[n];
+        S->ooff[g + 1] = S->ooff[g] + N;
+        maxN = std::max(maxN, N);
+    }
+    const size_t o_grp = 0, o_goff = align256((size_t)std::max(Bt.B, 1) * 4), o_ooff = o_goff + align256((G + 1) * 8);
+    const size_t total = o_ooff + align256((G + 1) * 8);
+    if (hipMalloc(&S->dmem, total) != hipSuccess) {
+        delete S;
+        return fail(SLOS_ENOMEM, "slos_superposition_create: hipMalloc failed");
+    }
+    char* base = (char*)S->dmem;
+    hipError_t e = hipMemcpy(base + o_grp, group.data(), group.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(base + o_goff, S->goff.data(), (G + 1) * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(base + o_ooff, S->ooff.data(), (G + 1) * 8, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        hipFree(S->dmem);
+        delete S;
+        return fail(SLOS_EHIP, "slos_superposition_create: upload failed");
+    }
+    S->dev.G = G;
+    S->dev.group = (const int32_t*)(base + o_grp);
+    S->dev.goff = (const int64_t*)(base + o_goff);
+    S->dev.ooff = (const int64_t*)(base + o_ooff);
+    S->dev.max_n_states = maxN;
+    *out = S;
+    return SLOS_OK;
+}
+
+extern "C" int slos_superposition_destroy(slos_superposition_t sup) {
+    if (!sup) return SLOS_OK;
+    hipDeviceSynchronize();
+    if (sup->dmem) hipFree(sup->dmem);
+    delete sup;
+    return SLOS_OK;
+}
+
+extern "C" int64_t slos_superposition_out_len(slos_superposition_t sup) { return sup ? sup->ooff.back() : -1; }
+
+extern "C" int slos_superposition_out_offsets(slos_superposition_t sup, int64_t* off_host) {
+    if (!sup || !off_host) return fail(SLOS_EINVAL, "slos_superposition_out_offsets: NULL argument");
+    std::memcpy(off_host, sup->ooff.data(), sup->ooff.size() * 8);
+    return SLOS_OK;
+}
+
+extern "C" int slos_superposition_workspace_bytes(slos_superposition_t sup, int backward, size_t* bytes) {
+    if (!sup || !bytes) return fail(SLOS_EINVAL, "slos_superposition_workspace_bytes: NULL argument");
+    size_t uc, a, ga, guc, amp;
+    *bytes = sup_ws_parts(*sup, backward != 0, &uc, &a, &ga, &guc, &amp);
+    return SLOS_OK;
+}
+
+extern "C" int fock_superposition_amplitudes(slos_superposition_t sup, const float* U, const float* x, float* out,
+                                             void* ws, size_t ws_bytes, void* stream) {
+    const std::string nm = "fock_superposition_amplitudes";
+    if (!sup) return fail(SLOS_EINVAL, nm + ": sup is NULL");
+    if (sup->dev.G == 0) return SLOS_OK;
+    if (!U || !x || !out) return fail(SLOS_EINVAL, nm + ": NULL device pointer");
+    size_t uc, a, ga, guc, amp;
+    const size_t need = sup_ws_parts(*sup, false, &uc, &a, &ga, &guc, &amp);
+    if (!ws || ws_bytes < need)
+        return fail(SLOS_EWORKSPACE, nm + ": workspace missing or too small (need " + std::to_string(need) + " bytes)");
+    char* base = (char*)ws;
+    float2* Uc = (float2*)base;
+    float2* A = (float2*)(base + uc);
+    void* rest = base + uc + a;
+    hipStream_t s = (hipStream_t)stream;
+    const slos_batch_s& Bt = *sup->batch;
+    int rc = launch_superposition(kSupReplicateU, sup->dev, Bt, U, nullptr, nullptr, Uc, s);
+    if (rc == SLOS_OK) rc = run(sup->batch, SLOS_OP_AMPLITUDES, (const float*)Uc, nullptr, A, rest, amp, stream);
+    if (rc == SLOS_OK) rc = launch_superposition(kSupCombine, sup->dev, Bt, x, A, nullptr, out, s);
+    return rc;
+}
+
+extern "C" int fock_superposition_amplitudes_backward(slos_superposition_t sup, const float* U, const float* x,
+                                                      const float* grad_out, float* grad_U, float* grad_x, void* ws,
+                                                      size_t ws_bytes, void* stream) {
+    const std::string nm = "fock_superposition_amplitudes_backward";
+    if (!sup) return fail(SLOS_EINVAL, nm + ": sup is NULL");
+    if (sup->dev.G == 0) return SLOS_OK;
+    if (!U || !x || !grad_out || !grad_U) return fail(SLOS_EINVAL, nm + ": NULL device pointer");
+    size_t uc, a, ga, guc, amp;
+    const size_t need = sup_ws_parts(*sup, true, &uc, &a, &ga, &guc, &amp);
+    if (!ws || ws_bytes < need)
+        return fail(SLOS_EWORKSPACE, nm + ": workspace missing or too small (need " + std::to_string(need) + " bytes)");
+    char* base = (char*)ws;
+    float2* Uc = (float2*)base;
+    float2* A = (float2*)(base + uc);
+    float2* gA = (float2*)(base + uc + a);
+    float2* gUc = (float2*)(base + uc + a + ga);
+    void* rest = base + uc + a + ga + guc;
+    hipStream_t s = (hipStream_t)stream;
+    const slos_batch_s& Bt = *sup->batch;
+    int rc = launch_superposition(kSupReplicateU, sup->dev, Bt, U, nullptr, nullptr, Uc, s);
+    if (rc == SLOS_OK && grad_x) {
+        rc = run(sup->batch, SLOS_OP_AMPLITUDES, (const float*)Uc, nullptr, A, rest, amp, stream);
+        if (rc == SLOS_OK) rc = launch_superposition(kSupGradX, sup->dev, Bt, A, grad_out, nullptr, grad_x, s);
+    }
+    if (rc == SLOS_OK) rc = launch_superposition(kSupExpand, sup->dev, Bt, x, grad_out, nullptr, gA, s);
+    if (rc == SLOS_OK)
+        rc = run(sup->batch, SLOS_OP_AMPLITUDES_BACKWARD, (const float*)Uc, gA, (float*)gUc, rest, amp, stream);
+    if (rc == SLOS_OK) rc = launch_superposition(kSupGroupSum, sup->dev, Bt, gUc, nullptr, nullptr, grad_U, s);
+    return rc;
+}
+
 extern "C" int fock_sample(slos_batch_t batch, const float* U, const float* u, int S, int32_t* shots, void* ws,
                            size_t ws_bytes, void* stream) {
     const std::string nm = "fock_sample";

@@ -140,6 +140,19 @@ int64_t threshold_dim(int m, int n);
 // shots[b][s] <- first t with cdf_b[t] > u[b][s] cdf_b[N_b - 1]; part: B * chunks doubles
 // (chunks = mode_expect_chunks), cdf: out_len doubles
 int64_t mode_expect_chunks(const slos_batch_s& Bt);
+
+// Amplitude-encoded inputs: the batch's samples are components; group g
+// holds components [goff[g], goff[g+1]) and owns outputs [ooff[g], ooff[g+1]).
+struct SupDev {
+    int G = 0;
+    const int32_t* group = nullptr;  // [C] group of each component
+    const int64_t* goff = nullptr;   // [G+1]
+    const int64_t* ooff = nullptr;   // [G+1]
+    int64_t max_n_states = 1;        // largest output block of a group
+};
+enum { kSupReplicateU, kSupCombine, kSupExpand, kSupGradX, kSupGroupSum };
+int launch_superposition(int kind, const SupDev& S, const slos_batch_s& Bt, const void* a0, const void* a1,
+                         const void* a2, void* out, hipStream_t stream);
 int launch_sample(const slos_batch_s& Bt, const float* p, double* part, double* cdf, const float* u, int S,
                   int32_t* shots, hipStream_t stream);
 

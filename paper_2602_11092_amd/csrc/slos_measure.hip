@@ -228,6 +228,109 @@ __global__ __launch_bounds__(kMeasureBlock) void sample_kernel(BatchDev Bt, cons
     shots[i] = (int32_t)lo;
 }
 
+// ---- amplitude-encoded inputs: components c in [goff[g], goff[g+1]) of group g
+
+// Uc[c] = U[group[c]]
+__global__ __launch_bounds__(kMeasureBlock) void replicate_u_kernel(int mm, int C, const int32_t* __restrict__ group,
+                                                                    const float2* __restrict__ U,
+                                                                    float2* __restrict__ Uc) {
+    const int64_t i = (int64_t)blockIdx.x * kMeasureBlock + threadIdx.x;
+    if (i >= (int64_t)C * mm) return;
+    const int64_t c = i / mm, e = i % mm;
+    Uc[i] = U[(int64_t)ldg(group + c) * mm + e];
+}
+
+// out[ooff[g] + t] = sum_c x_c A[off_c + t], components in order; workgroup
+// g * T + chunk covers kChunkStates output states of group g
+__global__ __launch_bounds__(kMeasureBlock) void combine_kernel(BatchDev Bt, const int64_t* __restrict__ goff,
+                                                                const int64_t* __restrict__ ooff, int T,
+                                                                const float2* __restrict__ x,
+                                                                const float2* __restrict__ A,
+                                                                float2* __restrict__ out) {
+    const int g = blockIdx.x / T, ch = blockIdx.x % T;
+    const int64_t c0 = ldg(goff + g), c1 = ldg(goff + g + 1);
+    const int64_t o = ldg(ooff + g), N = ldg(ooff + g + 1) - o;
+    const int64_t lo = (int64_t)ch * kChunkStates, hi = lo + kChunkStates < N ? lo + kChunkStates : N;
+    for (int64_t t = lo + threadIdx.x; t < hi; t += kMeasureBlock) {
+        float2 acc = make_float2(0.f, 0.f);
+        for (int64_t c = c0; c < c1; ++c) {
+            const float2 w = x[c], a = A[ldg(Bt.off + c) + t];
+            acc.x += w.x * a.x - w.y * a.y;
+            acc.y += w.x * a.y + w.y * a.x;
+        }
+        out[o + t] = acc;
+    }
+}
+
+// gA[off_c + t] = conj(x_c) G[ooff[group c] + t]; workgroup c * T + chunk
+__global__ __launch_bounds__(kMeasureBlock) void expand_sup_kernel(BatchDev Bt, const int32_t* __restrict__ group,
+                                                                   const int64_t* __restrict__ ooff, int T,
+                                                                   const float2* __restrict__ x,
+                                                                   const float2* __restrict__ G,
+                                                                   float2* __restrict__ gA) {
+    const int64_t c = blockIdx.x / T;
+    const int ch = blockIdx.x % T;
+    const int64_t off = ldg(Bt.off + c), N = ldg(Bt.off + c + 1) - off;
+    const int64_t o = ldg(ooff + ldg(group + c));
+    const float2 w = x[c];
+    const int64_t lo = (int64_t)ch * kChunkStates, hi = lo + kChunkStates < N ? lo + kChunkStates : N;
+    for (int64_t t = lo + threadIdx.x; t < hi; t += kMeasureBlock) {
+        const float2 gv = G[o + t];
+        gA[off + t] = make_float2(w.x * gv.x + w.y * gv.y, w.x * gv.y - w.y * gv.x);
+    }
+}
+
+// grad_x[c] = sum_t conj(A[off_c + t]) G[ooff[group c] + t], one workgroup per component
+__global__ __launch_bounds__(kMeasureBlock) void grad_x_kernel(BatchDev Bt, const int32_t* __restrict__ group,
+                                                               const int64_t* __restrict__ ooff,
+                                                               const float2* __restrict__ A,
+                                                               const float2* __restrict__ G,
+                                                               float2* __restrict__ gx) {
+    __shared__ double red[2][kMeasureBlock / 64];
+    const int64_t c = blockIdx.x;
+    const int64_t off = ldg(Bt.off + c), N = ldg(Bt.off + c + 1) - off;
+    const int64_t o = ldg(ooff + ldg(group + c));
+    double re = 0.0, im = 0.0;
+    for (int64_t t = threadIdx.x; t < N; t += kMeasureBlock) {
+        const float2 a = A[off + t], gv = G[o + t];
+        re += (double)a.x * gv.x + (double)a.y * gv.y;
+        im += (double)a.x * gv.y - (double)a.y * gv.x;
+    }
+    for (int s = 32; s >= 1; s >>= 1) {
+        re += __shfl_xor(re, s, 64);
+        im += __shfl_xor(im, s, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = re;
+        red[1][threadIdx.x >> 6] = im;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double r = 0.0, i = 0.0;
+        for (int w = 0; w < kMeasureBlock / 64; ++w) {
+            r += red[0][w];
+            i += red[1][w];
+        }
+        gx[c] = make_float2((float)r, (float)i);
+    }
+}
+
+// gU[g] = sum of gUc[c] over the group's components, in order
+__global__ __launch_bounds__(kMeasureBlock) void group_sum_kernel(int mm, int G, const int64_t* __restrict__ goff,
+                                                                  const float2* __restrict__ gUc,
+                                                                  float2* __restrict__ gU) {
+    const int64_t i = (int64_t)blockIdx.x * kMeasureBlock + threadIdx.x;
+    if (i >= (int64_t)G * mm) return;
+    const int64_t g = i / mm, e = i % mm;
+    float2 acc = make_float2(0.f, 0.f);
+    for (int64_t c = ldg(goff + g); c < ldg(goff + g + 1); ++c) {
+        const float2 v = gUc[c * mm + e];
+        acc.x += v.x;
+        acc.y += v.y;
+    }
+    gU[i] = acc;
+}
+
 int threshold_chunks(const slos_batch_s& Bt) {
     const int64_t Q = threshold_dim(Bt.plan->m, Bt.n_max);
     return (int)std::max<int64_t>(1, (Q + kChunkPatterns - 1) / kChunkPatterns);
@@ -270,6 +373,38 @@ int launch_sample(const slos_batch_s& Bt, const float* p, double* part, double* 
                             dim3(kMeasureBlock), a3, 0, stream);
     }
     if (e != hipSuccess) return fail(SLOS_EHIP, std::string("fock_sample launch: ") + hipGetErrorString(e));
+    return SLOS_OK;
+}
+
+static unsigned blocks_for(int64_t n) { return (unsigned)((n + kMeasureBlock - 1) / kMeasureBlock); }
+
+int launch_superposition(int kind, const SupDev& S, const slos_batch_s& Bt, const void* a0, const void* a1,
+                         const void* a2, void* outp, hipStream_t stream) {
+    const int m = Bt.plan->m, mm = m * m, C = Bt.B, G = S.G;
+    const int T = (int)std::max<int64_t>(1, (S.max_n_states + kChunkStates - 1) / kChunkStates);
+    hipError_t e = hipSuccess;
+    if (kind == kSupReplicateU) {
+        void* args[] = {(void*)&mm, (void*)&C, (void*)&S.group, (void*)&a0, (void*)&outp};
+        e = hipLaunchKernel((void*)&replicate_u_kernel, dim3(blocks_for((int64_t)C * mm)), dim3(kMeasureBlock), args, 0,
+                            stream);
+    } else if (kind == kSupCombine) {  // a0 = x, a1 = A
+        void* args[] = {(void*)&Bt.dev, (void*)&S.goff, (void*)&S.ooff, (void*)&T, (void*)&a0, (void*)&a1, (void*)&outp};
+        e = hipLaunchKernel((void*)&combine_kernel, dim3((unsigned)((int64_t)G * T)), dim3(kMeasureBlock), args, 0,
+                            stream);
+    } else if (kind == kSupExpand) {  // a0 = x, a1 = G
+        void* args[] = {(void*)&Bt.dev, (void*)&S.group, (void*)&S.ooff, (void*)&T, (void*)&a0, (void*)&a1, (void*)&outp};
+        e = hipLaunchKernel((void*)&expand_sup_kernel, dim3((unsigned)((int64_t)C * T)), dim3(kMeasureBlock), args, 0,
+                            stream);
+    } else if (kind == kSupGradX) {  // a0 = A, a1 = G
+        void* args[] = {(void*)&Bt.dev, (void*)&S.group, (void*)&S.ooff, (void*)&a0, (void*)&a1, (void*)&outp};
+        e = hipLaunchKernel((void*)&grad_x_kernel, dim3((unsigned)C), dim3(kMeasureBlock), args, 0, stream);
+    } else {  // kSupGroupSum, a0 = per-component gradients
+        void* args[] = {(void*)&mm, (void*)&G, (void*)&S.goff, (void*)&a0, (void*)&outp};
+        e = hipLaunchKernel((void*)&group_sum_kernel, dim3(blocks_for((int64_t)G * mm)), dim3(kMeasureBlock), args, 0,
+                            stream);
+    }
+    (void)a2;
+    if (e != hipSuccess) return fail(SLOS_EHIP, std::string("superposition kernel launch: ") + hipGetErrorString(e));
     return SLOS_OK;
 }
 

@@ -224,3 +224,25 @@ def test_fused_adjoint_every_workgroup_size(block):
         sl = slice(batch.offsets[b], batch.offsets[b + 1])
         ref = O.probs_grad(widen(U[b]), occ[b], gp[sl].astype(np.float64))
         assert rel_err(G[b], ref) <= G_RTOL, (block, b, rel_err(G[b], ref))
+
+
+def test_autograd_resolves_lazy_conjugate_gradients():
+    # L = Re(sum conj(a) w) hands the amplitude adjoint a lazily conjugated
+    # gradient view; the wrapper must pass its values, not its raw memory
+    from paper_2602_11092_amd.autograd import fock_amplitudes
+    rng = np.random.default_rng(17)
+    m, B_ = 5, 6
+    U64 = W.haar_unitaries(rng, B_, m)
+    occ = np.zeros((B_, m), dtype=np.int32)
+    occ[:, :3] = 1
+    batch = B.Batch(B.Plan(m, 3), occ)
+    U = to_dev_c64(U64).requires_grad_(True)
+    a = fock_amplitudes(U, batch)
+    w = torch.from_numpy((rng.standard_normal(batch.out_len) + 1j * rng.standard_normal(batch.out_len))
+                         .astype(np.complex64)).to(DEV)
+    (a.conj() * w).real.sum().backward()
+    direct = B.fock_amplitudes_backward(batch, U.detach(), w)
+    torch.cuda.synchronize()
+    assert torch.allclose(U.grad, direct, rtol=1e-6, atol=1e-7)
+    with pytest.raises(ValueError):
+        B.fock_amplitudes_backward(batch, U.detach(), w.conj())  # a lazy view is refused
