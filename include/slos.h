@@ -88,8 +88,9 @@ extern "C" {
  * QuantumBridge example of Sec. II-D uses it): only unbunched outputs,
  * t_j <= 1, C(m, n) of them, in the basis order above restricted to them.
  * The recursion stays exact (removing a photon keeps a state unbunched).
- * Input states may be bunched.  Such plans are forward-only: backward calls
- * return SLOS_EUNSUPPORTED.  Requires n_max <= m. */
+ * Input states may be bunched.  The adjoint runs in the layered variant
+ * (successors outside the space contribute nothing); the fused adjoint
+ * reports SLOS_EUNSUPPORTED.  Requires n_max <= m. */
 #define SLOS_PLAN_UNBUNCHED 2
 /* Dual-rail computation space (Sec. II-B: computation spaces; Sec. II-D:
  * the qubit-photon bridge): qubit g is the mode pair (2g, 2g+1) and every
@@ -97,8 +98,8 @@ extern "C" {
  * n = m/2 photons these are the 2^n logical states |q_0 ... q_{n-1}> (the
  * photon of qubit g in mode 2g + q_g), in big-endian binary order.  The
  * recursion stays exact (removing a photon keeps the constraint).  Inputs
- * may be any Fock state.  Forward-only like SLOS_PLAN_UNBUNCHED; requires
- * an even m and n_max <= m/2; excludes SLOS_PLAN_UNBUNCHED. */
+ * may be any Fock state.  Adjoint as for SLOS_PLAN_UNBUNCHED; requires an
+ * even m and n_max <= m/2; excludes SLOS_PLAN_UNBUNCHED. */
 #define SLOS_PLAN_DUAL_RAIL 4
 /* Also build the threshold-detector tables (Sec. II-B: detector models)
  * used by fock_threshold_probs: per photon layer, the states of each click
@@ -242,8 +243,8 @@ SLOS_API int fock_mode_expectations(slos_batch_t batch, const float* U, float* o
 /* grad_U (device, complex, [B][m][m]) <- dL/dU given grad_out = dL/d<n_j>
  * (device, float, [B][m]).  Forms dL/dp_t = sum_j t_j grad_out[b][j] in the
  * workspace (out_len floats) and runs the probability adjoint with the
- * configuration set for SLOS_OP_MODE_EXPECTATIONS_BACKWARD.  Full-space
- * plans with successor tables only (SLOS_EUNSUPPORTED otherwise). */
+ * configuration set for SLOS_OP_MODE_EXPECTATIONS_BACKWARD.  Plans with
+ * successor tables only (SLOS_EUNSUPPORTED otherwise). */
 SLOS_API int fock_mode_expectations_backward(slos_batch_t batch, const float* U, const float* grad_out,
                                              float* grad_U, void* ws, size_t ws_bytes, void* stream);
 
@@ -311,7 +312,7 @@ SLOS_API int fock_threshold_probs(slos_batch_t batch, const float* U, float* out
 
 /* grad_U <- dL/dU given grad_out = dL/dP (device, float, [threshold_len]):
  * dL/dp_t = dL/dP(pattern of t) in the workspace, then the probability
- * adjoint.  Full-space plans with successor tables only. */
+ * adjoint.  Plans with successor tables only. */
 SLOS_API int fock_threshold_probs_backward(slos_batch_t batch, const float* U, const float* grad_out,
                                            float* grad_U, void* ws, size_t ws_bytes, void* stream);
 

@@ -841,6 +841,10 @@ bool fused_bwd_supported(const slos_plan_s& P, int n_max, int block, std::string
         if (why) *why = "block must be 256, 512, 768 or 1024";
         return false;
     }
+    if (P.flags & (SLOS_PLAN_UNBUNCHED | SLOS_PLAN_DUAL_RAIL)) {
+        if (why) *why = "restricted spaces use the layered adjoint";
+        return false;
+    }
     if (!compact_tables(P, n_max)) {
         if (why) *why = "photon layers too large for compact tables";
         return false;

@@ -378,8 +378,8 @@ extern "C" int slos_plan_create(int m, int n_max, int flags, slos_plan_t* out) {
     P->num_cu = cu;
     P->max_lds = (size_t)lds;
 
-    // restricted spaces have no adjoint (t' + e_j can leave them): forward only
-    const bool want_succ = !(flags & SLOS_PLAN_FORWARD_ONLY) && group == 0;
+    // successors that leave a restricted space are marked (-1 << 3) for the layered adjoint
+    const bool want_succ = !(flags & SLOS_PLAN_FORWARD_ONLY);
     std::vector<HostLayer> H(n_max + 1);
     std::vector<int> shifts(n_max + 1, kPredShiftCompact);
     std::vector<Counter> C;
@@ -750,8 +750,6 @@ int run(slos_batch_t batch, int op, const float* U, const void* gin, void* out, 
     if (bwd && !gin) return fail(SLOS_EINVAL, nm + ": gradient input is NULL");
     if (bwd && (batch->plan->flags & SLOS_PLAN_FORWARD_ONLY))
         return fail(SLOS_EUNSUPPORTED, nm + ": plan was created forward-only");
-    if (bwd && flags_group(batch->plan->flags) != 0)
-        return fail(SLOS_EUNSUPPORTED, nm + ": unbunched and dual-rail plans are forward-only");
     int v, blk;
     resolve(*batch, op, &v, &blk);
     const bool probs = (op == SLOS_OP_PROBS || op == SLOS_OP_PROBS_BACKWARD);

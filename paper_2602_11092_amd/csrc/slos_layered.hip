@@ -153,7 +153,12 @@ __global__ __launch_bounds__(BLOCK) void layered_layer_kernel(int m, const Layer
 // padding successors and zero coefficients and are never written out),
 // loads the successors of four modes at once, and the block adds the lanes
 // of each sample in a fixed order through an LDS window of 8 modes.
-template <int BLOCK, int MMAX>
+// RESTRICTED: plans of a restricted space, whose successor tables mark
+// successors outside the space with kNoSuccessor; those pairs contribute
+// nothing (the forward never formed such states).
+constexpr uint32_t kNoSuccessor = 0xFFFFFFF8u;  // (uint32)(-1) << 3
+
+template <int BLOCK, int MMAX, bool RESTRICTED>
 __global__ __launch_bounds__(BLOCK) void layered_pull_kernel(int m, const LayerDev* __restrict__ Ls, BatchDev Bt,
                                                              const float2* __restrict__ U, int k,
                                                              const float2* __restrict__ gk, float2* __restrict__ gkm1,
@@ -200,7 +205,15 @@ __global__ __launch_bounds__(BLOCK) void layered_pull_kernel(int m, const LayerD
                 const uint32_t sv[4] = {s4.x, s4.y, s4.z, s4.w};
                 float2 gv[4];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) gv[q] = gkg[(size_t)(sv[q] >> 3) * SG];
+                for (int q = 0; q < 4; ++q) {
+                    if (RESTRICTED) {
+                        const bool none = sv[q] == kNoSuccessor;
+                        const float2 v = gkg[(size_t)((none ? 0u : sv[q]) >> 3) * SG];
+                        gv[q] = none ? c_zero() : v;
+                    } else {
+                        gv[q] = gkg[(size_t)(sv[q] >> 3) * SG];
+                    }
+                }
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     c_fma_conj(acc, us[bl * kUcolSlots + 4 * q4 + q], gv[q]);
@@ -337,14 +350,17 @@ int launch_layered_fwd(const slos_batch_s& Bt, int block, const float2* U, void*
     return SLOS_OK;
 }
 
-static void* pull_fn(int m) {
-    if (m <= 8) return (void*)&layered_pull_kernel<256, 8>;
-    if (m <= 12) return (void*)&layered_pull_kernel<256, 12>;
-    if (m <= 16) return (void*)&layered_pull_kernel<256, 16>;
-    if (m <= 20) return (void*)&layered_pull_kernel<256, 20>;
-    if (m <= 24) return (void*)&layered_pull_kernel<256, 24>;
-    return (void*)&layered_pull_kernel<256, 32>;
+template <bool R>
+static void* pull_fn_r(int m) {
+    if (m <= 8) return (void*)&layered_pull_kernel<256, 8, R>;
+    if (m <= 12) return (void*)&layered_pull_kernel<256, 12, R>;
+    if (m <= 16) return (void*)&layered_pull_kernel<256, 16, R>;
+    if (m <= 20) return (void*)&layered_pull_kernel<256, 20, R>;
+    if (m <= 24) return (void*)&layered_pull_kernel<256, 24, R>;
+    return (void*)&layered_pull_kernel<256, 32, R>;
 }
+
+static void* pull_fn(int m, bool restricted) { return restricted ? pull_fn_r<true>(m) : pull_fn_r<false>(m); }
 
 int launch_layered_bwd(const slos_batch_s& Bt, int block, const float2* U, const void* gin, bool probs, float2* gU,
                        void* ws, hipStream_t stream) {
@@ -371,7 +387,8 @@ int launch_layered_bwd(const slos_batch_s& Bt, int block, const float2* U, const
         const float2* dkm1 = store(k - 1);
         void* args[] = {(void*)&m, (void*)&Ls, (void*)&Bt.dev, (void*)&U, (void*)&k, (void*)&gk,
                         (void*)&gkm1, (void*)&dkm1, (void*)&partial, (void*)&SG, (void*)&NGRP};
-        hipError_t e = hipLaunchKernel(pull_fn(m), dim3(sh.GX, NGRP), dim3(256), args, 0, stream);
+        const bool restricted = (P.flags & (SLOS_PLAN_UNBUNCHED | SLOS_PLAN_DUAL_RAIL)) != 0;
+        hipError_t e = hipLaunchKernel(pull_fn(m, restricted), dim3(sh.GX, NGRP), dim3(256), args, 0, stream);
         if (e != hipSuccess) return fail(SLOS_EHIP, std::string("layered pull launch: ") + hipGetErrorString(e));
     }
     int GX = sh.GX;

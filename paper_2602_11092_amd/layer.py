@@ -24,8 +24,8 @@ class QuantumLayer(nn.Module):
     computation_space="unbunched" keeps only the output states with at most
     one photon per mode (C(m, n) of them, in the same relative order);
     "dual_rail" keeps those with at most one photon per mode pair (2g, 2g+1)
-    (the 2^n logical states when n = m/2).  Both are forward-only, so they
-    need torch.no_grad() or a theta without grad."""
+    (the 2^n logical states when n = m/2).  Their adjoint runs in the
+    layered kernels."""
 
     def __init__(self, m: int, input_state: Sequence[int], enc_scale: float = math.pi,
                  measurement: str = "probs", seed: int = 0, computation_space: str = "fock"):
@@ -75,8 +75,6 @@ class QuantumLayer(nn.Module):
         return bt
 
     def forward(self, x: torch.Tensor) -> torch.Tensor:
-        if self.computation_space != "fock" and torch.is_grad_enabled() and self.theta.requires_grad:
-            raise RuntimeError("the %s computation space is forward-only: use torch.no_grad()" % self.computation_space)
         U = mesh_to_unitary(self.theta, x.to(torch.float32), self.enc_scale, self.m)
         bt = self._batch(x.shape[0])
         if self.measurement == "probs":

@@ -14,7 +14,7 @@ import workloads as W
 from oracle import oracle as O
 from paper_2602_11092_amd import QuantumLayer
 from paper_2602_11092_amd import _binding as B
-from tests.gpu_util import A_TOL, DEV, P_TOL, run_forward, say, to_dev_c64, widen
+from tests.gpu_util import A_TOL, DEV, G_RTOL, P_TOL, rel_err, run_forward, say, to_dev_c64, widen
 
 pytestmark = pytest.mark.gpu
 
@@ -133,21 +133,57 @@ def test_unbunched_m24_n8_sampled():
         assert np.abs(pb[b, ranks] - ref).max() <= P_TOL
 
 
-def test_unbunched_backward_is_rejected():
-    rng = np.random.default_rng(1)
-    U, occ = _batch(rng, 4, 6, 3, 3, False)
-    batch = B.Batch(B.Plan(6, 3, unbunched=True), occ)
-    Ud = to_dev_c64(U)
-    g = torch.ones(batch.out_len, dtype=torch.float32, device=DEV)
+@pytest.mark.parametrize("space", ["unbunched", "dual_rail"])
+def test_restricted_backward_against_oracle(space):
+    # the layered adjoint on a restricted plan: the gradient of a loss of the
+    # restricted probabilities only (successors outside the space contribute nothing)
+    m = 8
+    dual = space == "dual_rail"
+    rng = np.random.default_rng(11)
+    U, occ = _batch(rng, 12, m, 1, 4, True)
+    plan = B.Plan(m, 4, unbunched=not dual, dual_rail=dual)
+    batch = B.Batch(plan, occ)
+    assert batch.get_config(B.OP_PROBS_BACKWARD)[0] == B.VARIANT_LAYERED
     with pytest.raises(B.SlosError):
-        B.fock_probs_backward(batch, Ud, g)
-    layer = QuantumLayer(6, [1, 1, 1, 0, 0, 0], computation_space="unbunched").to(DEV)
-    x = torch.zeros(2, 6, device=DEV)
-    with pytest.raises(RuntimeError):
-        layer(x)
-    with torch.no_grad():
-        p = layer(x)
-    assert p.shape == (2, 20)
+        batch.set_config(B.OP_PROBS_BACKWARD, B.VARIANT_FUSED, 256)
+    Ud = to_dev_c64(U)
+    gp = rng.standard_normal(batch.out_len).astype(np.float32)
+    say("restricted backward", space)
+    gU = B.fock_probs_backward(batch, Ud, torch.from_numpy(gp).to(DEV))
+    ga = (rng.standard_normal(batch.out_len) + 1j * rng.standard_normal(batch.out_len)).astype(np.complex64)
+    gUa = B.fock_amplitudes_backward(batch, Ud, torch.from_numpy(ga).to(DEV))
+    torch.cuda.synchronize()
+    gU, gUa = gU.cpu().numpy(), gUa.cpu().numpy()
+    for b in range(12):
+        n = int(occ[b].sum())
+        outs = O.fock_basis(m, n)
+        keep = outs.reshape(len(outs), -1, 2).sum(2).max(1) <= 1 if dual else outs.max(1) <= 1
+        o0, o1 = batch.offsets[b], batch.offsets[b + 1]
+        ref = O.probs_grad(widen(U[b]), occ[b], gp[o0:o1].astype(np.float64), outputs=outs[keep])
+        assert rel_err(gU[b], ref) <= G_RTOL, (b, rel_err(gU[b], ref))
+        refa = O.amplitude_grad(widen(U[b]), occ[b], ga[o0:o1].astype(np.complex128), outputs=outs[keep])
+        assert rel_err(gUa[b], refa) <= G_RTOL, (b, rel_err(gUa[b], refa))
+
+
+def test_restricted_layer_trains():
+    # autograd through the mesh on the unbunched space against the oracle chain
+    m, occ = 6, [1, 1, 1, 0, 0, 0]
+    layer = QuantumLayer(m, occ, computation_space="unbunched").to(DEV)
+    rng = np.random.default_rng(4)
+    x = torch.from_numpy(rng.standard_normal((3, m)).astype(np.float32)).to(DEV).requires_grad_(True)
+    w = torch.from_numpy(rng.standard_normal((3, 20)).astype(np.float32)).to(DEV)
+    p = layer(x)
+    assert p.shape == (3, 20)
+    (p * w).sum().backward()
+    torch.cuda.synchronize()
+    th = layer.theta.detach().cpu().numpy().astype(np.float64)
+    xx = x.detach().cpu().numpy().astype(np.float64)
+    Us = O.encoded_unitaries(th, xx, math.pi)
+    outs = _outputs(m, 3)
+    GU = np.stack([O.probs_grad(Us[b], occ, w[b].cpu().numpy().astype(np.float64), outputs=outs) for b in range(3)])
+    rt, rx = O.mesh_grad(th, xx, math.pi, GU)
+    assert rel_err(layer.theta.grad.cpu().numpy(), rt) <= G_RTOL
+    assert rel_err(x.grad.cpu().numpy(), rx) <= G_RTOL
 
 
 # ------------------------------------------------------------------ dual-rail
@@ -226,7 +262,7 @@ def test_dual_rail_m24_q12_sampled():
         assert np.abs(p[b, idx] - ref).max() <= P_TOL
 
 
-def test_dual_rail_is_the_fock_subvector_and_forward_only():
+def test_dual_rail_is_the_fock_subvector():
     m, n = 10, 3
     rng = np.random.default_rng(13)
     U, occ = _batch(rng, 12, m, n, n, True)
@@ -236,5 +272,3 @@ def test_dual_rail_is_the_fock_subvector_and_forward_only():
     pf = run_forward(B.Batch(B.Plan(m, n), occ), Ud, False).reshape(12, -1)
     keep = np.array([int(t.reshape(-1, 2).sum(1).max()) <= 1 for t in O.fock_basis(m, n)])
     assert np.abs(pd - pf[:, keep]).max() <= 1e-6
-    with pytest.raises(B.SlosError):
-        B.fock_probs_backward(bd, Ud, torch.ones(bd.out_len, dtype=torch.float32, device=DEV))
