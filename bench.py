@@ -77,6 +77,8 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
+    if args.workload in EXTENSIONS:
+        return bench_extension(args, dev)
     wl = W.make(args.workload)
     if wl.theta is None or not wl.backward or not (wl.n == wl.n.max()).all():
         return bench_other(args, wl, dev)
@@ -392,6 +394,161 @@ def bench_other(args, wl, dev):
                       "autotuned": {str(op): "%s/%d" % (names[t["variant"]], t["block"]) for op, t in tuned.items()}},
            "roofline": None, "cpu_baseline": None}
     print(json.dumps(out), flush=True)
+
+
+# Workloads of the measurement, encoding and kernel extensions (one line each).
+EXTENSIONS = ("expectations_clements_m20_n5_b512", "threshold_clements_m20_n5_b512",
+              "sample_clements_m20_n5_b512_s1024", "unbunched_haar_m24_n8_b16",
+              "superposition_m6_n3_g1024", "fidelity_m6_n4_b1024")
+FP64_PEAK = 78.6  # TFLOP/s, MI355X vector FP64 (equal to its unpacked FP32 rate)
+
+
+def slos_fwd_flop(m, n, flags=0, B=None):
+    """Algorithmic flops of one forward: sum_k k N_k complex MACs (8 flops)."""
+    from paper_2602_11092_amd import _binding as Bd
+    return 8.0 * sum(k * Bd.slos_space_dim(m, k, flags) for k in range(1, n + 1))
+
+
+def bench_extension(args, dev):
+    """One line per extension workload: HIP-event time of its entry point on
+    the launch stream, an ALU roofline from its algorithmic flops, and the
+    FP64 oracle timed on a bounded sample beside it."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from oracle import oracle as O
+    from paper_2602_11092_amd import _binding as B
+
+    name = args.workload
+    stream = torch.cuda.current_stream()
+    oracle_units = None  # units of `unit` one oracle call covers (default: one sample's share)
+    rng = np.random.default_rng(2602)
+    cpu_budget = 0.0 if args.no_cpu_baseline else 8.0  # seconds of oracle work
+    if name.endswith("clements_m20_n5_b512") or name.startswith("sample_clements"):
+        wl = W.make("clements_m20_n5_b512")
+        m, n, Bn, occ = 20, 5, wl.B, wl.occ
+        U64 = O.encoded_unitaries(wl.theta.astype(np.float64), wl.x.astype(np.float64), wl.enc_scale)
+    elif name == "unbunched_haar_m24_n8_b16":
+        wl = W.make("haar_m24_n8_b16")
+        m, n, Bn, occ = 24, 8, wl.B, wl.occ
+        U64 = wl.U.astype(np.complex128)
+    elif name == "superposition_m6_n3_g1024":
+        m, n, Bn = 6, 3, 1024
+        basis = O.fock_basis(m, n)
+        occ = np.tile(basis, (Bn, 1)).astype(np.int32)
+        U64 = W.haar_unitaries(rng, Bn, m)
+    else:  # fidelity_m6_n4_b1024: the paper's kernel example shape, Gram of 1024 states
+        m, n, Bn = 6, 4, 1024
+        occ = np.array([1, 1, 1, 1, 0, 0], dtype=np.int32)
+        U64 = W.haar_unitaries(rng, Bn, m)
+    U = torch.from_numpy(U64.astype(np.complex64)).to(dev)
+    Uh = U.cpu().numpy().astype(np.complex128)
+
+    if name.startswith("expectations"):
+        batch = B.Batch(B.Plan(m, n), occ)
+        out = torch.empty((Bn, m), dtype=torch.float32, device=dev)
+        ws = batch.workspace(B.OP_MODE_EXPECTATIONS, dev)
+        step = lambda: B.fock_mode_expectations(batch, U, out=out, ws=ws)
+        work, unit = Bn * math.comb(m + n - 1, n), "Fock states/s"
+        flop = Bn * slos_fwd_flop(m, n)
+        oracle_one = lambda b: O.mode_expectations(Uh[b], occ[b])
+        check = lambda b, r: float(np.abs(out[b].cpu().numpy() - r).max())
+        cfg = "fused last-layer epilogue, p never written"
+    elif name.startswith("threshold"):
+        batch = B.Batch(B.Plan(m, n, threshold=True), occ)
+        out = torch.empty(batch.threshold_len, dtype=torch.float32, device=dev)
+        ws = batch.workspace(B.OP_THRESHOLD_PROBS, dev)
+        step = lambda: B.fock_threshold_probs(batch, U, out=out, ws=ws)
+        work, unit = Bn * math.comb(m + n - 1, n), "Fock states/s"
+        flop = Bn * slos_fwd_flop(m, n)
+        oracle_one = lambda b: O.threshold_probs(Uh[b], occ[b])
+        toff = batch.threshold_offsets
+        check = lambda b, r: float(np.abs(out[toff[b]:toff[b + 1]].cpu().numpy() - r).max())
+        cfg = "probabilities, then per-pattern gather"
+    elif name.startswith("sample"):
+        S = 1024
+        batch = B.Batch(B.Plan(m, n), occ)
+        u = torch.from_numpy(rng.random((Bn, S)).astype(np.float32)).to(dev)
+        out = torch.empty((Bn, S), dtype=torch.int32, device=dev)
+        ws = batch.workspace(B.OP_SAMPLE, dev)
+        step = lambda: B.fock_sample(batch, U, u, out=out, ws=ws)
+        work, unit = Bn * S, "shots/s"
+        flop = Bn * slos_fwd_flop(m, n)
+        uh = u.cpu().numpy().astype(np.float64)
+        oracle_one = lambda b: O.sample_shots(Uh[b], occ[b], uh[b])
+        check = lambda b, r: float(np.mean(out[b].cpu().numpy() != r))  # fraction differing (boundary ties)
+        cfg = "probabilities, FP64 cumulative sums, binary search; 1024 shots per sample"
+    elif name.startswith("unbunched"):
+        batch = B.Batch(B.Plan(m, n, unbunched=True), occ)
+        out = torch.empty(batch.out_len, dtype=torch.float32, device=dev)
+        ws = batch.workspace(B.OP_PROBS, dev)
+        step = lambda: B.fock_probs(batch, U, out=out, ws=ws)
+        work, unit = batch.out_len, "Fock amplitudes/s"
+        flop = Bn * slos_fwd_flop(m, n, B.PLAN_UNBUNCHED)
+        outs = np.zeros((math.comb(m, n), m), dtype=np.int32)
+        for r, c in enumerate(__import__("itertools").combinations(range(m), n)):
+            outs[r, list(c)] = 1
+        pick = rng.integers(0, len(outs), 64)
+        N = len(outs)
+        oracle_one = lambda b: O.probabilities(Uh[b], occ[b], outs[pick])
+        check = lambda b, r: float(np.abs(out[b * N + pick].cpu().numpy() - r).max())
+        cfg = "unbunched space, probabilities (oracle on 64 sampled outputs per sample)"
+        oracle_units = 64
+    elif name.startswith("superposition"):
+        N = math.comb(m + n - 1, n)
+        batch = B.Batch(B.Plan(m, n), occ)
+        sup = B.Superposition(batch, np.arange(Bn + 1) * N)
+        Ug = U
+        x = torch.from_numpy((rng.standard_normal(Bn * N) + 1j * rng.standard_normal(Bn * N)).astype(np.complex64)).to(dev)
+        out = torch.empty(sup.out_len, dtype=torch.complex64, device=dev)
+        ws = sup.workspace(False, dev)
+        step = lambda: B.fock_superposition_amplitudes(sup, Ug, x, out=out, ws=ws)
+        work, unit = Bn * N, "output amplitudes/s"
+        flop = Bn * N * (slos_fwd_flop(m, n) + 8.0 * N)  # one SLOS per component + the weighted combine
+        xh = x.cpu().numpy().astype(np.complex128)
+        oracle_one = lambda b: O.superposition_amplitudes(Uh[b], occ[b * N:(b + 1) * N], xh[b * N:(b + 1) * N])
+        check = lambda b, r: float(np.abs(out[b * N:(b + 1) * N].cpu().numpy() - r).max())
+        cfg = "dense inputs: every basis state a component; one SLOS per component + combine"
+    else:
+        out = torch.empty((Bn, Bn), dtype=torch.float32, device=dev)
+        step = lambda: B.fock_fidelity_kernel(occ, U, out=out)
+        work, unit = Bn * Bn, "kernel entries/s"
+        flop = Bn * Bn * (8.0 * n * n * m + (2 ** n) * (2 * n + 6 * (n - 1)))
+        oracle_one = lambda b: np.array([O.fidelity(Uh[b], Uh[c], occ) for c in range(32)])
+        check = lambda b, r: float(np.abs(out[b, :32].cpu().numpy() - r).max())
+        cfg = "thread per pair, FP64 Ryser with unrolled Gray code (oracle: 32 entries per sampled row)"
+        oracle_units = 32
+
+    for _ in range(args.warmup):
+        step()
+    ms = time_region(step, args.steps, stream)
+    achieved = flop / (ms * 1e-3) / 1e12
+    line = {"metric": "%s throughput (%s)" % (name.split("_")[0], name), "value": work / (ms * 1e-3), "unit": unit,
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f64" if name.startswith("fidelity") else "c64",
+            "data": "synthetic", "config": {"workload": name, "m": m, "n": n, "batch": Bn, "path": cfg,
+                                            "launch": "eager"},
+            "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_PEAK, "unit": "TFLOP/s",
+                         "frac": round(achieved / FP64_PEAK, 4), "traffic": None,
+                         "algorithmic_flop": flop},
+            "cpu_baseline": None}
+    if cpu_budget > 0:
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
+        torch.cuda.synchronize()
+        O.build(force=False)
+        t0 = time.perf_counter()
+        done, worst = 0, 0.0
+        while done < Bn and time.perf_counter() - t0 < cpu_budget:
+            worst = max(worst, check(done, oracle_one(done)))
+            done += 1
+        dt = time.perf_counter() - t0
+        per = oracle_units or work / Bn
+        line["cpu_baseline"] = {"value": done * per / dt, "unit": unit, "cores": threads, "kind": "oracle",
+                                "sample": "%d of %d samples (rows), %d %s each" % (done, Bn, per, unit.split("/")[0]),
+                                "seconds": round(dt, 2),
+                                "max_diff_vs_gpu": worst}
+    print(json.dumps(line), flush=True)
 
 
 def load_traffic(kernel):
