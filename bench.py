@@ -399,7 +399,8 @@ def bench_other(args, wl, dev):
 # Workloads of the measurement, encoding and kernel extensions (one line each).
 EXTENSIONS = ("expectations_clements_m20_n5_b512", "threshold_clements_m20_n5_b512",
               "sample_clements_m20_n5_b512_s1024", "unbunched_haar_m24_n8_b16",
-              "superposition_m6_n3_g1024", "fidelity_m6_n4_b1024")
+              "superposition_m6_n3_g1024", "superposition_shared_m8_n4_g4096", "fidelity_m6_n4_b1024")
+FP32_MFMA_PEAK = 157.3  # TFLOP/s, MI355X dense FP32 matrix-core rate
 FP64_PEAK = 78.6  # TFLOP/s, MI355X vector FP64 (equal to its unpacked FP32 rate)
 
 
@@ -433,6 +434,10 @@ def bench_extension(args, dev):
         wl = W.make("haar_m24_n8_b16")
         m, n, Bn, occ = 24, 8, wl.B, wl.occ
         U64 = wl.U.astype(np.complex128)
+    elif name == "superposition_shared_m8_n4_g4096":
+        m, n, Bn = 8, 4, 4096
+        U64 = W.haar_unitaries(rng, 1, m)
+        occ = None
     elif name == "superposition_m6_n3_g1024":
         m, n, Bn = 6, 3, 1024
         basis = O.fock_basis(m, n)
@@ -495,6 +500,26 @@ def bench_extension(args, dev):
         check = lambda b, r: float(np.abs(out[b * N + pick].cpu().numpy() - r).max())
         cfg = "unbunched space, probabilities (oracle on 64 sampled outputs per sample)"
         oracle_units = 64
+    elif name.startswith("superposition_shared"):
+        ss = B.SharedSuperposition(B.Plan(m, n), n)
+        N = ss.N
+        Uone = U[0].contiguous()
+        X = torch.from_numpy(((rng.standard_normal((Bn, N)) + 1j * rng.standard_normal((Bn, N))) / np.sqrt(2 * N))
+                             .astype(np.complex64)).to(dev)
+        out = torch.empty((Bn, N), dtype=torch.complex64, device=dev)
+        step = lambda: B.fock_shared_superposition_amplitudes(ss, Uone, X, out=out)
+        work, unit = Bn * N, "output amplitudes/s"
+        gemm_flop = 8.0 * Bn * N * N
+        flop = gemm_flop + N * slos_fwd_flop(m, n)
+        basis = O.fock_basis(m, n)
+        A_ref = {}
+
+        def oracle_one(b):
+            if "A" not in A_ref:  # Uhat's rows, built once like the kernel's
+                A_ref["A"] = np.stack([O.amplitudes(Uh[0], basis[c]) for c in range(N)])
+            return X[b].cpu().numpy().astype(np.complex128) @ A_ref["A"]
+        check = lambda b, r: float(np.abs(out[b].cpu().numpy() - r).max())
+        cfg = "one U for every input: Uhat built by %d SLOS runs, then one complex GEMM (rocBLAS cgemm)" % N
     elif name.startswith("superposition"):
         N = math.comb(m + n - 1, n)
         batch = B.Batch(B.Plan(m, n), occ)
@@ -529,9 +554,12 @@ def bench_extension(args, dev):
             "scaling": "weak", "vs_baseline": None, "dtype": "f64" if name.startswith("fidelity") else "c64",
             "data": "synthetic", "config": {"workload": name, "m": m, "n": n, "batch": Bn, "path": cfg,
                                             "launch": "eager"},
-            "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_PEAK, "unit": "TFLOP/s",
-                         "frac": round(achieved / FP64_PEAK, 4), "traffic": None,
-                         "algorithmic_flop": flop},
+            "roofline": ({"bound": "mfma", "achieved": round(achieved, 3), "peak": FP32_MFMA_PEAK, "unit": "TFLOP/s",
+                          "frac": round(achieved / FP32_MFMA_PEAK, 4), "traffic": None, "algorithmic_flop": flop}
+                         if name.startswith("superposition_shared") else
+                         {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_PEAK, "unit": "TFLOP/s",
+                          "frac": round(achieved / FP64_PEAK, 4), "traffic": None,
+                          "algorithmic_flop": flop}),
             "cpu_baseline": None}
     if cpu_budget > 0:
         threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()

@@ -287,6 +287,26 @@ SLOS_API int fock_superposition_amplitudes_backward(slos_superposition_t sup, co
                                                     const float* grad_out, float* grad_U, float* grad_x,
                                                     void* ws, size_t ws_bytes, void* stream);
 
+/* Inputs that all go through one interferometer, each a dense vector over
+ * the n-photon basis (basis order): Uhat, U's n-photon representation, is
+ * built once per call (one SLOS per basis state, A[c][t] = a_t(U, basis_c))
+ * and the G inputs go through a complex GEMM, out = X A (rocBLAS cgemm on
+ * the caller's stream).  The object owns its buffers (about 2 N^2 complex
+ * plus the basis batch); calls that share it on one device race.  At most
+ * 16384 basis states (SLOS_EUNSUPPORTED beyond). */
+typedef struct slos_shared_superposition_s* slos_shared_superposition_t;
+SLOS_API int slos_shared_superposition_create(slos_plan_t plan, int n, slos_shared_superposition_t* out);
+SLOS_API int slos_shared_superposition_destroy(slos_shared_superposition_t s);
+SLOS_API int64_t slos_shared_superposition_dim(slos_shared_superposition_t s);
+/* out, X: device, complex, [G][N] row-major; U: device, complex, [m][m]. */
+SLOS_API int fock_shared_superposition_amplitudes(slos_shared_superposition_t s, const float* U, const float* X,
+                                                  int G, float* out, void* stream);
+/* grad_U [m][m] <- dL/dU; grad_X [G][N] (may be NULL) <- dL/dX, from
+ * grad_out = dL/dout [G][N] (dL/dRe + i dL/dIm convention). */
+SLOS_API int fock_shared_superposition_amplitudes_backward(slos_shared_superposition_t s, const float* U,
+                                                           const float* X, int G, const float* grad_out,
+                                                           float* grad_U, float* grad_X, void* stream);
+
 /* ---- Measurement: threshold detectors (Sec. II-B: detector models) ------- */
 
 /* Number of click patterns of n photons over m modes: the non-empty sets of

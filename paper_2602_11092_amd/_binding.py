@@ -83,6 +83,11 @@ SIGNATURES = {
     "slos_superposition_workspace_bytes": (_c.c_int, [_vp, _c.c_int, _vp]),
     "fock_superposition_amplitudes": (_c.c_int, [_vp, _vp, _vp, _vp, _vp, _c.c_size_t, _vp]),
     "fock_superposition_amplitudes_backward": (_c.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _c.c_size_t, _vp]),
+    "slos_shared_superposition_create": (_c.c_int, [_vp, _c.c_int, _vp]),
+    "slos_shared_superposition_destroy": (_c.c_int, [_vp]),
+    "slos_shared_superposition_dim": (_c.c_int64, [_vp]),
+    "fock_shared_superposition_amplitudes": (_c.c_int, [_vp, _vp, _vp, _c.c_int, _vp, _vp]),
+    "fock_shared_superposition_amplitudes_backward": (_c.c_int, [_vp, _vp, _vp, _c.c_int, _vp, _vp, _vp, _vp]),
     "fock_sample": (_c.c_int, [_vp, _vp, _vp, _c.c_int, _vp, _vp, _c.c_size_t, _vp]),
     "fock_fidelity_kernel": (_c.c_int, [_c.c_int, _vp, _vp, _c.c_int, _vp, _c.c_int, _vp, _vp]),
     "mesh_workspace_bytes": (_c.c_int, [_c.c_int, _c.c_int, _c.POINTER(_c.c_size_t)]),
@@ -490,6 +495,65 @@ def fock_superposition_amplitudes_backward(sup: Superposition, U: torch.Tensor, 
            lib().fock_superposition_amplitudes_backward(sup.handle, _ptr(U), _ptr(x), _ptr(grad_out), _ptr(gU),
                                                         _ptr(gx), wp, wn, _stream_ptr(U.device)))
     return gU, gx
+
+
+class SharedSuperposition:
+    """Dense inputs over the n-photon basis that all go through one U
+    (slos_shared_superposition_create): out = X Uhat^T by one complex GEMM."""
+
+    def __init__(self, plan: Plan, n: int):
+        h = _vp()
+        _check("slos_shared_superposition_create", lib().slos_shared_superposition_create(plan.handle, n, ctypes.byref(h)))
+        self._h = h
+        self.plan = plan
+        self.m = plan.m
+        self.n = n
+        self.N = int(lib().slos_shared_superposition_dim(h))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            lib().slos_shared_superposition_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def fock_shared_superposition_amplitudes(s: SharedSuperposition, U: torch.Tensor, X: torch.Tensor,
+                                         out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """X [G, N] complex64 -> U's action, complex64 [G, N]."""
+    _require(U, "U", torch.complex64, (s.m, s.m))
+    _require(X, "X", torch.complex64)
+    if X.dim() != 2 or X.shape[1] != s.N:
+        raise ValueError("X must be [G, %d]" % s.N)
+    G = X.shape[0]
+    if out is None:
+        out = torch.empty((G, s.N), dtype=torch.complex64, device=U.device)
+    _require(out, "out", torch.complex64, (G, s.N))
+    _check("fock_shared_superposition_amplitudes",
+           lib().fock_shared_superposition_amplitudes(s.handle, _ptr(U), _ptr(X), G, _ptr(out), _stream_ptr(U.device)))
+    return out
+
+
+def fock_shared_superposition_amplitudes_backward(s: SharedSuperposition, U: torch.Tensor, X: torch.Tensor,
+                                                  grad_out: torch.Tensor, need_grad_x: bool = True):
+    _require(U, "U", torch.complex64, (s.m, s.m))
+    _require(X, "X", torch.complex64)
+    G = X.shape[0]
+    _require(grad_out, "grad_out", torch.complex64, (G, s.N))
+    gU = torch.empty_like(U)
+    gX = torch.empty_like(X) if need_grad_x else None
+    _check("fock_shared_superposition_amplitudes_backward",
+           lib().fock_shared_superposition_amplitudes_backward(s.handle, _ptr(U), _ptr(X), G, _ptr(grad_out), _ptr(gU),
+                                                               _ptr(gX), _stream_ptr(U.device)))
+    return gU, gX
 
 
 def fock_sample(batch: Batch, U: torch.Tensor, u: torch.Tensor, out: Optional[torch.Tensor] = None,

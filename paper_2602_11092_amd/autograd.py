@@ -106,6 +106,25 @@ class FockSuperposition(torch.autograd.Function):
         return gU, gx, None
 
 
+class FockSharedSuperposition(torch.autograd.Function):
+    """U [m, m] and dense inputs X [G, N] (complex64) -> U's action on each input, [G, N]."""
+
+    @staticmethod
+    def forward(ctx, U: torch.Tensor, X: torch.Tensor, s: B.SharedSuperposition):
+        U = _dense(U, torch.complex64)
+        X = _dense(X, torch.complex64)
+        ctx.s = s
+        ctx.save_for_backward(U, X)
+        return B.fock_shared_superposition_amplitudes(s, U, X)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        U, X = ctx.saved_tensors
+        gU, gX = B.fock_shared_superposition_amplitudes_backward(ctx.s, U, X, _dense(grad_out, torch.complex64),
+                                                                 need_grad_x=ctx.needs_input_grad[1])
+        return gU, gX, None
+
+
 class MeshToUnitary(torch.autograd.Function):
     """theta [m(m-1)] float32 and features x [B, m] float32 (or None) ->
     U [B, m, m] complex64."""
@@ -149,6 +168,10 @@ def fock_threshold_probs(U: torch.Tensor, batch: B.Batch) -> torch.Tensor:
 
 def fock_superposition_amplitudes(U: torch.Tensor, x: torch.Tensor, sup: B.Superposition) -> torch.Tensor:
     return FockSuperposition.apply(U, x, sup)
+
+
+def fock_shared_superposition_amplitudes(U: torch.Tensor, X: torch.Tensor, s: B.SharedSuperposition) -> torch.Tensor:
+    return FockSharedSuperposition.apply(U, X, s)
 
 
 def mesh_to_unitary(theta: torch.Tensor, x: Optional[torch.Tensor], enc_scale: float = math.pi,

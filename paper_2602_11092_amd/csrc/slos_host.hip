@@ -8,6 +8,8 @@
 #include <numeric>
 #include <thread>
 
+#include <rocblas/rocblas.h>
+
 #include "slos_internal.h"
 
 namespace slos {
@@ -953,6 +955,166 @@ extern "C" int fock_superposition_amplitudes_backward(slos_superposition_t sup, 
     if (rc == SLOS_OK)
         rc = run(sup->batch, SLOS_OP_AMPLITUDES_BACKWARD, (const float*)Uc, gA, (float*)gUc, rest, amp, stream);
     if (rc == SLOS_OK) rc = launch_superposition(kSupGroupSum, sup->dev, Bt, gUc, nullptr, nullptr, grad_U, s);
+    return rc;
+}
+
+// ------------------------------------------- superpositions through one U
+
+// Every input is a dense vector over the n-photon basis and all inputs share
+// one interferometer, so U's n-photon representation Uhat is built once per
+// call (one SLOS per basis state: row c of A holds a(U, basis_c)) and the
+// inputs go through one complex GEMM: out[g][t] = sum_c X[g][c] A[c][t].
+struct slos_shared_superposition_s {
+    slos_batch_t basis = nullptr;  // the N basis states of n photons, one per sample
+    int N = 0;
+    int m = 0;
+    void* dmem = nullptr;
+    float2 *Urep = nullptr, *A = nullptr, *gA = nullptr, *gUc = nullptr;
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    SupDev dev;  // one group holding every basis state
+    rocblas_handle blas = nullptr;
+};
+
+extern "C" int slos_shared_superposition_create(slos_plan_t plan, int n, slos_shared_superposition_t* out) {
+    if (!out) return fail(SLOS_EINVAL, "slos_shared_superposition_create: out is NULL");
+    *out = nullptr;
+    if (!plan || n < 0 || n > plan->n_max) return fail(SLOS_EINVAL, "slos_shared_superposition_create: bad plan or n");
+    const int64_t N = plan->N[n];
+    if (N > 16384) return fail(SLOS_EUNSUPPORTED, "slos_shared_superposition_create: more than 16384 basis states");
+    const int m = plan->m;
+    std::vector<int32_t> occ((size_t)N * m, 0);
+    const int group = flags_group(plan->flags);
+    Counter C(m, n, group);
+    std::vector<int> L(std::max(n, 1));
+    for (int64_t c = 0; c < N; ++c) {
+        C.unrank(c, n, L.data());
+        for (int p = 0; p < n; ++p) occ[(size_t)c * m + L[p]] += 1;
+    }
+    auto* S = new slos_shared_superposition_s();
+    S->N = (int)N;
+    S->m = m;
+    int rc = slos_batch_create(plan, (int)N, occ.data(), &S->basis);
+    if (rc != SLOS_OK) {
+        delete S;
+        return rc;
+    }
+    size_t wf = 0, wb = 0;
+    slos_workspace_bytes(S->basis, SLOS_OP_AMPLITUDES, &wf);
+    slos_workspace_bytes(S->basis, SLOS_OP_AMPLITUDES_BACKWARD, &wb);
+    S->ws_bytes = std::max(wf, wb);
+    const size_t mm = (size_t)m * m, NN = (size_t)N * N;
+    const size_t o_u = 0, o_a = o_u + align256(N * mm * 8), o_ga = o_a + align256(NN * 8);
+    const size_t o_guc = o_ga + align256(NN * 8), o_ws = o_guc + align256(N * mm * 8);
+    const size_t o_grp = o_ws + align256(S->ws_bytes), o_goff = o_grp + align256(N * 4);
+    const size_t total = o_goff + 256;
+    if (hipMalloc(&S->dmem, total) != hipSuccess) {
+        slos_batch_destroy(S->basis);
+        delete S;
+        return fail(SLOS_ENOMEM, "slos_shared_superposition_create: hipMalloc failed");
+    }
+    char* base = (char*)S->dmem;
+    S->Urep = (float2*)(base + o_u);
+    S->A = (float2*)(base + o_a);
+    S->gA = (float2*)(base + o_ga);
+    S->gUc = (float2*)(base + o_guc);
+    S->ws = base + o_ws;
+    std::vector<int32_t> zeros(N, 0);
+    const int64_t goff[2] = {0, N};
+    hipError_t e = hipMemcpy(base + o_grp, zeros.data(), N * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(base + o_goff, goff, sizeof(goff), hipMemcpyHostToDevice);
+    if (e != hipSuccess || rocblas_create_handle(&S->blas) != rocblas_status_success) {
+        hipFree(S->dmem);
+        slos_batch_destroy(S->basis);
+        delete S;
+        return fail(SLOS_EHIP, "slos_shared_superposition_create: setup failed");
+    }
+    S->dev.G = 1;
+    S->dev.group = (const int32_t*)(base + o_grp);
+    S->dev.goff = (const int64_t*)(base + o_goff);
+    S->dev.ooff = (const int64_t*)(base + o_goff);
+    S->dev.max_n_states = N;
+    *out = S;
+    return SLOS_OK;
+}
+
+extern "C" int slos_shared_superposition_destroy(slos_shared_superposition_t s) {
+    if (!s) return SLOS_OK;
+    hipDeviceSynchronize();
+    if (s->blas) rocblas_destroy_handle(s->blas);
+    if (s->dmem) hipFree(s->dmem);
+    slos_batch_destroy(s->basis);
+    delete s;
+    return SLOS_OK;
+}
+
+extern "C" int64_t slos_shared_superposition_dim(slos_shared_superposition_t s) { return s ? s->N : -1; }
+
+namespace {
+
+// Uhat's rows into s->A on `stream`
+int shared_rows(slos_shared_superposition_s& S, const float* U, hipStream_t stream) {
+    const slos_batch_s& Bt = *S.basis;
+    int rc = launch_superposition(kSupReplicateU, S.dev, Bt, U, nullptr, nullptr, S.Urep, stream);
+    if (rc == SLOS_OK) rc = run(S.basis, SLOS_OP_AMPLITUDES, (const float*)S.Urep, nullptr, S.A, S.ws, S.ws_bytes, stream);
+    return rc;
+}
+
+// C (column-major, ldc) = op(A) op(B), complex FP32 on `stream`
+int cgemm(rocblas_handle h, hipStream_t stream, rocblas_operation ta, rocblas_operation tb, int M, int Nc, int K,
+          const float2* A, int lda, const float2* B, int ldb, float2* C, int ldc) {
+    const rocblas_float_complex one(1.f, 0.f), zero(0.f, 0.f);
+    if (rocblas_set_stream(h, stream) != rocblas_status_success) return fail(SLOS_EHIP, "rocblas_set_stream failed");
+    const rocblas_status st = rocblas_cgemm(h, ta, tb, M, Nc, K, &one, (const rocblas_float_complex*)A, lda,
+                                            (const rocblas_float_complex*)B, ldb, &zero, (rocblas_float_complex*)C, ldc);
+    if (st != rocblas_status_success) return fail(SLOS_EHIP, "rocblas_cgemm failed (" + std::to_string((int)st) + ")");
+    return SLOS_OK;
+}
+
+}  // namespace
+
+extern "C" int fock_shared_superposition_amplitudes(slos_shared_superposition_t s, const float* U, const float* X,
+                                                    int G, float* out, void* stream) {
+    const std::string nm = "fock_shared_superposition_amplitudes";
+    if (!s || G < 0) return fail(SLOS_EINVAL, nm + ": bad argument");
+    if (G == 0) return SLOS_OK;
+    if (!U || !X || !out) return fail(SLOS_EINVAL, nm + ": NULL device pointer");
+    hipStream_t st = (hipStream_t)stream;
+    int rc = shared_rows(*s, U, st);
+    // out_cm (N x G) = A_cm (N x N) X_cm (N x G), A_cm = A's rows read column-major
+    if (rc == SLOS_OK)
+        rc = cgemm(s->blas, st, rocblas_operation_none, rocblas_operation_none, s->N, G, s->N, s->A, s->N,
+                   (const float2*)X, s->N, (float2*)out, s->N);
+    return rc;
+}
+
+extern "C" int fock_shared_superposition_amplitudes_backward(slos_shared_superposition_t s, const float* U,
+                                                             const float* X, int G, const float* grad_out,
+                                                             float* grad_U, float* grad_X, void* stream) {
+    const std::string nm = "fock_shared_superposition_amplitudes_backward";
+    if (!s || G < 0) return fail(SLOS_EINVAL, nm + ": bad argument");
+    if (!U || !grad_U) return fail(SLOS_EINVAL, nm + ": NULL device pointer");
+    if (G > 0 && (!X || !grad_out)) return fail(SLOS_EINVAL, nm + ": NULL device pointer");
+    hipStream_t st = (hipStream_t)stream;
+    const int N = s->N;
+    int rc = shared_rows(*s, U, st);
+    // dL/dX[g][c] = sum_t conj(A[c][t]) G[g][t]:  gX_cm (N x G) = A_cm^H G_cm
+    if (rc == SLOS_OK && grad_X && G > 0)
+        rc = cgemm(s->blas, st, rocblas_operation_conjugate_transpose, rocblas_operation_none, N, G, N, s->A, N,
+                   (const float2*)grad_out, N, (float2*)grad_X, N);
+    // dL/dA[c][t] = sum_g conj(X[g][c]) G[g][t]:  gA_cm (N x N) = G_cm X_cm^H
+    if (rc == SLOS_OK) {
+        if (G > 0)
+            rc = cgemm(s->blas, st, rocblas_operation_none, rocblas_operation_conjugate_transpose, N, N, G,
+                       (const float2*)grad_out, N, (const float2*)X, N, s->gA, N);
+        else
+            rc = hipMemsetAsync(s->gA, 0, (size_t)N * N * 8, st) == hipSuccess ? SLOS_OK : fail(SLOS_EHIP, nm + ": clear failed");
+    }
+    if (rc == SLOS_OK)
+        rc = run(s->basis, SLOS_OP_AMPLITUDES_BACKWARD, (const float*)s->Urep, s->gA, (float*)s->gUc, s->ws,
+                 s->ws_bytes, stream);
+    if (rc == SLOS_OK)
+        rc = launch_superposition(kSupGroupSum, s->dev, *s->basis, s->gUc, nullptr, nullptr, grad_U, st);
     return rc;
 }
 

@@ -120,3 +120,50 @@ def test_superposition_autograd_and_edge_cases():
     bad = B.Batch(B.Plan(m, 3), np.array([[1, 1, 0, 0], [1, 1, 1, 0]], dtype=np.int32))
     with pytest.raises(B.SlosError):
         B.Superposition(bad, [0, 2])
+
+
+# ------------------------------------------------- one shared interferometer
+
+@pytest.mark.parametrize("m,n,G", [(4, 2, 5), (6, 3, 64), (8, 4, 33)])
+def test_shared_superposition_against_oracle(m, n, G):
+    rng = np.random.default_rng(50 + m)
+    U = W.haar_unitaries(rng, 1, m).astype(np.complex64)[0]
+    s = B.SharedSuperposition(B.Plan(m, n), n)
+    N = s.N
+    assert N == O.fock_dim(m, n)
+    X = ((rng.standard_normal((G, N)) + 1j * rng.standard_normal((G, N))) / np.sqrt(2 * N)).astype(np.complex64)
+    Ud = to_dev_c64(U)
+    Xd = torch.from_numpy(X).to(DEV)
+    say("shared superposition m", m, "n", n, "G", G)
+    out = B.fock_shared_superposition_amplitudes(s, Ud, Xd).cpu().numpy()
+    basis = O.fock_basis(m, n)
+    # Uhat's rows from the oracle: A[c] = a(U, basis_c)
+    A = np.stack([O.amplitudes(widen(U), basis[c]) for c in range(N)])
+    ref = X.astype(np.complex128) @ A
+    assert np.abs(out - ref).max() <= S_TOL
+    Gd = ((rng.standard_normal((G, N)) + 1j * rng.standard_normal((G, N)))).astype(np.complex64)
+    gU, gX = B.fock_shared_superposition_amplitudes_backward(s, Ud, Xd, torch.from_numpy(Gd).to(DEV))
+    torch.cuda.synchronize()
+    gU, gX = gU.cpu().numpy(), gX.cpu().numpy()
+    G64 = Gd.astype(np.complex128)
+    assert rel_err(gX, G64 @ A.conj().T) <= G_RTOL
+    gA = X.astype(np.complex128).conj().T @ G64  # dL/dA[c][t]
+    ref_U = sum(O.amplitude_grad(widen(U), basis[c], gA[c]) for c in range(N))
+    assert rel_err(gU, ref_U) <= G_RTOL
+
+
+def test_shared_superposition_is_unitary_and_trains():
+    # Uhat is unitary on the n-photon space: orthonormal inputs stay orthonormal
+    m, n = 5, 3
+    rng = np.random.default_rng(61)
+    s = B.SharedSuperposition(B.Plan(m, n), n)
+    N = s.N
+    Q, _ = np.linalg.qr(rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N)))
+    X = torch.from_numpy(Q[:8].astype(np.complex64)).to(DEV)
+    U = to_dev_c64(W.haar_unitaries(rng, 1, m)[0]).requires_grad_(True)
+    from paper_2602_11092_amd.autograd import fock_shared_superposition_amplitudes
+    out = fock_shared_superposition_amplitudes(U, X, s)
+    gram = (out @ out.conj().T).detach().cpu().numpy()
+    assert np.abs(gram - np.eye(8)).max() <= 1e-5
+    out.abs().pow(2)[:, 0].sum().backward()
+    assert U.grad is not None and torch.isfinite(U.grad.abs()).all()
