@@ -11,7 +11,8 @@ import torch
 from torch import nn
 
 from . import _binding as B
-from .autograd import fock_amplitudes, fock_mode_expectations, fock_probs, fock_threshold_probs, mesh_to_unitary
+from .autograd import (fock_amplitudes, fock_mode_expectations, fock_probs, fock_shared_superposition_amplitudes,
+                       fock_threshold_probs, mesh_to_unitary)
 
 
 class QuantumLayer(nn.Module):
@@ -84,3 +85,34 @@ class QuantumLayer(nn.Module):
         if self.measurement == "threshold_probs":
             return fock_threshold_probs(U, bt).view(x.shape[0], -1)
         return fock_amplitudes(U, bt).view(x.shape[0], -1)
+
+
+class AmplitudeEncodedLayer(nn.Module):
+    """Amplitude encoding (Sec. II-C-2): X [batch, C(m+n-1, n)] complex64, each
+    row an n-photon state in basis order, goes through the trainable mesh
+    W2 W1 (no feature phases).  Returns the output amplitudes, or their
+    squared moduli with measurement="probs".  One interferometer for the
+    whole batch: its n-photon representation is built once per call and the
+    batch goes through one complex GEMM."""
+
+    def __init__(self, m: int, n: int, measurement: str = "amplitudes", seed: int = 0):
+        super().__init__()
+        if measurement not in ("amplitudes", "probs"):
+            raise ValueError("measurement must be 'amplitudes' or 'probs'")
+        self.m = m
+        self.n = n
+        self.measurement = measurement
+        g = torch.Generator().manual_seed(seed)
+        self.theta = nn.Parameter(torch.rand(m * (m - 1), generator=g) * (2 * math.pi))
+        self._shared = None
+
+    @property
+    def state_size(self) -> int:
+        return B.slos_fock_dim(self.m, self.n)
+
+    def forward(self, X: torch.Tensor) -> torch.Tensor:
+        if self._shared is None:
+            self._shared = B.SharedSuperposition(B.Plan(self.m, max(self.n, 1)), self.n)
+        U = mesh_to_unitary(self.theta, None, 0.0, self.m)[0]
+        out = fock_shared_superposition_amplitudes(U, X.to(torch.complex64), self._shared)
+        return out if self.measurement == "amplitudes" else out.abs() ** 2

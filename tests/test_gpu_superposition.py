@@ -167,3 +167,32 @@ def test_shared_superposition_is_unitary_and_trains():
     assert np.abs(gram - np.eye(8)).max() <= 1e-5
     out.abs().pow(2)[:, 0].sum().backward()
     assert U.grad is not None and torch.isfinite(U.grad.abs()).all()
+
+
+def test_amplitude_encoded_layer_trains_against_oracle():
+    from paper_2602_11092_amd import AmplitudeEncodedLayer
+    m, n = 5, 2
+    layer = AmplitudeEncodedLayer(m, n, measurement="probs").to(DEV)
+    N = layer.state_size
+    rng = np.random.default_rng(70)
+    X = rng.standard_normal((6, N)) + 1j * rng.standard_normal((6, N))
+    X /= np.linalg.norm(X, axis=1, keepdims=True)
+    Xd = torch.from_numpy(X.astype(np.complex64)).to(DEV)
+    w = torch.from_numpy(rng.standard_normal((6, N)).astype(np.float32)).to(DEV)
+    p = layer(Xd)
+    (p * w).sum().backward()
+    torch.cuda.synchronize()
+    th = layer.theta.detach().cpu().numpy().astype(np.float64)
+    U = O.mesh_unitary(th, m)
+    basis = O.fock_basis(m, n)
+    A = np.stack([O.amplitudes(U, basis[c]) for c in range(N)])
+    X64 = Xd.cpu().numpy().astype(np.complex128)
+    out = X64 @ A
+    assert np.abs(p.detach().cpu().numpy() - np.abs(out) ** 2).max() <= 1e-5
+    assert np.abs(p.detach().cpu().numpy().sum(1) - 1).max() <= 1e-5  # normalised inputs stay normalised
+    # chain: dL/dout = 2 w out, dL/dA = X^H (2 w out), then the amplitude and mesh gradients
+    gout = 2 * w.cpu().numpy().astype(np.float64) * out
+    gA = X64.conj().T @ gout
+    GU = sum(O.amplitude_grad(U, basis[c], gA[c]) for c in range(N))
+    rt, _ = O.mesh_grad(th, None, 0.0, GU)
+    assert rel_err(layer.theta.grad.cpu().numpy(), rt) <= G_RTOL
