@@ -25,25 +25,43 @@ FORWARD_CANDIDATES = [(B.VARIANT_FUSED, 256), (B.VARIANT_FUSED, 512), (B.VARIANT
                       (B.VARIANT_LAYERED, 128), (B.VARIANT_LAYERED, 256), (B.VARIANT_LAYERED, 512)]
 BACKWARD_CANDIDATES = [(B.VARIANT_FUSED, 256), (B.VARIANT_FUSED, 512), (B.VARIANT_FUSED, 768), (B.VARIANT_FUSED, 1024),
                        (B.VARIANT_LAYERED, 128), (B.VARIANT_LAYERED, 256), (B.VARIANT_LAYERED, 512)]
-_BACKWARD = (B.OP_AMPLITUDES_BACKWARD, B.OP_PROBS_BACKWARD)
+_BACKWARD = (B.OP_AMPLITUDES_BACKWARD, B.OP_PROBS_BACKWARD, B.OP_MODE_EXPECTATIONS_BACKWARD,
+             B.OP_THRESHOLD_PROBS_BACKWARD)
 
 
 def _runner(batch: B.Batch, U: torch.Tensor, op: int):
     """A closure that runs `op` once on fixed buffers (allocated here, before timing)."""
     dev = U.device
     n = batch.out_len
+    ws = batch.workspace(op, dev)
     if op == B.OP_PROBS:
         out = torch.empty(n, dtype=torch.float32, device=dev)
-        return lambda: B.fock_probs(batch, U, out=out)
+        return lambda: B.fock_probs(batch, U, out=out, ws=ws)
     if op == B.OP_AMPLITUDES:
         out = torch.empty(n, dtype=torch.complex64, device=dev)
-        return lambda: B.fock_amplitudes(batch, U, out=out)
+        return lambda: B.fock_amplitudes(batch, U, out=out, ws=ws)
+    if op == B.OP_MODE_EXPECTATIONS:
+        out = torch.empty((batch.B, batch.m), dtype=torch.float32, device=dev)
+        return lambda: B.fock_mode_expectations(batch, U, out=out, ws=ws)
+    if op == B.OP_THRESHOLD_PROBS:
+        out = torch.empty(batch.threshold_len, dtype=torch.float32, device=dev)
+        return lambda: B.fock_threshold_probs(batch, U, out=out, ws=ws)
+    if op == B.OP_SAMPLE:
+        u = torch.rand((batch.B, 64), device=dev)
+        out = torch.empty((batch.B, 64), dtype=torch.int32, device=dev)
+        return lambda: B.fock_sample(batch, U, u, out=out, ws=ws)
     gU = torch.empty_like(U)
     if op == B.OP_PROBS_BACKWARD:
         g = torch.ones(n, dtype=torch.float32, device=dev)
-        return lambda: B.fock_probs_backward(batch, U, g, out=gU)
+        return lambda: B.fock_probs_backward(batch, U, g, out=gU, ws=ws)
+    if op == B.OP_MODE_EXPECTATIONS_BACKWARD:
+        g = torch.ones((batch.B, batch.m), dtype=torch.float32, device=dev)
+        return lambda: B.fock_mode_expectations_backward(batch, U, g, out=gU, ws=ws)
+    if op == B.OP_THRESHOLD_PROBS_BACKWARD:
+        g = torch.ones(batch.threshold_len, dtype=torch.float32, device=dev)
+        return lambda: B.fock_threshold_probs_backward(batch, U, g, out=gU, ws=ws)
     g = torch.ones(n, dtype=torch.complex64, device=dev)
-    return lambda: B.fock_amplitudes_backward(batch, U, g, out=gU)
+    return lambda: B.fock_amplitudes_backward(batch, U, g, out=gU, ws=ws)
 
 
 def _time_us(fn, warmup: int, iters: int) -> float:

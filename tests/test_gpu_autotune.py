@@ -73,3 +73,18 @@ def test_autotune_skips_unsupported_candidates():
     assert (B.VARIANT_LAYERED, 256) in blocks
     with pytest.raises(B.SlosError):
         batch.set_config(B.OP_PROBS_BACKWARD, B.VARIANT_FUSED, 768)
+
+
+def test_autotune_measurement_ops():
+    # the expectation, threshold and sampling ops are tuned on their own entry points
+    U64, occ = _mixed_batch(seed=21, B_=16, m=8)
+    batch = B.Batch(B.Plan(8, int(occ.sum(1).max()), threshold=True), occ)
+    Ud = to_dev_c64(U64)
+    ops = (B.OP_MODE_EXPECTATIONS, B.OP_THRESHOLD_PROBS, B.OP_SAMPLE, B.OP_MODE_EXPECTATIONS_BACKWARD,
+           B.OP_THRESHOLD_PROBS_BACKWARD)
+    rep = autotune(batch, Ud, ops=ops, warmup=1, iters=1)
+    for op in ops:
+        assert rep[op]["timings"] and batch.get_config(op) == (rep[op]["variant"], rep[op]["block"])
+    e = B.fock_mode_expectations(batch, Ud).cpu().numpy()
+    for b in range(batch.B):
+        assert np.abs(e[b] - O.mode_expectations(widen(U64[b]), occ[b])).max() <= 2e-5
