@@ -14,10 +14,12 @@
 // cancels strongly).
 //
 // Two kernels:
-//  * n <= 6: one thread per (a, b) pair.  M lives in registers and the
+//  * n <= 7: one thread per (a, b) pair.  M lives in registers and the
 //    2^n - 1 Gray-code steps are unrolled for the compile-time n, so every
 //    index into M is static.  Lanes of a wave share a (U1 loads broadcast).
-//  * n >= 7 (and n = 0): one wave per pair.  Its lanes build M in LDS, then
+//    n = 7 takes all 256 VGPRs (one wave per SIMD) and still runs several
+//    times faster than a wave per pair; n = 8 would spill.
+//  * n >= 8 (and n = 0): one wave per pair.  Its lanes build M in LDS, then
 //    lane l walks the Gray-code positions [l K, (l+1) K), K = ceil(2^n / 64),
 //    from row sums formed directly; a fixed-order shuffle reduction combines
 //    the lanes.
@@ -207,10 +209,11 @@ extern "C" int fock_fidelity_kernel(int m, const int32_t* occ, const float* U1, 
     if ((int64_t)B1 * B2 == 0) return SLOS_OK;
     if (!U1 || !U2 || !K) return fail(SLOS_EINVAL, "fock_fidelity_kernel: NULL device pointer");
     const double scale = 1.0 / fact;
-    if (n >= 1 && n <= 6) {
-        static void* const thread_fns[6] = {(void*)&fidelity_thread_kernel<1>, (void*)&fidelity_thread_kernel<2>,
+    if (n >= 1 && n <= 7) {
+        static void* const thread_fns[7] = {(void*)&fidelity_thread_kernel<1>, (void*)&fidelity_thread_kernel<2>,
                                             (void*)&fidelity_thread_kernel<3>, (void*)&fidelity_thread_kernel<4>,
-                                            (void*)&fidelity_thread_kernel<5>, (void*)&fidelity_thread_kernel<6>};
+                                            (void*)&fidelity_thread_kernel<5>, (void*)&fidelity_thread_kernel<6>,
+                                            (void*)&fidelity_thread_kernel<7>};
         const int64_t blocks = ((int64_t)B1 * B2 + kFidBlock - 1) / kFidBlock;
         if (blocks >= ((int64_t)1 << 31)) return fail(SLOS_EUNSUPPORTED, "fock_fidelity_kernel: too many pairs");
         void* args[] = {(void*)&m, (void*)&C, (void*)&scale, (void*)&U1, (void*)&B1, (void*)&U2, (void*)&B2, (void*)&K};
