@@ -272,3 +272,50 @@ def test_dual_rail_is_the_fock_subvector():
     pf = run_forward(B.Batch(B.Plan(m, n), occ), Ud, False).reshape(12, -1)
     keep = np.array([int(t.reshape(-1, 2).sum(1).max()) <= 1 for t in O.fock_basis(m, n)])
     assert np.abs(pd - pf[:, keep]).max() <= 1e-6
+
+
+# ---------------------------------------------- measurements on restricted plans
+
+def test_expectation_adjoint_on_unbunched_plan():
+    m = 7
+    rng = np.random.default_rng(31)
+    U, occ = _batch(rng, 10, m, 1, 4, False)
+    batch = B.Batch(B.Plan(m, 4, unbunched=True), occ)
+    Ud = to_dev_c64(U)
+    w = rng.standard_normal((10, m)).astype(np.float32)
+    e = B.fock_mode_expectations(batch, Ud).cpu().numpy()
+    gU = B.fock_mode_expectations_backward(batch, Ud, torch.from_numpy(w).to(DEV)).cpu().numpy()
+    for b in range(10):
+        outs = _outputs(m, int(occ[b].sum()))
+        assert np.abs(e[b] - O.mode_expectations(widen(U[b]), occ[b], outputs=outs)).max() <= 2e-5
+        ref = O.probs_grad(widen(U[b]), occ[b], outs @ w[b].astype(np.float64), outputs=outs)
+        assert rel_err(gU[b], ref) <= G_RTOL, b
+
+
+def test_sampling_and_threshold_on_dual_rail_plan():
+    m, q = 8, 4
+    rng = np.random.default_rng(32)
+    U = W.haar_unitaries(rng, 6, m).astype(np.complex64)
+    occ = np.zeros((6, m), dtype=np.int32)
+    for b in range(6):
+        occ[b, 2 * np.arange(q) + rng.integers(0, 2, size=q)] = 1
+    batch = B.Batch(B.Plan(m, q, dual_rail=True, threshold=True), occ)
+    Ud = to_dev_c64(U)
+    # shots index the 16 logical states; a shot's state must carry probability
+    u = torch.from_numpy(rng.random((6, 256)).astype(np.float32)).to(DEV)
+    shots = B.fock_sample(batch, Ud, u).cpu().numpy()
+    p = B.fock_probs(batch, Ud).cpu().numpy().reshape(6, 16)
+    assert shots.min() >= 0 and shots.max() < 16
+    assert all(p[b, shots[b]].min() > 0 for b in range(6))
+    # threshold patterns: only size-q patterns that are logical states get mass
+    P = B.fock_threshold_probs(batch, Ud).cpu().numpy().reshape(6, -1)
+    start = sum(math.comb(m, k) for k in range(1, q))
+    assert np.all(P[:, :start] == 0)
+    outs = _dual_outputs(m, q)
+    for b in range(6):
+        ref = O.probabilities(widen(U[b]), occ[b], outputs=outs)
+        for r, t in enumerate(outs):
+            modes = [j for j in range(m) if t[j]]
+            idx = start + [i for i, c in enumerate(__import__("itertools").combinations(range(m), q))
+                           if list(c) == modes][0]
+            assert abs(P[b, idx] - ref[r]) <= 2e-5
