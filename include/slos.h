@@ -70,7 +70,10 @@ extern "C" {
 #define SLOS_MAX_MODES 32
 #define SLOS_MAX_PHOTONS 16
 
-/* Operation codes for slos_workspace_bytes / slos_batch_set_config. */
+/* Operation codes for slos_workspace_bytes / slos_batch_set_config.  The
+ * measurement ops (4, 6, 8) configure the forward pass behind their entry
+ * point (fock_mode_expectations, fock_threshold_probs, fock_sample), and
+ * their backward ops (5, 7) the probability adjoint behind theirs. */
 #define SLOS_OP_AMPLITUDES 0
 #define SLOS_OP_PROBS 1
 #define SLOS_OP_AMPLITUDES_BACKWARD 2
