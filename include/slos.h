@@ -133,6 +133,19 @@ SLOS_API int64_t slos_unbunched_dim(int m, int n);
 SLOS_API int64_t slos_space_dim(int m, int n, int flags);
 
 /* Occupation vector (occ[0..m-1], host) of the state of the given rank in
+ * the space of plans with these flags (the basis order restricted to the
+ * space).  SLOS_EINVAL for bad flags, m, n, rank or NULL. */
+SLOS_API int slos_space_unrank(int m, int n, int flags, int64_t rank, int32_t* occ);
+
+/* Rank of occ (host, m entries summing to n) in that space; -1 if invalid
+ * or outside the space. */
+SLOS_API int64_t slos_space_rank(int m, int n, int flags, const int32_t* occ);
+
+/* clicks[0..m-1] (host) <- 1 for the modes of click pattern q of n photons
+ * (the order of slos_threshold_dim), else 0.  SLOS_EINVAL for a bad q. */
+SLOS_API int slos_threshold_pattern(int m, int n, int64_t q, int32_t* clicks);
+
+/* Occupation vector (occ[0..m-1], host) of the state of the given rank in
  * the basis order above.  Returns SLOS_EINVAL for a bad m, n, rank or NULL. */
 SLOS_API int slos_fock_unrank(int m, int n, int64_t rank, int32_t* occ);
 

@@ -51,6 +51,9 @@ SIGNATURES = {
     "slos_fock_dim": (_c.c_int64, [_c.c_int, _c.c_int]),
     "slos_unbunched_dim": (_c.c_int64, [_c.c_int, _c.c_int]),
     "slos_space_dim": (_c.c_int64, [_c.c_int, _c.c_int, _c.c_int]),
+    "slos_space_unrank": (_c.c_int, [_c.c_int, _c.c_int, _c.c_int, _c.c_int64, _vp]),
+    "slos_space_rank": (_c.c_int64, [_c.c_int, _c.c_int, _c.c_int, _vp]),
+    "slos_threshold_pattern": (_c.c_int, [_c.c_int, _c.c_int, _c.c_int64, _vp]),
     "slos_fock_unrank": (_c.c_int, [_c.c_int, _c.c_int, _c.c_int64, _vp]),
     "slos_fock_rank": (_c.c_int64, [_c.c_int, _c.c_int, _vp]),
     "slos_last_error": (_c.c_char_p, []),
@@ -162,6 +165,25 @@ def slos_unbunched_dim(m: int, n: int) -> int:
 
 def space_flags(unbunched: bool = False, dual_rail: bool = False) -> int:
     return (PLAN_UNBUNCHED if unbunched else 0) | (PLAN_DUAL_RAIL if dual_rail else 0)
+
+
+def slos_space_unrank(m: int, n: int, flags: int, rank: int) -> np.ndarray:
+    """Occupation of the state of `rank` in the space of plans with `flags`."""
+    occ = np.zeros(m, dtype=np.int32)
+    _check("slos_space_unrank", lib().slos_space_unrank(m, n, flags, rank, occ.ctypes.data_as(_vp)))
+    return occ
+
+
+def slos_space_rank(m: int, n: int, flags: int, occ) -> int:
+    occ = np.ascontiguousarray(np.asarray(occ, dtype=np.int32))
+    return int(lib().slos_space_rank(m, n, flags, occ.ctypes.data_as(_vp)))
+
+
+def slos_threshold_pattern(m: int, n: int, q: int) -> np.ndarray:
+    """0/1 clicks of click pattern q of n photons over m modes."""
+    clicks = np.zeros(m, dtype=np.int32)
+    _check("slos_threshold_pattern", lib().slos_threshold_pattern(m, n, q, clicks.ctypes.data_as(_vp)))
+    return clicks
 
 
 def slos_threshold_dim(m: int, n: int) -> int:

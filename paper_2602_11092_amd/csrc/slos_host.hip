@@ -320,6 +320,48 @@ extern "C" int64_t slos_fock_rank(int m, int n, const int32_t* occ) {
 
 extern "C" int64_t slos_unbunched_dim(int m, int n) { return space_dim(m, n, 1); }
 
+extern "C" int slos_space_unrank(int m, int n, int flags, int64_t rank, int32_t* occ) {
+    if (!occ) return fail(SLOS_EINVAL, "slos_space_unrank: occ is NULL");
+    if (m < 1 || m > kMaxModes || n < 0 || n > 64) return fail(SLOS_EINVAL, "slos_space_unrank: bad m or n");
+    const int64_t N = slos_space_dim(m, n, flags);
+    if (N < 0 || rank < 0 || rank >= N) return fail(SLOS_EINVAL, "slos_space_unrank: bad flags or rank out of range");
+    Counter C(m, n, flags_group(flags));
+    std::vector<int> L(n > 0 ? n : 1);
+    C.unrank(rank, n, L.data());
+    for (int j = 0; j < m; ++j) occ[j] = 0;
+    for (int p = 0; p < n; ++p) occ[L[p]] += 1;
+    return SLOS_OK;
+}
+
+extern "C" int64_t slos_space_rank(int m, int n, int flags, const int32_t* occ) {
+    if (!occ || m < 1 || m > kMaxModes || n < 0 || n > 64 || slos_space_dim(m, n, flags) < 0) return -1;
+    std::vector<int> L;
+    for (int j = 0; j < m; ++j) {
+        if (occ[j] < 0) return -1;
+        for (int q = 0; q < occ[j]; ++q) L.push_back(j);
+    }
+    if ((int)L.size() != n) return -1;
+    Counter C(m, n, flags_group(flags));
+    for (int p = 0; p < n; ++p)  // the state must lie in the space
+        if (p > 0 && L[p] < C.next_lo(L[p - 1])) return -1;
+    return C.rank(L.data(), n);
+}
+
+extern "C" int slos_threshold_pattern(int m, int n, int64_t q, int32_t* clicks) {
+    if (!clicks) return fail(SLOS_EINVAL, "slos_threshold_pattern: clicks is NULL");
+    const int64_t Q = threshold_dim(m, n);
+    if (m > kMaxModes || Q < 0 || q < 0 || q >= Q) return fail(SLOS_EINVAL, "slos_threshold_pattern: bad m, n or q");
+    for (int j = 0; j < m; ++j) clicks[j] = 0;
+    if (n == 0) return SLOS_OK;  // the empty pattern
+    int k = 1;
+    while (q >= binom(m, k)) q -= binom(m, k++);
+    Counter C(m, k, 1);
+    int L[kMaxModes];
+    C.unrank(q, k, L);
+    for (int p = 0; p < k; ++p) clicks[L[p]] = 1;
+    return SLOS_OK;
+}
+
 extern "C" int64_t slos_space_dim(int m, int n, int flags) {
     if (flags & ~kPlanFlags || (flags & SLOS_PLAN_UNBUNCHED && flags & SLOS_PLAN_DUAL_RAIL)) return -1;
     return space_dim(m, n, flags_group(flags));

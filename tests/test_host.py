@@ -261,3 +261,36 @@ def test_threshold_dim(m, n):
 def test_threshold_layer_output_size():
     from paper_2602_11092_amd import QuantumLayer
     assert QuantumLayer(4, [1, 1, 0, 0], measurement="threshold_probs").output_size == 4 + 6
+
+
+@pytest.mark.parametrize("flags,m,n", [(0, 5, 3), (B.PLAN_UNBUNCHED, 6, 3), (B.PLAN_DUAL_RAIL, 8, 3),
+                                       (B.PLAN_DUAL_RAIL, 6, 3), (B.PLAN_UNBUNCHED, 4, 4)])
+def test_space_rank_unrank_match_enumeration(flags, m, n):
+    basis = O.fock_basis(m, n)
+    if flags == B.PLAN_UNBUNCHED:
+        basis = [t for t in basis if t.max() <= 1]
+    elif flags == B.PLAN_DUAL_RAIL:
+        basis = [t for t in basis if t.reshape(-1, 2).sum(1).max() <= 1]
+    assert B.slos_space_dim(m, n, flags) == len(basis)
+    for r, t in enumerate(basis):
+        assert np.array_equal(B.slos_space_unrank(m, n, flags, r), t)
+        assert B.slos_space_rank(m, n, flags, t) == r
+    if flags:  # a state outside the space has no rank
+        out = np.zeros(m, dtype=np.int32)
+        out[0] = 2
+        out[1] = n - 2
+        assert B.slos_space_rank(m, n, flags, out) == -1
+    with pytest.raises(B.SlosError):
+        B.slos_space_unrank(m, n, flags, len(basis))
+
+
+@pytest.mark.parametrize("m,n", [(4, 0), (4, 2), (5, 3), (3, 5)])
+def test_threshold_pattern_order(m, n):
+    pats = O.click_patterns(m, n)
+    assert B.slos_threshold_dim(m, n) == len(pats)
+    for q, c in enumerate(pats):
+        want = np.zeros(m, dtype=np.int32)
+        want[list(c)] = 1
+        assert np.array_equal(B.slos_threshold_pattern(m, n, q), want)
+    with pytest.raises(B.SlosError):
+        B.slos_threshold_pattern(m, n, len(pats))
