@@ -1,0 +1,26 @@
+"""CPU checks of bench.py's command line: more than one GPU is refused with
+a message (this build measures one GPU), and every extension workload name
+is one bench.py knows how to run."""
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def test_extension_workloads_are_listed():
+    sys.path.insert(0, ROOT)
+    import bench
+    assert len(set(bench.EXTENSIONS)) == len(bench.EXTENSIONS)
+    for name in ("expectations_clements_m20_n5_b512", "threshold_clements_m20_n5_b512",
+                 "sample_clements_m20_n5_b512_s1024", "unbunched_haar_m24_n8_b16", "superposition_m6_n3_g1024",
+                 "superposition_shared_m8_n4_g4096", "fidelity_m6_n4_b1024"):
+        assert name in bench.EXTENSIONS
+        assert os.path.exists(os.path.join(ROOT, "profiles", "bench_%s.json" % name))
