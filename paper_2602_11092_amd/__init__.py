@@ -25,4 +25,4 @@ from ._binding import (  # noqa: F401
     slos_fock_dim, slos_fock_rank, slos_fock_unrank, slos_space_dim, slos_threshold_dim, slos_unbunched_dim,
 )
 from . import autograd  # noqa: F401
-from .layer import AmplitudeEncodedLayer, QuantumLayer  # noqa: F401
+from .layer import AmplitudeEncodedLayer, FidelityKernel, QuantumLayer  # noqa: F401

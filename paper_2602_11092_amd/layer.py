@@ -116,3 +116,43 @@ class AmplitudeEncodedLayer(nn.Module):
         U = mesh_to_unitary(self.theta, None, 0.0, self.m)[0]
         out = fock_shared_superposition_amplitudes(U, X.to(torch.complex64), self._shared)
         return out if self.measurement == "amplitudes" else out.abs() ** 2
+
+
+class FidelityKernel:
+    """Fidelity kernel k(x1, x2) = |<phi(x1)|phi(x2)>|^2 with |phi(x)> =
+    U(x, theta)|s> (Sec. III-A), for kernel methods with a precomputed Gram
+    matrix: K = kernel(X) or kernel(X_test, X_train).  Features x (up to m
+    per sample) drive the angle-encoding phases of the mesh; fewer features
+    than modes leave the remaining phases at zero.  numpy inputs give a numpy
+    Gram matrix (float64), torch inputs a float32 device tensor."""
+
+    def __init__(self, m: int, input_state: Sequence[int], enc_scale: float = math.pi, seed: int = 0,
+                 device: str = "cuda"):
+        occ = np.asarray(input_state, dtype=np.int32)
+        if occ.shape != (m,):
+            raise ValueError("input_state must have m entries")
+        self.m = m
+        self.occ = occ
+        self.enc_scale = float(enc_scale)
+        self.device = device
+        g = torch.Generator().manual_seed(seed)
+        self.theta = (torch.rand(m * (m - 1), generator=g) * (2 * math.pi)).to(device)
+
+    def _unitaries(self, X: torch.Tensor) -> torch.Tensor:
+        X = X.to(self.device, torch.float32)
+        if X.dim() != 2 or X.shape[1] > self.m:
+            raise ValueError("features must be [batch, <= m]")
+        if X.shape[1] < self.m:
+            X = torch.cat([X, X.new_zeros(X.shape[0], self.m - X.shape[1])], dim=1)
+        return B.mesh_to_unitary(self.theta, X.contiguous(), self.enc_scale)
+
+    def __call__(self, X1, X2=None):
+        as_numpy = isinstance(X1, np.ndarray)
+        t1 = torch.as_tensor(np.asarray(X1, dtype=np.float32)) if as_numpy else X1
+        U1 = self._unitaries(t1)
+        if X2 is None:
+            K = B.fock_fidelity_kernel(self.occ, U1)
+        else:
+            t2 = torch.as_tensor(np.asarray(X2, dtype=np.float32)) if isinstance(X2, np.ndarray) else X2
+            K = B.fock_fidelity_kernel(self.occ, U1, self._unitaries(t2))
+        return K.cpu().numpy().astype(np.float64) if as_numpy else K

@@ -101,3 +101,26 @@ def test_fidelity_edge_cases():
     assert out.shape == (0, 3)
     with pytest.raises(B.SlosError):
         B.fock_fidelity_kernel([17] + [0] * 3, to_dev_c64(U))
+
+
+def test_fidelity_kernel_gram_from_features():
+    # the paper's example shape: 4 features, 6 modes, 4 photons; a train Gram and a test-by-train block
+    from paper_2602_11092_amd import FidelityKernel
+    kern = FidelityKernel(6, [1, 1, 1, 1, 0, 0], seed=3)
+    rng = np.random.default_rng(9)
+    Xtr = rng.standard_normal((12, 4))
+    Xte = rng.standard_normal((5, 4))
+    Ktr = kern(Xtr)
+    Kte = kern(Xte, Xtr)
+    assert isinstance(Ktr, np.ndarray) and Ktr.shape == (12, 12) and Kte.shape == (5, 12)
+    # U comes from the FP32 mesh, unitary to ~1e-7 per entry, so K(x, x) = |phi(x)|^4 is 1 to ~1e-6
+    assert np.abs(Ktr - Ktr.T).max() <= K_TOL and np.abs(np.diag(Ktr) - 1).max() <= 1e-5
+    th = kern.theta.cpu().numpy().astype(np.float64)
+    pad = lambda X: np.concatenate([X, np.zeros((X.shape[0], 2))], axis=1).astype(np.float32).astype(np.float64)
+    Utr = O.encoded_unitaries(th, pad(Xtr), math.pi)
+    Ute = O.encoded_unitaries(th, pad(Xte), math.pi)
+    occ = [1, 1, 1, 1, 0, 0]
+    for a, b in [(0, 1), (3, 7), (11, 2)]:
+        assert abs(Ktr[a, b] - O.fidelity(Utr[a], Utr[b], occ)) <= 1e-5
+    for a, b in [(0, 0), (4, 9)]:
+        assert abs(Kte[a, b] - O.fidelity(Ute[a], Utr[b], occ)) <= 1e-5
