@@ -876,6 +876,9 @@ extern "C" int slos_superposition_create(slos_batch_t components, int G, const i
     const slos_batch_s& Bt = *components;
     if (group_off[0] != 0 || group_off[G] != Bt.B)
         return fail(SLOS_EINVAL, "slos_superposition_create: offsets must run from 0 to the batch size");
+    for (int g = 0; g < G; ++g)  // every offset is checked before any is used
+        if (group_off[g + 1] <= group_off[g] || group_off[g + 1] > Bt.B)
+            return fail(SLOS_EINVAL, "slos_superposition_create: offsets must increase (one component or more per group)");
     auto* S = new slos_superposition_s();
     S->batch = components;
     S->goff.assign(group_off, group_off + G + 1);
@@ -899,6 +902,12 @@ extern "C" int slos_superposition_create(slos_batch_t components, int G, const i
         const int64_t N = Bt.plan->N[n];
         S->ooff[g + 1] = S->ooff[g] + N;
         maxN = std::max(maxN, N);
+    }
+    // the combine and expand grids are (group or component) x (state chunk)
+    const int64_t chunks = (maxN + kMeasureChunkStates - 1) / kMeasureChunkStates;
+    if ((int64_t)std::max(G, Bt.B) * chunks >= ((int64_t)1 << 31)) {
+        delete S;
+        return fail(SLOS_EUNSUPPORTED, "slos_superposition_create: too many components for one launch");
     }
     const size_t o_grp = 0, o_goff = align256((size_t)std::max(Bt.B, 1) * 4), o_ooff = o_goff + align256((G + 1) * 8);
     const size_t total = o_ooff + align256((G + 1) * 8);
@@ -1168,6 +1177,9 @@ extern "C" int fock_sample(slos_batch_t batch, const float* U, const float* u, i
     if (batch->B == 0) return SLOS_OK;
     if (!U) return fail(SLOS_EINVAL, nm + ": U is NULL");
     if (S > 0 && (!u || !shots)) return fail(SLOS_EINVAL, nm + ": uniforms or shots pointer is NULL");
+    if (((int64_t)batch->B * S + 255) / 256 >= ((int64_t)1 << 31) ||
+        (int64_t)batch->B * mode_expect_chunks(*batch) >= ((int64_t)1 << 31))
+        return fail(SLOS_EUNSUPPORTED, nm + ": too many samples or shots for one launch");
     int v, blk;
     resolve(*batch, SLOS_OP_SAMPLE, &v, &blk);
     const bool fused = v == SLOS_VARIANT_FUSED;

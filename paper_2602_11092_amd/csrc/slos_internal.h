@@ -126,6 +126,8 @@ int launch_layered_bwd(const slos_batch_s& Bt, int block, const float2* U, const
                        float2* gU, void* ws, hipStream_t stream);
 
 // ---- measurement kernels: slos_measure.hip ----
+// States per workgroup in the measurement kernels' (sample, chunk) grids.
+constexpr int64_t kMeasureChunkStates = 16384;
 // out[b][j] = sum_t t_j p[off_b + t] (p: the batch's probabilities), via
 // per-chunk partial sums in `part` (mode_expect_part_bytes bytes)
 size_t mode_expect_part_bytes(const slos_batch_s& Bt);

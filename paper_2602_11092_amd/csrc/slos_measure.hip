@@ -23,7 +23,7 @@ namespace {
 
 constexpr int kMeasureBlock = 256;
 constexpr int kParts = kMeasureBlock / kMaxModes;  // partial sums per mode in the final reduction
-constexpr int64_t kChunkStates = (int64_t)kMeasureBlock * 64;  // states per workgroup in the expectation sums
+constexpr int64_t kChunkStates = kMeasureChunkStates;  // states per workgroup in the (sample, chunk) grids
 static_assert(kParts * kMaxModes == kMeasureBlock, "one thread per (mode, part)");
 
 // Stage 1: workgroup (b, c) sums states [c*kChunkStates, (c+1)*kChunkStates)
@@ -360,6 +360,8 @@ int launch_sample(const slos_batch_s& Bt, const float* p, double* part, double* 
                   int32_t* shots, hipStream_t stream) {
     int C = (int)mode_expect_chunks(Bt);
     if ((int64_t)Bt.B * C >= ((int64_t)1 << 31)) return fail(SLOS_EUNSUPPORTED, "fock_sample: batch too large");
+    if (((int64_t)Bt.B * S + kMeasureBlock - 1) / kMeasureBlock >= ((int64_t)1 << 31))
+        return fail(SLOS_EUNSUPPORTED, "fock_sample: too many shots for one launch");
     void* a1[] = {(void*)&Bt.dev, (void*)&p, (void*)&part, (void*)&C};
     hipError_t e = hipLaunchKernel((void*)&cdf_partial_kernel, dim3((unsigned)(Bt.B * C)), dim3(kMeasureBlock), a1, 0,
                                    stream);

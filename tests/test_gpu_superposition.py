@@ -116,6 +116,11 @@ def test_superposition_autograd_and_edge_cases():
     a = B.fock_superposition_amplitudes(s1, to_dev_c64(U[:1]), torch.ones(1, dtype=torch.complex64, device=DEV))
     ref = B.fock_amplitudes(b1, to_dev_c64(U[:1]))
     assert torch.equal(a, ref)
+    # offsets out of order, or past the batch, are rejected before any is used
+    with pytest.raises(B.SlosError):
+        B.Superposition(batch, [0, 5, 3] if batch.B == 3 else [0, batch.B + 2, batch.B])
+    with pytest.raises(B.SlosError):
+        B.Superposition(batch, [0, 0, batch.B])  # an empty group
     # a group mixing photon numbers is rejected
     bad = B.Batch(B.Plan(m, 3), np.array([[1, 1, 0, 0], [1, 1, 1, 0]], dtype=np.int32))
     with pytest.raises(B.SlosError):
