@@ -63,8 +63,8 @@ def time_region(fn, iters, stream):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the work shards by samples with one all-reduce of dL/dtheta; see the design notes). "
+        print("bench.py measures one GPU only: there is no multi-GPU path "
+              "(the work would shard by samples, with one all-reduce of dL/dtheta). "
               "Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
     import numpy as np

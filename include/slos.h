@@ -66,7 +66,7 @@ extern "C" {
 #define SLOS_EWORKSPACE (-4)    /* workspace pointer null or smaller than required */
 #define SLOS_EUNSUPPORTED (-5)  /* valid request outside what this plan/build supports */
 
-/* Limits of this build. */
+/* Library limits. */
 #define SLOS_MAX_MODES 32
 #define SLOS_MAX_PHOTONS 16
 

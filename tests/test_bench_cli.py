@@ -1,5 +1,5 @@
 """CPU checks of bench.py's command line: more than one GPU is refused with
-a message (this build measures one GPU), and every extension workload name
+a message (the benchmark measures one GPU), and every extension workload name
 is one bench.py knows how to run."""
 import os
 import subprocess
