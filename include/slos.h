@@ -352,7 +352,7 @@ SLOS_API int fock_threshold_probs(slos_batch_t batch, const float* U, float* out
 SLOS_API int fock_threshold_probs_backward(slos_batch_t batch, const float* U, const float* grad_out,
                                            float* grad_U, void* ws, size_t ws_bytes, void* stream);
 
-/* ---- Measurement: shot sampling (Sec. II-B, finite-shot measurement) ----- */
+/* ---- Measurement: shot sampling (Sec. II-D: hardware returns shot-based samples) */
 
 /* shots (device, int32, [B][S]) <- output-state indices (within each
  * sample's output block, basis order) drawn from p / sum(p) by inverse

@@ -25,9 +25,10 @@ Contents, each following the passage it cites (arXiv 2602.11092):
 * Threshold-detector click probabilities P(c) = sum of p_t over the states
   t whose occupied modes are exactly c (the detector model of Sec. II-B),
   patterns ordered by click count, then lexicographically.
-* Shot sampling from the output distribution by inverse transform: with a
-  uniform u in [0, 1), the first state t whose cumulative probability (in
-  basis order, normalised over the output states) exceeds u.
+* Shot sampling from the output distribution by inverse transform (the
+  shot-based readout of hardware, Sec. II-D): with a uniform u in [0, 1),
+  the first state t whose cumulative probability (in basis order,
+  normalised over the output states) exceeds u.
 * Amplitude-encoded inputs (Sec. II-C-2): a superposition sum_c x_c |s_c>
   of n-photon Fock states maps to sum_c x_c U|s_c> (linearity of U's
   action), over the whole n-photon basis.
