@@ -22,6 +22,9 @@ Contents, each following the passage it cites (arXiv 2602.11092):
   by the product rule, in float64 NumPy.
 * Per-mode photon-number expectations <n_j> = sum_t t_j p_t over a set of
   output states (the measurement strategy of Sec. II-B), by that definition.
+* Per-mode click probabilities of threshold detectors, P(t_j > 0) =
+  sum_t [t_j > 0] p_t (the threshold-detection expectation values of
+  Sec. II-B and Fig. 3), by that definition.
 * Threshold-detector click probabilities P(c) = sum of p_t over the states
   t whose occupied modes are exactly c (the detector model of Sec. II-B),
   patterns ordered by click count, then lexicographically.
@@ -211,6 +214,19 @@ def mode_expectations(U: np.ndarray, s: Sequence[int], outputs: Optional[np.ndar
     if n == 0:
         return np.zeros(m)
     return probabilities(U, s, outputs.astype(np.int32)) @ outputs
+
+
+def mode_click_probabilities(U: np.ndarray, s: Sequence[int], outputs: Optional[np.ndarray] = None) -> np.ndarray:
+    """P(t_j > 0) = sum_t [t_j > 0] p_t over `outputs` (default: the whole basis)."""
+    U = np.ascontiguousarray(U, dtype=np.complex128)
+    m = U.shape[0]
+    n = int(np.sum(s))
+    if outputs is None:
+        outputs = fock_basis(m, n)
+    outputs = np.asarray(outputs, dtype=np.int32).reshape(-1, m)
+    if n == 0:
+        return np.zeros(m)
+    return probabilities(U, s, outputs) @ (outputs > 0).astype(np.float64)
 
 
 def superposition_amplitudes(U: np.ndarray, states: Sequence[Sequence[int]], x: Sequence[complex]) -> np.ndarray:

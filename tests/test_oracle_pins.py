@@ -524,3 +524,20 @@ def test_superposition_amplitudes_pins():
     U = _haar(rng, m)
     x /= np.linalg.norm(x)
     assert abs(np.linalg.norm(O.superposition_amplitudes(U, comps, x)) - 1) < 1e-12
+
+
+def test_mode_click_probabilities_closed_forms():
+    rng = np.random.default_rng(33)
+    U = _haar(rng, 4)
+    # one photon: a click is the photon, P = |U_ji|^2
+    assert np.abs(O.mode_click_probabilities(U, [0, 0, 1, 0]) - np.abs(U[:, 2]) ** 2).max() < 1e-14
+    # two photons from mode 1: P(click j) = |U_j1|^2 (2 - |U_j1|^2)
+    q = np.abs(U[:, 1]) ** 2
+    assert np.abs(O.mode_click_probabilities(U, [0, 2, 0, 0]) - q * (2 - q)).max() < 1e-14
+    # Hong-Ou-Mandel: the photons leave together, each detector clicks half the time
+    bs = np.array([[1, 1j], [1j, 1]]) / np.sqrt(2)
+    assert np.abs(O.mode_click_probabilities(bs, [1, 1]) - [0.5, 0.5]).max() < 1e-15
+    # clicks never exceed photons: sum_j P(click j) <= n, and <= the PNR expectations mode by mode
+    s = [1, 1, 1, 0]
+    c, e = O.mode_click_probabilities(U, s), O.mode_expectations(U, s)
+    assert c.sum() <= 3 + 1e-12 and np.all(c <= e + 1e-14)
