@@ -264,6 +264,19 @@ SLOS_API int fock_mode_expectations(slos_batch_t batch, const float* U, float* o
 SLOS_API int fock_mode_expectations_backward(slos_batch_t batch, const float* U, const float* grad_out,
                                              float* grad_U, void* ws, size_t ws_bytes, void* stream);
 
+/* Detector models for the per-mode expectations (Sec. II-B; Fig. 3). */
+#define SLOS_DETECTOR_PNR 0        /* photon-number resolving: <n_j> = sum_t t_j p_t */
+#define SLOS_DETECTOR_THRESHOLD 1  /* click or no click: P(t_j > 0) = sum_t [t_j > 0] p_t */
+
+/* fock_mode_expectations / fock_mode_expectations_backward with a detector
+ * model (the plain calls are SLOS_DETECTOR_PNR); same buffers, workspace
+ * and configuration.  SLOS_EINVAL for an unknown model. */
+SLOS_API int fock_mode_expectations_ex(slos_batch_t batch, const float* U, float* out, int detector,
+                                       void* ws, size_t ws_bytes, void* stream);
+SLOS_API int fock_mode_expectations_backward_ex(slos_batch_t batch, const float* U, const float* grad_out,
+                                                float* grad_U, int detector, void* ws, size_t ws_bytes,
+                                                void* stream);
+
 /* ---- Amplitude-encoded inputs (Sec. II-C-2) -------------------------------- */
 /*
  * An amplitude-encoded input is a superposition sum_c x_c |s_c> of Fock

@@ -33,6 +33,8 @@ OP_MODE_EXPECTATIONS_BACKWARD = 5
 OP_THRESHOLD_PROBS = 6
 OP_THRESHOLD_PROBS_BACKWARD = 7
 OP_SAMPLE = 8
+DETECTOR_PNR = 0
+DETECTOR_THRESHOLD = 1
 
 PLAN_DEFAULT = 0
 PLAN_FORWARD_ONLY = 1
@@ -74,6 +76,8 @@ SIGNATURES = {
     "fock_probs_backward": (_c.c_int, [_vp, _vp, _vp, _vp, _vp, _c.c_size_t, _vp]),
     "fock_mode_expectations": (_c.c_int, [_vp, _vp, _vp, _vp, _c.c_size_t, _vp]),
     "fock_mode_expectations_backward": (_c.c_int, [_vp, _vp, _vp, _vp, _vp, _c.c_size_t, _vp]),
+    "fock_mode_expectations_ex": (_c.c_int, [_vp, _vp, _vp, _c.c_int, _vp, _c.c_size_t, _vp]),
+    "fock_mode_expectations_backward_ex": (_c.c_int, [_vp, _vp, _vp, _vp, _c.c_int, _vp, _c.c_size_t, _vp]),
     "slos_threshold_dim": (_c.c_int64, [_c.c_int, _c.c_int]),
     "slos_batch_threshold_len": (_c.c_int64, [_vp]),
     "slos_batch_threshold_offsets": (_c.c_int, [_vp, _vp]),
@@ -373,9 +377,18 @@ def fock_probs_backward(batch: Batch, U: torch.Tensor, grad_probs: torch.Tensor,
     return out
 
 
+def _detector(detector) -> int:
+    if detector in ("pnr", DETECTOR_PNR):
+        return DETECTOR_PNR
+    if detector in ("threshold", DETECTOR_THRESHOLD):
+        return DETECTOR_THRESHOLD
+    raise ValueError("detector must be 'pnr' or 'threshold'")
+
+
 def fock_mode_expectations(batch: Batch, U: torch.Tensor, out: Optional[torch.Tensor] = None,
-                           ws: Optional[torch.Tensor] = None) -> torch.Tensor:
-    """Per-mode photon-number expectations <n_j> = sum_t t_j p_t, float32 [B, m]."""
+                           ws: Optional[torch.Tensor] = None, detector="pnr") -> torch.Tensor:
+    """Per-mode photon-number expectations <n_j> = sum_t t_j p_t, float32 [B, m]
+    (detector="threshold": click probabilities sum_t [t_j > 0] p_t)."""
     _require(U, "U", torch.complex64, (batch.B, batch.m, batch.m))
     if out is None:
         out = torch.empty((batch.B, batch.m), dtype=torch.float32, device=U.device)
@@ -383,14 +396,15 @@ def fock_mode_expectations(batch: Batch, U: torch.Tensor, out: Optional[torch.Te
     if ws is None:
         ws = batch.workspace(OP_MODE_EXPECTATIONS, U.device)
     wp, wn = _ws_args(ws)
-    _check("fock_mode_expectations",
-           lib().fock_mode_expectations(batch.handle, _ptr(U), _ptr(out), wp, wn, _stream_ptr(U.device)))
+    _check("fock_mode_expectations_ex",
+           lib().fock_mode_expectations_ex(batch.handle, _ptr(U), _ptr(out), _detector(detector), wp, wn,
+                                           _stream_ptr(U.device)))
     return out
 
 
 def fock_mode_expectations_backward(batch: Batch, U: torch.Tensor, grad_out: torch.Tensor,
                                     out: Optional[torch.Tensor] = None,
-                                    ws: Optional[torch.Tensor] = None) -> torch.Tensor:
+                                    ws: Optional[torch.Tensor] = None, detector="pnr") -> torch.Tensor:
     _require(U, "U", torch.complex64, (batch.B, batch.m, batch.m))
     _require(grad_out, "grad_out", torch.float32, (batch.B, batch.m))
     if out is None:
@@ -399,9 +413,9 @@ def fock_mode_expectations_backward(batch: Batch, U: torch.Tensor, grad_out: tor
     if ws is None:
         ws = batch.workspace(OP_MODE_EXPECTATIONS_BACKWARD, U.device)
     wp, wn = _ws_args(ws)
-    _check("fock_mode_expectations_backward",
-           lib().fock_mode_expectations_backward(batch.handle, _ptr(U), _ptr(grad_out), _ptr(out), wp, wn,
-                                                 _stream_ptr(U.device)))
+    _check("fock_mode_expectations_backward_ex",
+           lib().fock_mode_expectations_backward_ex(batch.handle, _ptr(U), _ptr(grad_out), _ptr(out),
+                                                    _detector(detector), wp, wn, _stream_ptr(U.device)))
     return out
 
 

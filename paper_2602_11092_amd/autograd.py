@@ -56,17 +56,18 @@ class FockModeExpectations(torch.autograd.Function):
     """U [B, m, m] complex64 -> per-mode photon-number expectations float32 [B, m]."""
 
     @staticmethod
-    def forward(ctx, U: torch.Tensor, batch: B.Batch):
+    def forward(ctx, U: torch.Tensor, batch: B.Batch, detector="pnr"):
         U = _dense(U, torch.complex64)
         ctx.batch = batch
+        ctx.detector = detector
         ctx.save_for_backward(U)
-        return B.fock_mode_expectations(batch, U)
+        return B.fock_mode_expectations(batch, U, detector=detector)
 
     @staticmethod
     def backward(ctx, grad_e):
         (U,) = ctx.saved_tensors
-        gU = B.fock_mode_expectations_backward(ctx.batch, U, _dense(grad_e, torch.float32))
-        return gU, None
+        gU = B.fock_mode_expectations_backward(ctx.batch, U, _dense(grad_e, torch.float32), detector=ctx.detector)
+        return gU, None, None
 
 
 class FockThresholdProbs(torch.autograd.Function):
@@ -158,8 +159,8 @@ def fock_amplitudes(U: torch.Tensor, batch: B.Batch) -> torch.Tensor:
     return FockAmplitudes.apply(U, batch)
 
 
-def fock_mode_expectations(U: torch.Tensor, batch: B.Batch) -> torch.Tensor:
-    return FockModeExpectations.apply(U, batch)
+def fock_mode_expectations(U: torch.Tensor, batch: B.Batch, detector="pnr") -> torch.Tensor:
+    return FockModeExpectations.apply(U, batch, detector)
 
 
 def fock_threshold_probs(U: torch.Tensor, batch: B.Batch) -> torch.Tensor:

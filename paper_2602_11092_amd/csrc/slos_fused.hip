@@ -210,7 +210,7 @@ __device__ __forceinline__ LayerDev layer(const LayerDev* Ls, int k) {
 // previous slot's mode.  The group loads of all SU states are issued
 // together.  The lane's own column needs no atomics (LDS float atomics are
 // several times slower here than a read and a write).
-template <int BLOCK, int SU>
+template <int BLOCK, int SU, bool DISTINCT>
 __device__ __forceinline__ void photons_into_lds(const LayerDev& L, int k, int t0, int N, const float (&pv)[SU],
                                                  uint32_t accb) {
     const uint32_t gstride = (uint32_t)N * 16u;
@@ -231,7 +231,7 @@ __device__ __forceinline__ void photons_into_lds(const LayerDev& L, int k, int t
                 const int md = (int)(comp(e[u], q) >> L.pred_shift);
                 cur[u] = md == 32 ? cur[u] : md;
                 const uint32_t a = col + 4u * (uint32_t)(cur[u] * BLOCK);
-                lds_stf(a, lds_ldf(a) + pv[u]);
+                if (!DISTINCT || md != 32) lds_stf(a, lds_ldf(a) + pv[u]);
             }
         }
     }
@@ -241,12 +241,14 @@ __device__ __forceinline__ void photons_into_lds(const LayerDev& L, int k, int t
 // expectations, out[b][j] = sum_t t_j p_t ([B][m]): p_t is added to a
 // per-lane LDS accumulator for each photon's mode (lane tid owns column tid
 // of the [m][BLOCK] array after the state buffers, so no atomics), and the
-// columns are summed once per sample; p is never written.
+// columns are summed once per sample; p is never written.  3: the same with
+// one count per occupied mode, sum_t [t_j > 0] p_t (threshold detectors).
 template <int BLOCK, int EPI>
 __global__ __launch_bounds__(BLOCK) void fused_fwd_kernel(int m, const LayerDev* __restrict__ Ls, BatchDev Bt,
                                                           const float2* __restrict__ U, void* __restrict__ out,
                                                           int S) {
     constexpr bool PROBS = EPI >= 1;
+    constexpr bool EXPECT = EPI >= 2;  // 2: per photon (<n_j>), 3: per occupied mode (clicks)
     extern __shared__ float2 lds[];  // ucol at kUcolAddr, photon layers from kXAddr, accumulators after them
     const int tid = threadIdx.x;
     const uint32_t accb = kXAddr + 8u * (uint32_t)S;
@@ -259,7 +261,7 @@ __global__ __launch_bounds__(BLOCK) void fused_fwd_kernel(int m, const LayerDev*
         const float2* Ub = U + (size_t)b * m * m;
         const int32_t* modes = Bt.modes + (size_t)b * kMaxPhotons;  // read through ldg
         if (n == 0) {
-            if (EPI == 2) {
+            if (EXPECT) {
                 if (tid < m) ((float*)out)[(size_t)b * m + tid] = 0.f;  // the vacuum has no photons
             } else if (tid == 0) {
                 if (PROBS) ((float*)out)[off] = 1.f;
@@ -267,7 +269,7 @@ __global__ __launch_bounds__(BLOCK) void fused_fwd_kernel(int m, const LayerDev*
             }
             continue;
         }
-        if (EPI == 2)
+        if (EXPECT)
             for (int j = 0; j < m; ++j) lds_stf(accb + 4u * (uint32_t)(j * BLOCK + tid), 0.f);
         for (int k = 1; k <= n; ++k) {
             if (tid < m) lds_st(kUcolAddr + 8 * tid, Ub[tid * m + ldc(modes + (k - 1))]);
@@ -284,7 +286,7 @@ __global__ __launch_bounds__(BLOCK) void fused_fwd_kernel(int m, const LayerDev*
                 const __amdgpu_buffer_rsrc_t rn = buf_rsrc(L.nrm, (uint32_t)N * 4u);
                 const __amdgpu_buffer_rsrc_t ro =
                     buf_rsrc(PROBS ? (const void*)((float*)out + off) : (const void*)((float2*)out + off),
-                             EPI == 2 ? 0u : (uint32_t)N * (PROBS ? 4u : 8u));
+                             EXPECT ? 0u : (uint32_t)N * (PROBS ? 4u : 8u));
                 for (int t0 = tid; t0 < N; t0 += BLOCK * kLU) {
                     float c[kLU];
 #pragma unroll
@@ -295,7 +297,7 @@ __global__ __launch_bounds__(BLOCK) void fused_fwd_kernel(int m, const LayerDev*
 #pragma unroll
                     for (int u = 0; u < kLU; ++u) {
                         const int t = t0 + u * BLOCK;
-                        if (EPI != 2 && t < N) {
+                        if (!EXPECT && t < N) {
                             if (PROBS) {
                                 const float p = c[u] * c[u] * (acc[u].x * acc[u].x + acc[u].y * acc[u].y);
                                 __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(p), ro, t * 4, 0, kCpolStream);
@@ -306,18 +308,18 @@ __global__ __launch_bounds__(BLOCK) void fused_fwd_kernel(int m, const LayerDev*
                             }
                         }
                     }
-                    if (EPI == 2) {
+                    if (EXPECT) {
                         float pv[kLU];
 #pragma unroll
                         for (int u = 0; u < kLU; ++u)  // lanes past N add zero
                             pv[u] = t0 + u * BLOCK < N ? c[u] * c[u] * (acc[u].x * acc[u].x + acc[u].y * acc[u].y) : 0.f;
-                        photons_into_lds<BLOCK, kLU>(L, k, t0, N, pv, accb);
+                        photons_into_lds<BLOCK, kLU, EPI == 3>(L, k, t0, N, pv, accb);
                     }
                 }
             }
             __syncthreads();
         }
-        if (EPI == 2) {
+        if (EXPECT) {
             // column sums: wave w takes modes w, w + BLOCK/64, ...; fixed order
             const int w = tid >> 6, lane = tid & 63;
             for (int j = w; j < m; j += BLOCK / 64) {
@@ -735,8 +737,10 @@ bool compact_tables(const slos_plan_s& P, int n_max) {
 
 template <int BLOCK>
 void* fwd_fn(int epi) {
-    return epi == 0 ? (void*)&fused_fwd_kernel<BLOCK, 0>
-                    : epi == 1 ? (void*)&fused_fwd_kernel<BLOCK, 1> : (void*)&fused_fwd_kernel<BLOCK, 2>;
+    return epi == 0   ? (void*)&fused_fwd_kernel<BLOCK, 0>
+           : epi == 1 ? (void*)&fused_fwd_kernel<BLOCK, 1>
+           : epi == 2 ? (void*)&fused_fwd_kernel<BLOCK, 2>
+                      : (void*)&fused_fwd_kernel<BLOCK, 3>;
 }
 
 void* pick_fwd(int block, int epi) {
@@ -881,10 +885,10 @@ int launch_fused_fwd(const slos_batch_s& Bt, int block, const float2* U, void* o
                      hipStream_t stream) {
     const slos_plan_s& P = *Bt.plan;
     std::string why;
-    if (!fused_fwd_supported(P, Bt.n_max, block, &why, epi == 2))
+    if (!fused_fwd_supported(P, Bt.n_max, block, &why, epi >= 2))
         return fail(SLOS_EUNSUPPORTED, "fused forward: " + why);
     void* fn = pick_fwd(block, epi);
-    const size_t lds = fwd_lds_for(P, Bt.n_max, block, epi == 2);
+    const size_t lds = fwd_lds_for(P, Bt.n_max, block, epi >= 2);
     hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     const int grid = grid_for(P, fn, block, lds, Bt.B);
     const int S = (int)lds_fwd_states(P, Bt.n_max);

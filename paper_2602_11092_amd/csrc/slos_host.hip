@@ -727,10 +727,10 @@ namespace {
 // and reduces it; the adjoint expands dL/d<n_j> into dL/dp in the workspace
 // and runs the probability adjoint on it.
 int run_expect(const slos_batch_s& Bt, int op, int v, int blk, const float* U, const void* gin, void* out,
-               void* ws, size_t ws_bytes, hipStream_t s, const std::string& nm) {
+               void* ws, size_t ws_bytes, hipStream_t s, const std::string& nm, bool clicks) {
     const bool bwd = op == SLOS_OP_MODE_EXPECTATIONS_BACKWARD;
     const bool fused = v == SLOS_VARIANT_FUSED;
-    if (!bwd && fused) return launch_fused_fwd(Bt, blk, (const float2*)U, out, 2, s);
+    if (!bwd && fused) return launch_fused_fwd(Bt, blk, (const float2*)U, out, clicks ? 3 : 2, s);
     // workspace: [p or dL/dp][partial sums (forward)][layered workspace]
     const size_t head = expect_head_bytes(Bt);
     const size_t parts = bwd ? 0 : align256(mode_expect_part_bytes(Bt));
@@ -742,10 +742,10 @@ int run_expect(const slos_batch_s& Bt, int op, int v, int blk, const float* U, c
     int rc;
     if (!bwd) {
         rc = launch_layered_fwd(Bt, blk, (const float2*)U, pv, true, rest, s);
-        if (rc == SLOS_OK) rc = launch_mode_expect(Bt, pv, (float*)((char*)ws + head), (float*)out, s);
+        if (rc == SLOS_OK) rc = launch_mode_expect(Bt, pv, (float*)((char*)ws + head), (float*)out, clicks, s);
         return rc;
     }
-    rc = launch_expand_mode_weights(Bt, (const float*)gin, pv, s);
+    rc = launch_expand_mode_weights(Bt, (const float*)gin, pv, clicks, s);
     if (rc != SLOS_OK) return rc;
     return fused ? launch_fused_bwd(Bt, blk, (const float2*)U, pv, true, (float2*)out, s)
                  : launch_layered_bwd(Bt, blk, (const float2*)U, pv, true, (float2*)out, rest, s);
@@ -780,7 +780,7 @@ int run_threshold(const slos_batch_s& Bt, int op, int v, int blk, const float* U
 }
 
 int run(slos_batch_t batch, int op, const float* U, const void* gin, void* out, void* ws, size_t ws_bytes,
-        void* stream) {
+        void* stream, int detector = SLOS_DETECTOR_PNR) {
     static const char* names[8] = {"fock_amplitudes", "fock_probs", "fock_amplitudes_backward",
                                    "fock_probs_backward", "fock_mode_expectations",
                                    "fock_mode_expectations_backward", "fock_threshold_probs",
@@ -798,7 +798,8 @@ int run(slos_batch_t batch, int op, const float* U, const void* gin, void* out, 
     resolve(*batch, op, &v, &blk);
     const bool probs = (op == SLOS_OP_PROBS || op == SLOS_OP_PROBS_BACKWARD);
     hipStream_t s = (hipStream_t)stream;
-    if (op_expect(op)) return run_expect(*batch, op, v, blk, U, gin, out, ws, ws_bytes, s, nm);
+    if (op_expect(op))
+        return run_expect(*batch, op, v, blk, U, gin, out, ws, ws_bytes, s, nm, detector == SLOS_DETECTOR_THRESHOLD);
     if (op_threshold(op)) return run_threshold(*batch, op, v, blk, U, gin, out, ws, ws_bytes, s, nm);
     int rc;
     if (v == SLOS_VARIANT_FUSED) {
@@ -1229,4 +1230,19 @@ extern "C" int fock_mode_expectations(slos_batch_t batch, const float* U, float*
 extern "C" int fock_mode_expectations_backward(slos_batch_t batch, const float* U, const float* grad_out,
                                                float* grad_U, void* ws, size_t ws_bytes, void* stream) {
     return run(batch, SLOS_OP_MODE_EXPECTATIONS_BACKWARD, U, grad_out, grad_U, ws, ws_bytes, stream);
+}
+
+extern "C" int fock_mode_expectations_ex(slos_batch_t batch, const float* U, float* out, int detector, void* ws,
+                                         size_t ws_bytes, void* stream) {
+    if (detector != SLOS_DETECTOR_PNR && detector != SLOS_DETECTOR_THRESHOLD)
+        return fail(SLOS_EINVAL, "fock_mode_expectations_ex: unknown detector model");
+    return run(batch, SLOS_OP_MODE_EXPECTATIONS, U, nullptr, out, ws, ws_bytes, stream, detector);
+}
+
+extern "C" int fock_mode_expectations_backward_ex(slos_batch_t batch, const float* U, const float* grad_out,
+                                                  float* grad_U, int detector, void* ws, size_t ws_bytes,
+                                                  void* stream) {
+    if (detector != SLOS_DETECTOR_PNR && detector != SLOS_DETECTOR_THRESHOLD)
+        return fail(SLOS_EINVAL, "fock_mode_expectations_backward_ex: unknown detector model");
+    return run(batch, SLOS_OP_MODE_EXPECTATIONS_BACKWARD, U, grad_out, grad_U, ws, ws_bytes, stream, detector);
 }

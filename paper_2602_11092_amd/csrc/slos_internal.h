@@ -111,7 +111,8 @@ size_t fused_bwd_lds_bytes(const slos_plan_s& P, int n_max);
 bool fused_fwd_supported(const slos_plan_s& P, int n_max, int block, std::string* why, bool expect = false);
 bool fused_bwd_supported(const slos_plan_s& P, int n_max, int block, std::string* why);
 int fused_default_block(const slos_plan_s& P, int n_max, bool backward);
-// epi: 0 amplitudes, 1 probabilities, 2 per-mode expectations ([B][m] floats)
+// epi: 0 amplitudes, 1 probabilities, 2 per-mode expectations, 3 per-mode
+// click probabilities (both [B][m] floats)
 int launch_fused_fwd(const slos_batch_s& Bt, int block, const float2* U, void* out, int epi,
                      hipStream_t stream);
 int launch_fused_bwd(const slos_batch_s& Bt, int block, const float2* U, const void* gin, bool probs,
@@ -130,10 +131,12 @@ int launch_layered_bwd(const slos_batch_s& Bt, int block, const float2* U, const
 constexpr int64_t kMeasureChunkStates = 16384;
 // out[b][j] = sum_t t_j p[off_b + t] (p: the batch's probabilities), via
 // per-chunk partial sums in `part` (mode_expect_part_bytes bytes)
+// (distinct: per-mode click probabilities, sum_t [t_j > 0] p[off_b + t])
 size_t mode_expect_part_bytes(const slos_batch_s& Bt);
-int launch_mode_expect(const slos_batch_s& Bt, const float* p, float* part, float* out, hipStream_t stream);
-// gp[off_b + t] = sum_j t_j w[b][j]
-int launch_expand_mode_weights(const slos_batch_s& Bt, const float* w, float* gp, hipStream_t stream);
+int launch_mode_expect(const slos_batch_s& Bt, const float* p, float* part, float* out, bool distinct,
+                       hipStream_t stream);
+// gp[off_b + t] = sum_j t_j w[b][j]  (distinct: sum_j [t_j > 0] w[b][j])
+int launch_expand_mode_weights(const slos_batch_s& Bt, const float* w, float* gp, bool distinct, hipStream_t stream);
 // out[thr_off_b + q] = sum of p over click pattern q's states
 int launch_threshold_gather(const slos_batch_s& Bt, const float* p, float* out, hipStream_t stream);
 // gp[off_b + t] = gP[thr_off_b + pattern(t)]
@@ -234,11 +237,12 @@ __device__ __forceinline__ float lds_ldf(uint32_t a) { return *(const lds_f32*)(
 __device__ __forceinline__ void lds_stf(uint32_t a, float v) { *(lds_f32*)(size_t)a = v; }
 
 
-// Calls f(mode) once per photon of state t of photon layer L (k photons).
-// The state's predecessor entries list its sorted modes, one slot per
-// photon; an empty entry (mode field 32) repeats the previous slot's mode,
-// and slots past k are padding.  64-bit indexing: any layer size.
-template <class F>
+// Calls f(mode) once per photon of state t of photon layer L (k photons),
+// or, with DISTINCT, once per occupied mode.  The state's predecessor
+// entries list its sorted modes, one slot per photon; an empty entry (mode
+// field 32) repeats the previous slot's mode, and slots past k are padding.
+// 64-bit indexing: any layer size.
+template <bool DISTINCT = false, class F>
 __device__ __forceinline__ void for_each_photon(const slos::LayerDev& L, int k, int64_t t, F&& f) {
     int cur = 0;
     for (int g = 0; g < L.ngrp; ++g) {
@@ -250,7 +254,7 @@ __device__ __forceinline__ void for_each_photon(const slos::LayerDev& L, int k, 
             if (4 * g + q >= k) break;
             const int md = (int)(ev[q] >> L.pred_shift);
             if (md != 32) cur = md;
-            f(cur);
+            if (!DISTINCT || md != 32) f(cur);
         }
     }
 }

@@ -5,6 +5,8 @@
 //   <n_j>_b      = sum_t t_j p_b[t]     (mode_expect_partial_kernel, then
 //                                         mode_expect_final_kernel)
 //   dL/dp_b[t]   = sum_j t_j dL/d<n_j>_b  (expand_kernel)
+//   (DISTINCT instances: t_j replaced by [t_j > 0], the per-mode click
+//    probabilities of threshold detectors and their adjoint)
 //   P_b(c)       = sum of p_b over the states of click pattern c
 //                                         (threshold_gather_kernel)
 //   dL/dp_b[t]   = dL/dP_b(pattern of t)  (threshold_scatter_kernel)
@@ -28,6 +30,7 @@ static_assert(kParts * kMaxModes == kMeasureBlock, "one thread per (mode, part)"
 
 // Stage 1: workgroup (b, c) sums states [c*kChunkStates, (c+1)*kChunkStates)
 // of sample b into part[b][c][j] (zero where the chunk holds no state).
+template <bool DISTINCT>
 __global__ __launch_bounds__(kMeasureBlock) void mode_expect_partial_kernel(int m, const LayerDev* __restrict__ Ls,
                                                                             BatchDev Bt, const float* __restrict__ p,
                                                                             float* __restrict__ part, int C) {
@@ -43,7 +46,7 @@ __global__ __launch_bounds__(kMeasureBlock) void mode_expect_partial_kernel(int 
         const int64_t lo = (int64_t)c * kChunkStates, hi = lo + kChunkStates < L.N ? lo + kChunkStates : L.N;
         for (int64_t t = lo + tid; t < hi; t += kMeasureBlock) {
             const float v = p[off + t];
-            for_each_photon(L, n, t, [&](int j) { acc[j][tid] += v; });
+            for_each_photon<DISTINCT>(L, n, t, [&](int j) { acc[j][tid] += v; });
         }
     }
     __syncthreads();
@@ -70,6 +73,7 @@ __global__ __launch_bounds__(kMeasureBlock) void mode_expect_final_kernel(int m,
 
 // gp[off_b + t] = sum_j t_j w[b][j] for the states of chunk c of sample b
 // (workgroup b * C + c).
+template <bool DISTINCT>
 __global__ __launch_bounds__(kMeasureBlock) void expand_kernel(int m, const LayerDev* __restrict__ Ls, BatchDev Bt,
                                                                const float* __restrict__ w,
                                                                float* __restrict__ gp, int C) {
@@ -88,7 +92,7 @@ __global__ __launch_bounds__(kMeasureBlock) void expand_kernel(int m, const Laye
     const int64_t lo = (int64_t)c * kChunkStates, hi = lo + kChunkStates < L.N ? lo + kChunkStates : L.N;
     for (int64_t t = lo + tid; t < hi; t += kMeasureBlock) {
         float g = 0.f;
-        for_each_photon(L, n, t, [&](int j) { g += wb[j]; });
+        for_each_photon<DISTINCT>(L, n, t, [&](int j) { g += wb[j]; });
         gp[off + t] = g;
     }
 }
@@ -419,14 +423,15 @@ size_t mode_expect_part_bytes(const slos_batch_s& Bt) {
     return (size_t)Bt.B * mode_expect_chunks(Bt) * Bt.plan->m * sizeof(float);
 }
 
-int launch_mode_expect(const slos_batch_s& Bt, const float* p, float* part, float* out, hipStream_t stream) {
+int launch_mode_expect(const slos_batch_s& Bt, const float* p, float* part, float* out, bool distinct,
+                       hipStream_t stream) {
     const slos_plan_s& P = *Bt.plan;
     int m = P.m, B = Bt.B;
     int C = (int)mode_expect_chunks(Bt);
     if ((int64_t)B * C >= ((int64_t)1 << 31)) return fail(SLOS_EUNSUPPORTED, "mode expectations: batch too large");
     void* a1[] = {(void*)&m, (void*)&P.d_layers, (void*)&Bt.dev, (void*)&p, (void*)&part, (void*)&C};
-    hipError_t e = hipLaunchKernel((void*)&mode_expect_partial_kernel, dim3((unsigned)(B * C)), dim3(kMeasureBlock),
-                                   a1, 0, stream);
+    void* fn = distinct ? (void*)&mode_expect_partial_kernel<true> : (void*)&mode_expect_partial_kernel<false>;
+    hipError_t e = hipLaunchKernel(fn, dim3((unsigned)(B * C)), dim3(kMeasureBlock), a1, 0, stream);
     if (e != hipSuccess) return fail(SLOS_EHIP, std::string("mode expectation launch: ") + hipGetErrorString(e));
     void* a2[] = {(void*)&m, (void*)&B, (void*)&C, (void*)&part, (void*)&out};
     const unsigned g2 = (unsigned)(((int64_t)B * m + kMeasureBlock - 1) / kMeasureBlock);
@@ -435,14 +440,14 @@ int launch_mode_expect(const slos_batch_s& Bt, const float* p, float* part, floa
     return SLOS_OK;
 }
 
-int launch_expand_mode_weights(const slos_batch_s& Bt, const float* w, float* gp, hipStream_t stream) {
+int launch_expand_mode_weights(const slos_batch_s& Bt, const float* w, float* gp, bool distinct, hipStream_t stream) {
     const slos_plan_s& P = *Bt.plan;
     int m = P.m;
     int C = (int)mode_expect_chunks(Bt);
     if ((int64_t)Bt.B * C >= ((int64_t)1 << 31)) return fail(SLOS_EUNSUPPORTED, "mode weight expansion: batch too large");
     void* args[] = {(void*)&m, (void*)&P.d_layers, (void*)&Bt.dev, (void*)&w, (void*)&gp, (void*)&C};
-    hipError_t e = hipLaunchKernel((void*)&expand_kernel, dim3((unsigned)(Bt.B * C)), dim3(kMeasureBlock), args, 0,
-                                   stream);
+    void* fn = distinct ? (void*)&expand_kernel<true> : (void*)&expand_kernel<false>;
+    hipError_t e = hipLaunchKernel(fn, dim3((unsigned)(Bt.B * C)), dim3(kMeasureBlock), args, 0, stream);
     if (e != hipSuccess) return fail(SLOS_EHIP, std::string("mode weight expansion launch: ") + hipGetErrorString(e));
     return SLOS_OK;
 }

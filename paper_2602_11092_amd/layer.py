@@ -26,16 +26,21 @@ class QuantumLayer(nn.Module):
     one photon per mode (C(m, n) of them, in the same relative order);
     "dual_rail" keeps those with at most one photon per mode pair (2g, 2g+1)
     (the 2^n logical states when n = m/2).  Their adjoint runs in the
-    layered kernels."""
+    layered kernels.  detector="threshold" turns mode_expectations into
+    per-mode click probabilities P(t_j > 0)."""
 
     def __init__(self, m: int, input_state: Sequence[int], enc_scale: float = math.pi,
-                 measurement: str = "probs", seed: int = 0, computation_space: str = "fock"):
+                 measurement: str = "probs", seed: int = 0, computation_space: str = "fock",
+                 detector: str = "pnr"):
         super().__init__()
         occ = np.asarray(input_state, dtype=np.int32)
         if occ.shape != (m,):
             raise ValueError("input_state must have m entries")
         if measurement not in ("probs", "amplitudes", "mode_expectations", "threshold_probs"):
             raise ValueError("measurement must be 'probs', 'amplitudes', 'mode_expectations' or 'threshold_probs'")
+        if detector not in ("pnr", "threshold"):
+            raise ValueError("detector must be 'pnr' or 'threshold'")
+        self.detector = detector
         if computation_space not in ("fock", "unbunched", "dual_rail"):
             raise ValueError("computation_space must be 'fock', 'unbunched' or 'dual_rail'")
         if computation_space == "unbunched" and int(occ.sum()) > m:
@@ -81,7 +86,7 @@ class QuantumLayer(nn.Module):
         if self.measurement == "probs":
             return fock_probs(U, bt).view(x.shape[0], -1)
         if self.measurement == "mode_expectations":
-            return fock_mode_expectations(U, bt)
+            return fock_mode_expectations(U, bt, self.detector)
         if self.measurement == "threshold_probs":
             return fock_threshold_probs(U, bt).view(x.shape[0], -1)
         return fock_amplitudes(U, bt).view(x.shape[0], -1)

@@ -151,3 +151,32 @@ def test_layer_mode_expectations_autograd():
     rt, rx = O.mesh_grad(th, xx, math.pi, GU)
     assert rel_err(layer.theta.grad.cpu().numpy(), rt) <= G_RTOL
     assert rel_err(x.grad.cpu().numpy(), rx) <= G_RTOL
+
+
+@pytest.mark.parametrize("variant,block", [(B.VARIANT_FUSED, 256), (B.VARIANT_FUSED, 512), (B.VARIANT_LAYERED, 256)])
+def test_click_probabilities_and_adjoint(variant, block):
+    # threshold detectors: P(t_j > 0) = sum_t [t_j > 0] p_t, with bunched inputs
+    U, occ = _mixed(15, 24, 8, 5)
+    Ud = to_dev_c64(U)
+    batch = B.Batch(B.Plan(8, int(occ.sum(1).max())), occ)
+    batch.set_config(B.OP_MODE_EXPECTATIONS, variant, block)
+    batch.set_config(B.OP_MODE_EXPECTATIONS_BACKWARD, variant, 256)
+    say("click probabilities variant", variant, "block", block)
+    c = B.fock_mode_expectations(batch, Ud, detector="threshold").cpu().numpy()
+    e = B.fock_mode_expectations(batch, Ud).cpu().numpy()
+    rng = np.random.default_rng(5)
+    w = rng.standard_normal((24, 8)).astype(np.float32)
+    gU = B.fock_mode_expectations_backward(batch, Ud, torch.from_numpy(w).to(DEV), detector="threshold")
+    gU = gU.cpu().numpy()
+    for b in range(24):
+        n = int(occ[b].sum())
+        assert np.abs(c[b] - O.mode_click_probabilities(widen(U[b]), occ[b])).max() <= E_TOL, b
+        assert np.all(c[b] <= e[b] + E_TOL)
+        if n == 0:
+            assert np.all(gU[b] == 0)
+            continue
+        basis = O.fock_basis(8, n)
+        ref = O.probs_grad(widen(U[b]), occ[b], (basis > 0).astype(np.float64) @ w[b].astype(np.float64))
+        assert rel_err(gU[b], ref) <= G_RTOL, (b, rel_err(gU[b], ref))
+    with pytest.raises(ValueError):
+        B.fock_mode_expectations(batch, Ud, detector="pnr-ish")
