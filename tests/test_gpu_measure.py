@@ -180,3 +180,25 @@ def test_click_probabilities_and_adjoint(variant, block):
         assert rel_err(gU[b], ref) <= G_RTOL, (b, rel_err(gU[b], ref))
     with pytest.raises(ValueError):
         B.fock_mode_expectations(batch, Ud, detector="pnr-ish")
+
+
+def test_layer_click_probabilities_autograd():
+    m, occ = 6, [2, 0, 1, 0, 0, 0]
+    layer = QuantumLayer(m, occ, measurement="mode_expectations", detector="threshold").to(DEV)
+    rng = np.random.default_rng(14)
+    x = torch.from_numpy(rng.standard_normal((4, m)).astype(np.float32)).to(DEV).requires_grad_(True)
+    w = torch.from_numpy(rng.standard_normal((4, m)).astype(np.float32)).to(DEV)
+    c = layer(x)
+    (c * w).sum().backward()
+    torch.cuda.synchronize()
+    th = layer.theta.detach().cpu().numpy().astype(np.float64)
+    xx = x.detach().cpu().numpy().astype(np.float64)
+    Us = O.encoded_unitaries(th, xx, math.pi)
+    ref = np.stack([O.mode_click_probabilities(U, occ) for U in Us])
+    assert np.abs(c.detach().cpu().numpy() - ref).max() <= E_TOL
+    basis = (O.fock_basis(m, 3) > 0).astype(np.float64)
+    wn = w.cpu().numpy().astype(np.float64)
+    GU = np.stack([O.probs_grad(Us[b], occ, basis @ wn[b]) for b in range(4)])
+    rt, rx = O.mesh_grad(th, xx, math.pi, GU)
+    assert rel_err(layer.theta.grad.cpu().numpy(), rt) <= G_RTOL
+    assert rel_err(x.grad.cpu().numpy(), rx) <= G_RTOL
