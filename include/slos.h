@@ -230,8 +230,13 @@ SLOS_API int fock_amplitudes(slos_batch_t batch, const float* U, float* amps,
 SLOS_API int fock_probs(slos_batch_t batch, const float* U, float* probs,
                void* ws, size_t ws_bytes, void* stream);
 
-/* ---- Backward (adjoint of the recursion; intermediate photon layers are
- *      recomputed, not stored, so calls are stateless) --------------------- */
+/* ---- Backward (Sec. II-A-3: the trainable phases of U are optimised by
+ *      gradient descent through the simulation, so the recursion needs an
+ *      adjoint).  With G = dL/dRe + i dL/dIm and the layers d_k of the
+ *      recursion, g_n = c G_a (amplitudes) or 2 (dL/dp) c^2 d_n
+ *      (probabilities), g_{k-1}[t'] = sum_j conj(U[j][i_k]) g_k[t' + e_j] and
+ *      G_U[j][i_k] += sum_t' conj(d_{k-1}[t']) g_k[t' + e_j].  Intermediate
+ *      photon layers are recomputed, not stored, so calls are stateless. -- */
 
 /* grad_U (device, complex, [B][m][m]) <- dL/dU given grad_amps = dL/da
  * (device, complex, [out_len]).  Columns of U that carry no input photon get
@@ -335,6 +340,17 @@ SLOS_API int fock_shared_superposition_amplitudes(slos_shared_superposition_t s,
 SLOS_API int fock_shared_superposition_amplitudes_backward(slos_shared_superposition_t s, const float* U,
                                                            const float* X, int G, const float* grad_out,
                                                            float* grad_U, float* grad_X, void* stream);
+
+/* Probabilities of amplitudes formed by another call (Sec. II-A-1: an output
+ * probability is the squared modulus of its amplitude), e.g. the outputs of
+ * fock_shared_superposition_amplitudes: probs[i] (device, float) <- |amps[i]|^2
+ * for i < n, amps device complex.  Asynchronous; n = 0 does nothing;
+ * SLOS_EINVAL for n < 0 or a NULL pointer when n > 0. */
+SLOS_API int fock_probs_from_amplitudes(const float* amps, int64_t n, float* probs, void* stream);
+/* Its adjoint: grad_amps[i] (device, complex) <- 2 grad_probs[i] amps[i], the
+ * gradient dL/dRe + i dL/dIm of a real loss through p = |a|^2. */
+SLOS_API int fock_probs_from_amplitudes_backward(const float* amps, const float* grad_probs, int64_t n,
+                                                 float* grad_amps, void* stream);
 
 /* ---- Measurement: threshold detectors (Sec. II-B: detector models) ------- */
 

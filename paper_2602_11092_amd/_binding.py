@@ -95,6 +95,8 @@ SIGNATURES = {
     "slos_shared_superposition_dim": (_c.c_int64, [_vp]),
     "fock_shared_superposition_amplitudes": (_c.c_int, [_vp, _vp, _vp, _c.c_int, _vp, _vp]),
     "fock_shared_superposition_amplitudes_backward": (_c.c_int, [_vp, _vp, _vp, _c.c_int, _vp, _vp, _vp, _vp]),
+    "fock_probs_from_amplitudes": (_c.c_int, [_vp, _c.c_int64, _vp, _vp]),
+    "fock_probs_from_amplitudes_backward": (_c.c_int, [_vp, _vp, _c.c_int64, _vp, _vp]),
     "fock_sample": (_c.c_int, [_vp, _vp, _vp, _c.c_int, _vp, _vp, _c.c_size_t, _vp]),
     "fock_fidelity_kernel": (_c.c_int, [_c.c_int, _vp, _vp, _c.c_int, _vp, _c.c_int, _vp, _vp]),
     "mesh_workspace_bytes": (_c.c_int, [_c.c_int, _c.c_int, _c.POINTER(_c.c_size_t)]),
@@ -154,6 +156,44 @@ def _require(t: torch.Tensor, name: str, dtype, shape=None):
         raise ValueError("%s is a lazy conj/neg view; call resolve_conj()/resolve_neg() first" % name)
     if shape is not None and tuple(t.shape) != tuple(shape):
         raise ValueError("%s must have shape %s, got %s" % (name, tuple(shape), tuple(t.shape)))
+
+
+class WorkspaceCache:
+    """Device workspaces that the binding hands to compute calls when the
+    caller passes none.
+
+    A workspace handed to a call may have been captured into a HIP graph,
+    which keeps its raw address.  So a buffer is never freed while its owner
+    lives: when a call needs more bytes, the old buffer is retired (kept
+    alive) and a larger one, rounded up to a power of two, takes its place.
+    Keys include the stream, so calls on different streams never share a
+    buffer."""
+
+    def __init__(self):
+        self._live = {}
+        self._retired = []
+
+    @staticmethod
+    def _round(nbytes: int) -> int:
+        return 1 << max(8, (max(int(nbytes), 1) - 1).bit_length())
+
+    def get(self, key, nbytes: int, device) -> torch.Tensor:
+        dev = torch.device(device)
+        full = (key, str(dev))
+        ws = self._live.get(full)
+        if ws is None or ws.numel() < nbytes:
+            if ws is not None:
+                self._retired.append(ws)
+            ws = torch.empty(self._round(nbytes), dtype=torch.uint8, device=dev)
+            self._live[full] = ws
+        return ws
+
+    def retired(self) -> int:
+        return len(self._retired)
+
+
+def _stream_key(device) -> int:
+    return int(torch.cuda.current_stream(torch.device(device)).cuda_stream)
 
 
 # ------------------------------------------------------------------ combinatorics
@@ -266,7 +306,7 @@ class Batch:
         _check("slos_batch_threshold_offsets", lib().slos_batch_threshold_offsets(h, toff.ctypes.data_as(_vp)))
         self.threshold_offsets = toff
         self.threshold_len = int(toff[-1])
-        self._ws = {}
+        self._ws = WorkspaceCache()
 
     @property
     def handle(self):
@@ -279,7 +319,6 @@ class Batch:
 
     def set_config(self, op: int, variant: int, block: int = 0):
         _check("slos_batch_set_config", lib().slos_batch_set_config(self._h, op, variant, block))
-        self._ws.pop(op, None)
 
     def get_config(self, op: int) -> Tuple[int, int]:
         v, b = ctypes.c_int(0), ctypes.c_int(0)
@@ -287,15 +326,13 @@ class Batch:
         return int(v.value), int(b.value)
 
     def workspace(self, op: int, device) -> Optional[torch.Tensor]:
-        """Device workspace for `op`, allocated once and reused."""
+        """Device workspace for `op` on the current stream, kept by the batch
+        (see WorkspaceCache: buffers are retired, never freed, so a captured
+        graph's workspace outlives later calls that need more)."""
         need = self.workspace_bytes(op)
         if need == 0:
             return None
-        ws = self._ws.get(op)
-        if ws is None or ws.numel() < need or ws.device != torch.device(device):
-            ws = torch.empty(need, dtype=torch.uint8, device=device)
-            self._ws[op] = ws
-        return ws
+        return self._ws.get((op, _stream_key(device)), need, device)
 
     def close(self):
         if self._h is not None and self._h.value:
@@ -468,7 +505,7 @@ class Superposition:
         oo = np.zeros(self.G + 1, dtype=np.int64)
         _check("slos_superposition_out_offsets", lib().slos_superposition_out_offsets(h, oo.ctypes.data_as(_vp)))
         self.out_offsets = oo
-        self._ws = {}
+        self._ws = WorkspaceCache()
 
     @property
     def handle(self):
@@ -478,11 +515,7 @@ class Superposition:
         n = ctypes.c_size_t(0)
         _check("slos_superposition_workspace_bytes",
                lib().slos_superposition_workspace_bytes(self._h, int(backward), ctypes.byref(n)))
-        ws = self._ws.get(backward)
-        if ws is None or ws.numel() < n.value or ws.device != torch.device(device):
-            ws = torch.empty(max(int(n.value), 1), dtype=torch.uint8, device=device)
-            self._ws[backward] = ws
-        return ws
+        return self._ws.get((bool(backward), _stream_key(device)), int(n.value), device)
 
     def close(self):
         if self._h is not None and self._h.value:
@@ -592,6 +625,31 @@ def fock_shared_superposition_amplitudes_backward(s: SharedSuperposition, U: tor
     return gU, gX
 
 
+def fock_probs_from_amplitudes(a: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """|a|^2 elementwise (complex64 in, float32 out of the same shape)."""
+    _require(a, "amps", torch.complex64)
+    if out is None:
+        out = torch.empty(a.shape, dtype=torch.float32, device=a.device)
+    _require(out, "probs", torch.float32, tuple(a.shape))
+    _check("fock_probs_from_amplitudes",
+           lib().fock_probs_from_amplitudes(_ptr(a), a.numel(), _ptr(out), _stream_ptr(a.device)))
+    return out
+
+
+def fock_probs_from_amplitudes_backward(a: torch.Tensor, grad_p: torch.Tensor,
+                                        out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """dL/da = 2 (dL/dp) a for p = |a|^2."""
+    _require(a, "amps", torch.complex64)
+    _require(grad_p, "grad_probs", torch.float32, tuple(a.shape))
+    if out is None:
+        out = torch.empty_like(a)
+    _require(out, "grad_amps", torch.complex64, tuple(a.shape))
+    _check("fock_probs_from_amplitudes_backward",
+           lib().fock_probs_from_amplitudes_backward(_ptr(a), _ptr(grad_p), a.numel(), _ptr(out),
+                                                     _stream_ptr(a.device)))
+    return out
+
+
 def fock_sample(batch: Batch, U: torch.Tensor, u: torch.Tensor, out: Optional[torch.Tensor] = None,
                 ws: Optional[torch.Tensor] = None) -> torch.Tensor:
     """Shots drawn from p / sum(p) by inverse transform of the uniforms u
@@ -639,18 +697,16 @@ def fock_fidelity_kernel(occ, U1: torch.Tensor, U2: Optional[torch.Tensor] = Non
 
 # ------------------------------------------------------------------ mesh
 
-_mesh_ws = {}
+_mesh_ws = WorkspaceCache()
 
 
 def mesh_workspace(m: int, B: int, device) -> torch.Tensor:
+    """Workspace of the mesh calls on the current stream, shared by every
+    caller on that stream and device; buffers that become too small are
+    retired, never freed (WorkspaceCache)."""
     n = ctypes.c_size_t(0)
     _check("mesh_workspace_bytes", lib().mesh_workspace_bytes(m, B, ctypes.byref(n)))
-    key = (str(device),)
-    ws = _mesh_ws.get(key)
-    if ws is None or ws.numel() < n.value:
-        ws = torch.empty(int(n.value), dtype=torch.uint8, device=device)
-        _mesh_ws[key] = ws
-    return ws
+    return _mesh_ws.get(("mesh", _stream_key(device)), int(n.value), device)
 
 
 def mesh_to_unitary(theta: torch.Tensor, x: Optional[torch.Tensor], enc_scale: float, m: Optional[int] = None,

@@ -126,6 +126,21 @@ class FockSharedSuperposition(torch.autograd.Function):
         return gU, gX, None
 
 
+class ProbsFromAmplitudes(torch.autograd.Function):
+    """a (complex64, any shape) -> |a|^2 (float32), computed by the library."""
+
+    @staticmethod
+    def forward(ctx, a: torch.Tensor):
+        a = _dense(a, torch.complex64)
+        ctx.save_for_backward(a)
+        return B.fock_probs_from_amplitudes(a)
+
+    @staticmethod
+    def backward(ctx, grad_p):
+        (a,) = ctx.saved_tensors
+        return B.fock_probs_from_amplitudes_backward(a, _dense(grad_p, torch.float32))
+
+
 class MeshToUnitary(torch.autograd.Function):
     """theta [m(m-1)] float32 and features x [B, m] float32 (or None) ->
     U [B, m, m] complex64."""
@@ -173,6 +188,10 @@ def fock_superposition_amplitudes(U: torch.Tensor, x: torch.Tensor, sup: B.Super
 
 def fock_shared_superposition_amplitudes(U: torch.Tensor, X: torch.Tensor, s: B.SharedSuperposition) -> torch.Tensor:
     return FockSharedSuperposition.apply(U, X, s)
+
+
+def probs_from_amplitudes(a: torch.Tensor) -> torch.Tensor:
+    return ProbsFromAmplitudes.apply(a)
 
 
 def mesh_to_unitary(theta: torch.Tensor, x: Optional[torch.Tensor], enc_scale: float = math.pi,

@@ -1160,7 +1160,7 @@ extern "C" int fock_shared_superposition_amplitudes_backward(slos_shared_superpo
             rc = cgemm(s->blas, st, rocblas_operation_none, rocblas_operation_conjugate_transpose, N, N, G,
                        (const float2*)grad_out, N, (const float2*)X, N, s->gA, N);
         else
-            rc = hipMemsetAsync(s->gA, 0, (size_t)N * N * 8, st) == hipSuccess ? SLOS_OK : fail(SLOS_EHIP, nm + ": clear failed");
+            rc = launch_zero_c64((int64_t)N * N, s->gA, st);  // no inputs: dL/dA = 0
     }
     if (rc == SLOS_OK)
         rc = run(s->basis, SLOS_OP_AMPLITUDES_BACKWARD, (const float*)s->Urep, s->gA, (float*)s->gUc, s->ws,
@@ -1168,6 +1168,22 @@ extern "C" int fock_shared_superposition_amplitudes_backward(slos_shared_superpo
     if (rc == SLOS_OK)
         rc = launch_superposition(kSupGroupSum, s->dev, *s->basis, s->gUc, nullptr, nullptr, grad_U, st);
     return rc;
+}
+
+extern "C" int fock_probs_from_amplitudes(const float* amps, int64_t n, float* probs, void* stream) {
+    if (n < 0) return fail(SLOS_EINVAL, "fock_probs_from_amplitudes: n < 0");
+    if (n == 0) return SLOS_OK;
+    if (!amps || !probs) return fail(SLOS_EINVAL, "fock_probs_from_amplitudes: NULL device pointer");
+    return launch_abs2(n, (const float2*)amps, probs, (hipStream_t)stream);
+}
+
+extern "C" int fock_probs_from_amplitudes_backward(const float* amps, const float* grad_probs, int64_t n,
+                                                   float* grad_amps, void* stream) {
+    if (n < 0) return fail(SLOS_EINVAL, "fock_probs_from_amplitudes_backward: n < 0");
+    if (n == 0) return SLOS_OK;
+    if (!amps || !grad_probs || !grad_amps)
+        return fail(SLOS_EINVAL, "fock_probs_from_amplitudes_backward: NULL device pointer");
+    return launch_abs2_backward(n, (const float2*)amps, grad_probs, (float2*)grad_amps, (hipStream_t)stream);
 }
 
 extern "C" int fock_sample(slos_batch_t batch, const float* U, const float* u, int S, int32_t* shots, void* ws,

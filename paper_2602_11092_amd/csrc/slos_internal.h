@@ -158,6 +158,11 @@ struct SupDev {
 enum { kSupReplicateU, kSupCombine, kSupExpand, kSupGradX, kSupGroupSum };
 int launch_superposition(int kind, const SupDev& S, const slos_batch_s& Bt, const void* a0, const void* a1,
                          const void* a2, void* out, hipStream_t stream);
+// p[i] = |a[i]|^2 and its adjoint ga[i] = 2 gp[i] a[i], over n values
+int launch_abs2(int64_t n, const float2* a, float* p, hipStream_t stream);
+int launch_abs2_backward(int64_t n, const float2* a, const float* gp, float2* ga, hipStream_t stream);
+// z[0..n) = 0 by a fill kernel (capture-safe, unlike a memset node)
+int launch_zero_c64(int64_t n, float2* z, hipStream_t stream);
 int launch_sample(const slos_batch_s& Bt, const float* p, double* part, double* cdf, const float* u, int S,
                   int32_t* shots, hipStream_t stream);
 

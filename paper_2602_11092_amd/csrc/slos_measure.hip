@@ -335,6 +335,32 @@ __global__ __launch_bounds__(kMeasureBlock) void group_sum_kernel(int mm, int G,
     gU[i] = acc;
 }
 
+// p[i] = |a[i]|^2, the probability epilogue on amplitudes formed elsewhere
+__global__ __launch_bounds__(kMeasureBlock) void abs2_kernel(int64_t n, const float2* __restrict__ a,
+                                                             float* __restrict__ p) {
+    const int64_t i = (int64_t)blockIdx.x * kMeasureBlock + threadIdx.x;
+    if (i >= n) return;
+    const float2 v = a[i];
+    p[i] = v.x * v.x + v.y * v.y;
+}
+
+// ga[i] = 2 gp[i] a[i], the adjoint of p = |a|^2 (gradient dL/dRe + i dL/dIm)
+__global__ __launch_bounds__(kMeasureBlock) void abs2_backward_kernel(int64_t n, const float2* __restrict__ a,
+                                                                      const float* __restrict__ gp,
+                                                                      float2* __restrict__ ga) {
+    const int64_t i = (int64_t)blockIdx.x * kMeasureBlock + threadIdx.x;
+    if (i >= n) return;
+    const float2 v = a[i];
+    const float w = 2.f * gp[i];
+    ga[i] = make_float2(w * v.x, w * v.y);
+}
+
+// z[i] = 0 (a kernel, not a memset, so that captured graphs replay it as written)
+__global__ __launch_bounds__(kMeasureBlock) void zero_c64_kernel(int64_t n, float2* __restrict__ z) {
+    const int64_t i = (int64_t)blockIdx.x * kMeasureBlock + threadIdx.x;
+    if (i < n) z[i] = make_float2(0.f, 0.f);
+}
+
 int threshold_chunks(const slos_batch_s& Bt) {
     const int64_t Q = threshold_dim(Bt.plan->m, Bt.n_max);
     return (int)std::max<int64_t>(1, (Q + kChunkPatterns - 1) / kChunkPatterns);
@@ -411,6 +437,37 @@ int launch_superposition(int kind, const SupDev& S, const slos_batch_s& Bt, cons
     }
     (void)a2;
     if (e != hipSuccess) return fail(SLOS_EHIP, std::string("superposition kernel launch: ") + hipGetErrorString(e));
+    return SLOS_OK;
+}
+
+int launch_abs2(int64_t n, const float2* a, float* p, hipStream_t stream) {
+    if (n <= 0) return SLOS_OK;
+    if ((n + kMeasureBlock - 1) / kMeasureBlock >= ((int64_t)1 << 31))
+        return fail(SLOS_EUNSUPPORTED, "probabilities from amplitudes: too many values for one launch");
+    void* args[] = {(void*)&n, (void*)&a, (void*)&p};
+    hipError_t e = hipLaunchKernel((void*)&abs2_kernel, dim3(blocks_for(n)), dim3(kMeasureBlock), args, 0, stream);
+    if (e != hipSuccess) return fail(SLOS_EHIP, std::string("abs2 launch: ") + hipGetErrorString(e));
+    return SLOS_OK;
+}
+
+int launch_abs2_backward(int64_t n, const float2* a, const float* gp, float2* ga, hipStream_t stream) {
+    if (n <= 0) return SLOS_OK;
+    if ((n + kMeasureBlock - 1) / kMeasureBlock >= ((int64_t)1 << 31))
+        return fail(SLOS_EUNSUPPORTED, "probabilities from amplitudes: too many values for one launch");
+    void* args[] = {(void*)&n, (void*)&a, (void*)&gp, (void*)&ga};
+    hipError_t e =
+        hipLaunchKernel((void*)&abs2_backward_kernel, dim3(blocks_for(n)), dim3(kMeasureBlock), args, 0, stream);
+    if (e != hipSuccess) return fail(SLOS_EHIP, std::string("abs2 adjoint launch: ") + hipGetErrorString(e));
+    return SLOS_OK;
+}
+
+int launch_zero_c64(int64_t n, float2* z, hipStream_t stream) {
+    if (n <= 0) return SLOS_OK;
+    if ((n + kMeasureBlock - 1) / kMeasureBlock >= ((int64_t)1 << 31))
+        return fail(SLOS_EUNSUPPORTED, "zero fill: too many values for one launch");
+    void* args[] = {(void*)&n, (void*)&z};
+    hipError_t e = hipLaunchKernel((void*)&zero_c64_kernel, dim3(blocks_for(n)), dim3(kMeasureBlock), args, 0, stream);
+    if (e != hipSuccess) return fail(SLOS_EHIP, std::string("zero fill launch: ") + hipGetErrorString(e));
     return SLOS_OK;
 }
 

@@ -12,7 +12,7 @@ from torch import nn
 
 from . import _binding as B
 from .autograd import (fock_amplitudes, fock_mode_expectations, fock_probs, fock_shared_superposition_amplitudes,
-                       fock_threshold_probs, mesh_to_unitary)
+                       fock_threshold_probs, mesh_to_unitary, probs_from_amplitudes)
 
 
 class QuantumLayer(nn.Module):
@@ -120,7 +120,7 @@ class AmplitudeEncodedLayer(nn.Module):
             self._shared = B.SharedSuperposition(B.Plan(self.m, max(self.n, 1)), self.n)
         U = mesh_to_unitary(self.theta, None, 0.0, self.m)[0]
         out = fock_shared_superposition_amplitudes(U, X.to(torch.complex64), self._shared)
-        return out if self.measurement == "amplitudes" else out.abs() ** 2
+        return out if self.measurement == "amplitudes" else probs_from_amplitudes(out)
 
 
 class FidelityKernel:

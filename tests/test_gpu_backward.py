@@ -183,6 +183,47 @@ def test_large_state_m24_n8_gradients():
         assert e <= G_RTOL
 
 
+def test_large_state_m24_n8_dense_loss_directional_fd():
+    """m=24, n=8 on the workload's own loss, L = sum_b sum_t w_t p_bt with a
+    dense w ~ U[0,1) over all 7,888,725 outputs (layered adjoint, layers
+    recomputed): <G_U, V> against FP64 central differences (h = 1e-6) of the
+    oracle loss, for the first and last sample and two seeded directions
+    each.  Each direction V lives on one output mode's row j of U, so the
+    outputs with t_j = 0 keep their probability at U +- hV and drop out of the
+    difference exactly; the oracle evaluates the rest, a quarter of the basis,
+    by Ryser permanents."""
+    wl = W.make("haar_m24_n8_b16")
+    say("haar_m24_n8_b16 dense-loss gradient")
+    plan = B.Plan(wl.m, 8)
+    batch = B.Batch(plan, wl.occ)
+    U = to_dev_c64(wl.U)
+    gp = torch.from_numpy(np.tile(wl.loss_w, wl.B)).to(DEV)
+    G = _grad(batch, U, gp, True)
+    del gp
+    basis = O.fock_basis(24, 8)  # the basis order of the outputs
+    say("  basis enumerated")
+    w64 = wl.loss_w.astype(np.float64)
+    rng = np.random.default_rng(55)
+    h = 1e-6
+    got, fd = [], []
+    for b in (0, wl.B - 1):
+        U64 = widen(wl.U[b])
+        for _ in range(2):
+            j = int(rng.integers(0, 24))
+            V = np.zeros((24, 24), np.complex128)
+            V[j, :] = rng.standard_normal(24) + 1j * rng.standard_normal(24)
+            sel = basis[:, j] >= 1
+            outs, ws = basis[sel], w64[sel]
+            Lp = O.weighted_sum(O.probabilities(U64 + h * V, wl.occ[b], outs)[None, :], ws)[0]
+            Lm = O.weighted_sum(O.probabilities(U64 - h * V, wl.occ[b], outs)[None, :], ws)[0]
+            fd.append((Lp - Lm) / (2 * h))
+            got.append(float(np.real(np.sum(np.conj(G[b]) * V))))
+            say("  sample", b, "row", j, "gpu", got[-1], "fd", fd[-1])
+    e = rel_err(np.array(got), np.array(fd))
+    say("  directional rel err", e)
+    assert e <= G_RTOL
+
+
 def test_backward_deterministic_and_variants_agree():
     wl = W.make("clements_m20_n5_b512", B=24)
     U = B.mesh_to_unitary(torch.from_numpy(wl.theta).to(DEV), torch.from_numpy(wl.x).to(DEV), wl.enc_scale)

@@ -199,3 +199,35 @@ def test_hip_graph_replay_matches_eager():
         g.replay()
         torch.cuda.synchronize()
         assert np.array_equal(out.cpu().numpy(), eager), rep
+
+
+@pytest.mark.parametrize("variant,block", [(B.VARIANT_FUSED, 256), (B.VARIANT_FUSED, 512),
+                                           (B.VARIANT_FUSED, 1024), (B.VARIANT_LAYERED, 0)])
+def test_clements_m20_n5_b512(variant, block):
+    """The benchmark's own shape (m=20 Clements mesh with per-sample angle
+    encoding, n=5 in modes 0,4,8,12,16, B=512): mesh -> U, then amplitudes and
+    probabilities of the whole batch in one launch, compared element by
+    element with the oracle on 9 samples, the first and last of the work order
+    among them, at every fused workgroup size and in the layered variant."""
+    wl = W.make("clements_m20_n5_b512")
+    say("clements_m20_n5_b512 forward", variant, block)
+    theta = torch.from_numpy(wl.theta).to(DEV)
+    x = torch.from_numpy(wl.x).to(DEV)
+    U = B.mesh_to_unitary(theta, x, wl.enc_scale)
+    batch = B.Batch(B.Plan(wl.m, 5), wl.occ)
+    for op in (B.OP_AMPLITUDES, B.OP_PROBS):
+        batch.set_config(op, variant, block)
+    a = run_forward(batch, U, True)
+    p = run_forward(batch, U, False)
+    N = fock_dim(20, 5)
+    assert a.size == p.size == wl.B * N
+    U64 = U.cpu().numpy()
+    # every sample has 5 photons, so the largest-first work order is 0..511
+    picks = [0, 1, 2, 63, 64, 255, 256, 510, 511]
+    worst_a = _check_against_oracle(batch, U64, wl.occ, a, True, samples=picks)
+    worst_p = _check_against_oracle(batch, U64, wl.occ, p, False, samples=picks)
+    say("  max |da|", worst_a, "max |dp|", worst_p)
+    # invariants on every sample: the norm, and p = |a|^2 from the two launches
+    pb = p.reshape(wl.B, N)
+    assert np.abs(pb.sum(axis=1, dtype=np.float64) - 1).max() < 2e-5
+    assert np.abs(np.abs(a.reshape(wl.B, N)) ** 2 - pb).max() < 1e-6

@@ -96,3 +96,37 @@ def test_graph_superposition_and_fidelity():
         B.fock_fidelity_kernel(Kocc, U, out=K)
 
     _replays_match(fn, [out, gU, gx, K])
+
+
+def test_graph_shared_superposition_and_probabilities():
+    """The shared-interferometer calls (forward, adjoint with inputs and with
+    G = 0, where dL/dA is cleared by a fill kernel) and the probabilities
+    of their amplitudes with the adjoint of p = |a|^2."""
+    rng = np.random.default_rng(14)
+    m, n, G = 5, 2, 12
+    ss = B.SharedSuperposition(B.Plan(m, n), n)
+    N = ss.N
+    U = to_dev_c64(W.haar_unitaries(rng, 1, m)[0])
+    X = torch.randn(G, N, dtype=torch.complex64, device=DEV)
+    gout = torch.randn(G, N, dtype=torch.complex64, device=DEV)
+    out = torch.empty(G, N, dtype=torch.complex64, device=DEV)
+    gU, gX, gU0 = torch.empty_like(U), torch.empty_like(X), torch.empty_like(U)
+    X0 = torch.empty(0, N, dtype=torch.complex64, device=DEV)
+    g0 = torch.empty(0, N, dtype=torch.complex64, device=DEV)
+    p = torch.empty(G, N, dtype=torch.float32, device=DEV)
+    wp = torch.rand(G, N, device=DEV)
+    ga = torch.empty_like(X)
+    say("graph shared superposition")
+
+    def fn():
+        B.fock_shared_superposition_amplitudes(ss, U, X, out=out)
+        a, b = B.fock_shared_superposition_amplitudes_backward(ss, U, X, gout)
+        gU.copy_(a)
+        gX.copy_(b)
+        c, _ = B.fock_shared_superposition_amplitudes_backward(ss, U, X0, g0, need_grad_x=False)
+        gU0.copy_(c)
+        B.fock_probs_from_amplitudes(out, out=p)
+        B.fock_probs_from_amplitudes_backward(out, wp, out=ga)
+
+    _replays_match(fn, [out, gU, gX, gU0, p, ga])
+    assert torch.count_nonzero(gU0).item() == 0  # no inputs: zero gradient

@@ -294,3 +294,21 @@ def test_threshold_pattern_order(m, n):
         assert np.array_equal(B.slos_threshold_pattern(m, n, q), want)
     with pytest.raises(B.SlosError):
         B.slos_threshold_pattern(m, n, len(pats))
+
+
+def test_workspace_cache_retires_instead_of_freeing():
+    """A workspace handed to a call may be captured in a HIP graph: the cache
+    never frees one while it lives, grows geometrically, and keeps separate
+    buffers per key (op and stream)."""
+    c = B.WorkspaceCache()
+    a = c.get(("op", 1), 1000, "cpu")
+    assert a.numel() == 1024 and a.dtype.itemsize == 1
+    assert c.get(("op", 1), 700, "cpu") is a          # fits: the same buffer
+    b = c.get(("op", 1), 5000, "cpu")                   # grows: a is retired, not dropped
+    assert b is not a and b.numel() == 8192
+    assert c.retired() == 1 and any(r is a for r in c._retired)
+    assert c.get(("op", 1), 1000, "cpu") is b          # smaller again: keeps the larger one
+    other = c.get(("op", 2), 1000, "cpu")               # another stream: its own buffer
+    assert other is not b
+    assert c.get(("op", 1), 0, "cpu") is b
+    assert B.WorkspaceCache._round(1) == 256 and B.WorkspaceCache._round(257) == 512

@@ -410,6 +410,24 @@ def test_readout_cross_entropy_gradient():
     assert abs(L0 - math.log(C)) < 1e-14
 
 
+def test_weighted_sum_loss():
+    # hand-expanded: 0.5*2 + 0.25*4 + 0.1*2 + 0.15*4 = 2.8; dL/dp_bt = w_t
+    p = np.array([[0.5, 0.25], [0.1, 0.15]])
+    L, g = O.weighted_sum(p, np.array([2.0, 4.0]))
+    assert abs(L - 2.8) < 1e-15
+    assert np.array_equal(g, np.array([[2.0, 4.0], [2.0, 4.0]]))
+    # w = 1 on unitaries: each sample's probabilities sum to 1, so L = B
+    rng = np.random.default_rng(31)
+    s = [1, 0, 2, 0]
+    P = np.stack([O.probabilities(_haar(rng, 4), s) for _ in range(3)])
+    L1, _ = O.weighted_sum(P, np.ones(P.shape[1]))
+    assert abs(L1 - 3.0) < 1e-12
+    # a weight on a single output picks that output's probability out
+    w = np.zeros(P.shape[1])
+    w[7] = 1.0
+    assert abs(O.weighted_sum(P, w)[0] - P[:, 7].sum()) < 1e-15
+
+
 def test_mode_expectations_closed_form():
     # full space: <n_j> = sum_i s_i |U_ji|^2 (each photon leaves input mode i
     # towards j with probability |U_ji|^2), including bunched inputs
