@@ -438,6 +438,22 @@ SLOS_API int mesh_to_unitary_backward(int m, int B, const float* theta, const fl
                              const float* grad_U, float* grad_theta, float* grad_x,
                              void* ws, size_t ws_bytes, void* stream);
 
+/* mesh_to_unitary_backward for callers that cannot allocate (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same computation and results, with no workspace argument.  Its scratch is a
+ * static device array of SLOS_MESH_NOALLOC_SCRATCH_BYTES (16 MiB) per device,
+ * held until the process ends; the call allocates nothing and issues no
+ * memset.  Sizes with mesh_workspace_bytes(m, B) above that are rejected
+ * with SLOS_EUNSUPPORTED before anything is enqueued (B up to 2618 at
+ * m = 20, 1020 at m = 32).  The first call on a device looks up the array's
+ * address (hipGetSymbolAddress with that device current); make it outside a
+ * graph capture.  Every call on a device shares that device's array, so calls
+ * that overlap on one device (other streams, other threads) race; calls
+ * ordered on one stream do not. */
+#define SLOS_MESH_NOALLOC_SCRATCH_BYTES (16u << 20)
+SLOS_API int mesh_to_unitary_backward_noalloc(int m, int B, const float* theta, const float* x, float enc_scale,
+                                              const float* grad_U, float* grad_theta, float* grad_x, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -103,6 +103,7 @@ SIGNATURES = {
     "mesh_to_unitary": (_c.c_int, [_c.c_int, _c.c_int, _vp, _vp, _c.c_float, _vp, _vp, _c.c_size_t, _vp]),
     "mesh_to_unitary_backward": (_c.c_int, [_c.c_int, _c.c_int, _vp, _vp, _c.c_float, _vp, _vp, _vp, _vp,
                                             _c.c_size_t, _vp]),
+    "mesh_to_unitary_backward_noalloc": (_c.c_int, [_c.c_int, _c.c_int, _vp, _vp, _c.c_float, _vp, _vp, _vp, _vp]),
 }
 
 _lib = None
@@ -753,6 +754,28 @@ def mesh_to_unitary_backward(theta: torch.Tensor, x: Optional[torch.Tensor], enc
            lib().mesh_to_unitary_backward(m, B, _ptr(theta), _ptr(x), float(enc_scale), _ptr(grad_U), _ptr(gt),
                                           _ptr(gx), _ptr(ws), ws.numel(), _stream_ptr(theta.device)))
     return gt, gx
+
+
+MESH_NOALLOC_SCRATCH_BYTES = 16 << 20
+
+
+def mesh_to_unitary_backward_noalloc(theta: torch.Tensor, x: Optional[torch.Tensor], enc_scale: float,
+                                     grad_U: torch.Tensor, out_theta: torch.Tensor,
+                                     out_x: Optional[torch.Tensor] = None):
+    """mesh_to_unitary_backward with the library's static scratch instead of a
+    workspace: the caller passes every output, and nothing is allocated."""
+    B, m = grad_U.shape[0], grad_U.shape[1]
+    _require(grad_U, "grad_U", torch.complex64, (B, m, m))
+    _require(theta, "theta", torch.float32, (m * (m - 1),))
+    _require(out_theta, "grad_theta", torch.float32, (m * (m - 1),))
+    if x is not None:
+        _require(x, "x", torch.float32, (B, m))
+    if out_x is not None:
+        _require(out_x, "grad_x", torch.float32, (B, m))
+    _check("mesh_to_unitary_backward_noalloc",
+           lib().mesh_to_unitary_backward_noalloc(m, B, _ptr(theta), _ptr(x), float(enc_scale), _ptr(grad_U),
+                                                  _ptr(out_theta), _ptr(out_x), _stream_ptr(theta.device)))
+    return out_theta, out_x
 
 
 def slos_transition_tables(m: int, k: int, want_succ: bool = True, unbunched: bool = False,

@@ -11,6 +11,8 @@
 // dL/dx_b) in its own workgroup, sums them over the batch in a fixed order,
 // then sweeps the columns backwards, recovering each column's input as
 // T^H times its output (T unitary).
+#include <mutex>
+
 #include "slos_internal.h"
 
 namespace slos {
@@ -311,6 +313,41 @@ __global__ __launch_bounds__(1024) void mesh_bwd_sweep_kernel(int m, const float
 size_t mesh_ws(int m, int B) { return mesh_ws_floats2(m, B) * sizeof(float2); }
 
 }  // namespace
+
+// ---- scratch of the allocation-free adjoint (mesh_to_unitary_backward_noalloc)
+// One copy per device, held until the process ends.  In host code `scratch`
+// names a host-side stand-in, never the device memory: kernels and copies
+// take the address hipGetSymbolAddress returns for the current device.
+constexpr size_t kMeshScratchBytes = (size_t)16 << 20;
+static __device__ __align__(256) unsigned char scratch[kMeshScratchBytes];
+
+namespace {
+
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kScratchDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per device.
+int scratch_address(void** out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0)
+        return fail(SLOS_EHIP, "mesh_to_unitary_backward_noalloc: no current HIP device");
+    if (dev >= kScratchDevices)
+        return fail(SLOS_EUNSUPPORTED, "mesh_to_unitary_backward_noalloc: device index beyond 63");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(SLOS_EHIP, std::string("mesh_to_unitary_backward_noalloc: scratch lookup failed: ") +
+                                       hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return SLOS_OK;
+}
+
+}  // namespace
 }  // namespace slos
 
 using namespace slos;
@@ -361,4 +398,22 @@ extern "C" int mesh_to_unitary_backward(int m, int B, const float* theta, const 
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(SLOS_EHIP, std::string("mesh_to_unitary_backward launch: ") + hipGetErrorString(e));
     return SLOS_OK;
+}
+
+extern "C" int mesh_to_unitary_backward_noalloc(int m, int B, const float* theta, const float* x, float enc_scale,
+                                                const float* grad_U, float* grad_theta, float* grad_x,
+                                                void* stream) {
+    if (m < 2 || m > kMaxModes) return fail(SLOS_EINVAL, "mesh_to_unitary_backward_noalloc: m must be in [2, 32]");
+    if (B < 1) return fail(SLOS_EINVAL, "mesh_to_unitary_backward_noalloc: B < 1");
+    if (mesh_ws(m, B) > kMeshScratchBytes)
+        return fail(SLOS_EUNSUPPORTED, "mesh_to_unitary_backward_noalloc: needs " + std::to_string(mesh_ws(m, B)) +
+                                           " bytes of scratch, more than the " + std::to_string(kMeshScratchBytes) +
+                                           " the library holds");
+    void* ws = nullptr;
+    const int rc = scratch_address(&ws);
+    if (rc != SLOS_OK) return rc;
+    // the same kernels as the workspace call; every scratch word they read is
+    // written earlier in the same call, so nothing needs clearing
+    return mesh_to_unitary_backward(m, B, theta, x, enc_scale, grad_U, grad_theta, grad_x, ws, kMeshScratchBytes,
+                                    stream);
 }
