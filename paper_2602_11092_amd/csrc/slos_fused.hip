@@ -344,69 +344,68 @@ __global__ __launch_bounds__(BLOCK) void fused_fwd_kernel(int m, const LayerDev*
 // Successor offsets come in groups of four modes, [j/4][t'][4]: one
 // coalesced 16-byte load serves four pairs.
 
-// u_j is read at its point of use (a broadcast LDS read; volatile so that it
-// is not kept in registers across owned states).
+// u_j read at its point of use (a broadcast LDS read; volatile so that it is
+// not kept in registers where registers are short).
 __device__ __forceinline__ float2 coeff(uint32_t j) {
     typedef __attribute__((address_space(3))) const volatile unsigned long long lds_vu64;
     return __builtin_bit_cast(float2, *(lds_vu64*)(size_t)(kUcolAddr + 8 * j));
 }
 
-template <int BLOCK, int OWN, int MMAX, bool WITH_H = true>
-__device__ __forceinline__ void pair_math(int j, uint32_t so, uint32_t srcb, float2 dv, float2& acc,
-                                          float2 (&h)[MMAX]) {
-    const float2 g = lds_ld(srcb + so);
-    c_fma_conj(acc, coeff(j), g);
-    if (WITH_H) c_fma_conj(h[j], dv, g);
-}
-
 // Owned t' in [lo, hi), modes j in [jlo, jhi), by groups of four modes: per
-// owned state, one 16-byte successor load per group that meets the range.
-// No divergent branches around the accumulators (a divergent region that
-// updates long-lived registers costs copies at its join): pairs outside the
-// ranges read the zero slot instead.
+// owned state, one 16-byte successor load per group, all issued before the
+// first gather.  Branch-free per pair: a lane whose t' lies outside the range
+// gathers the zero slot (a select, no divergent region around the
+// accumulators), and modes outside [jlo, jhi) are skipped by uniform tests.
+// The coefficient column conj(u_j) sits in registers for the whole call
+// where the workgroup shape leaves room (below 1024 threads).
 template <int BLOCK, int OWN, int MMAX, bool WITH_H = true>
 __device__ __forceinline__ void pull(int lo, int hi, int jlo, int jhi, __amdgpu_buffer_rsrc_t rs, uint32_t gstride,
                                      uint32_t srcb, uint32_t Db, float2 (&acc)[OWN], float2 (&h)[MMAX]) {
     constexpr int NG = MMAX / 4;
+    constexpr bool kCoefRegs = BLOCK < 1024;
     if (lo >= hi || jlo >= jhi) return;
     const int tid = threadIdx.x;
     const int jbits = (int)range_bits(jlo, jhi);
     const int gbits = (int)range_bits(jlo >> 2, (jhi + 3) >> 2);
     const uint32_t zoff = kUcolAddr + 32 * 8 - srcb;  // srcb + zoff: the zero slot
+    float2 cu[kCoefRegs ? MMAX : 1];
+    if (kCoefRegs) {
+#pragma unroll
+        for (int j = 0; j < (kCoefRegs ? MMAX : 1); ++j) cu[j] = lds_ld(kUcolAddr + 8u * (uint32_t)j);
+    }
 #pragma unroll
     for (int s = 0; s < OWN; ++s) {
         if (!slot_meets<BLOCK>(s, lo, hi)) continue;  // no owned state in range (uniform)
         const int tp = fresh_v(tid) + s * BLOCK;
         const bool act = tp >= lo && tp < hi;
         const int tc = min(max(tp, lo), hi - 1);
-        const float2 dv = lds_ld(Db + 8u * (uint32_t)tc);
         const uint32_t vo = (uint32_t)tc * 16u;
-        // all groups' loads up front, or (the 1024-thread shape, short of
-        // registers) each group's load just before its use
-        constexpr bool kPreload = BLOCK < 1024;
         uint4 sv[NG];
 #pragma unroll
-        for (int g = 0; g < NG; ++g)
-            if (kPreload && has(gbits, g)) sv[g] = buf_ld4(rs, vo, (uint32_t)g * gstride);
+        for (int g = 0; g < NG; ++g) sv[g] = buf_ld4(rs, vo, (uint32_t)g * gstride);
+        const float2 dv = lds_ld(Db + 8u * (uint32_t)tc);
 #pragma unroll
         for (int g = 0; g < NG; ++g) {
-            if (!has(gbits, g)) continue;  // uniform
-            if (!kPreload) sv[g] = buf_ld4(rs, vo, (uint32_t)g * gstride);
+            if (!has(gbits, g)) continue;  // no mode of this group in range (uniform)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int j = 4 * g + q;
-                const uint32_t so = (act && has(jbits, j)) ? comp(sv[g], q) : zoff;
-                pair_math<BLOCK, OWN, MMAX, WITH_H>(j, so, srcb, dv, acc[s], h);
+                // a select, not a branch, so that the group's gathers issue together
+                const bool jin = has(jbits, j);
+                const uint32_t so = (act & jin) ? comp(sv[g], q) : zoff;
+                const float2 gv = lds_ld(srcb + so);
+                c_fma_conj(acc[s], kCoefRegs ? cu[kCoefRegs ? j : 0] : coeff(j), gv);
+                if (WITH_H) c_fma_conj(h[j], dv, gv);
             }
-            __builtin_amdgcn_sched_barrier(0);  // one group at a time: bounded register use
         }
     }
 }
 
 // A few modes j in [jlo, jhi) over owned t' in [lo, hi), one mode at a time
-// (a runtime loop: one successor column per mode, no wasted modes).  The G_U
-// share of mode j is summed over the wave in a fixed order and added by lane
-// 63 to its wave's slot Hn[wave][j] in LDS.
+// (a runtime loop: one successor column per mode, no wasted modes).  The
+// owned states' conj(d_{k-1}) values stay in registers across the modes.  The
+// G_U share of mode j is summed over the wave in a fixed order and added by
+// lane 63 to its wave's slot Hn[wave][j] in LDS.
 template <int BLOCK, int OWN>
 __device__ __forceinline__ void pull_few(int lo, int hi, int jlo, int jhi, __amdgpu_buffer_rsrc_t rs,
                                          uint32_t gstride, uint32_t srcb, uint32_t Db, uint32_t Hn,
@@ -415,26 +414,35 @@ __device__ __forceinline__ void pull_few(int lo, int hi, int jlo, int jhi, __amd
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const uint32_t zoff = kUcolAddr + 32 * 8 - srcb;  // srcb + zoff: the zero slot
+    float2 dv[OWN];
+#pragma unroll
+    for (int s = 0; s < OWN; ++s) {
+        dv[s] = c_zero();
+        if (!slot_meets<BLOCK>(s, lo, hi)) continue;  // uniform
+        const int tc = min(max(fresh_v(tid) + s * BLOCK, lo), hi - 1);
+        dv[s] = lds_ld(Db + 8u * (uint32_t)tc);
+    }
     for (int j = jlo; j < jhi; ++j) {
         const uint32_t col = 4u * (uint32_t)(j & 3), goff = (uint32_t)(j >> 2) * gstride;
         uint32_t sv[OWN];
 #pragma unroll
         for (int s = 0; s < OWN; ++s) {
+            sv[s] = 0;
             if (!slot_meets<BLOCK>(s, lo, hi)) continue;  // uniform
             const int tc = min(max(fresh_v(tid) + s * BLOCK, lo), hi - 1);
             sv[s] = buf_ld1(rs, (uint32_t)tc * 16u + col, goff);
         }
         const float2 uj = coeff(j);
-        constexpr int HQ = BLOCK >= 1024 ? 1 : 4;  // partial sums (short chains) where registers allow
-        float2 hq[4] = {c_zero(), c_zero(), c_zero(), c_zero()};
+        constexpr int HQ = 4;  // partial sums (short dependence chains)
+        float2 hq[HQ] = {c_zero(), c_zero(), c_zero(), c_zero()};
 #pragma unroll
         for (int s = 0; s < OWN; ++s) {
             if (!slot_meets<BLOCK>(s, lo, hi)) continue;
             const int tp = fresh_v(tid) + s * BLOCK;
-            const int tc = min(max(tp, lo), hi - 1);
-            const float2 g = lds_ld(srcb + ((tp >= lo && tp < hi) ? sv[s] : zoff));
+            const uint32_t so = (tp >= lo && tp < hi) ? sv[s] : zoff;
+            const float2 g = lds_ld(srcb + so);
             c_fma_conj(acc[s], uj, g);
-            c_fma_conj(hq[s % HQ], lds_ld(Db + 8u * (uint32_t)tc), g);
+            c_fma_conj(hq[s % HQ], dv[s], g);
         }
         const float2 hj = c_add(c_add(hq[0], hq[1]), c_add(hq[2], hq[3]));
         const float re = wave_sum63(hj.x);
