@@ -401,55 +401,53 @@ __device__ __forceinline__ void pull(int lo, int hi, int jlo, int jhi, __amdgpu_
     }
 }
 
-// A few modes j in [jlo, jhi) over owned t' in [lo, hi), one mode at a time
-// (a runtime loop: one successor column per mode, no wasted modes).  The
-// owned states' conj(d_{k-1}) values stay in registers across the modes.  The
-// G_U share of mode j is summed over the wave in a fixed order and added by
-// lane 63 to its wave's slot Hn[wave][j] in LDS.
-template <int BLOCK, int OWN>
-__device__ __forceinline__ void pull_few(int lo, int hi, int jlo, int jhi, __amdgpu_buffer_rsrc_t rs,
-                                         uint32_t gstride, uint32_t srcb, uint32_t Db, uint32_t Hn,
-                                         float2 (&acc)[OWN]) {
+// A few modes j in [jlo, jhi) over owned t' in [lo, hi), owned states in
+// blocks of SB: per block, each state's successor row offset, range mask and
+// conj(d_{k-1}) are formed once; then mode by mode (a uniform test per mode)
+// the block's successor loads and gathers issue together, the mode's
+// successor column chosen by the load's scalar offset.  G_U shares go to the
+// same per-lane h[j] as the wide pull.
+template <int BLOCK, int OWN, int MMAX>
+__device__ __forceinline__ void pull_narrow(int lo, int hi, int jlo, int jhi, __amdgpu_buffer_rsrc_t rs,
+                                            uint32_t gstride, uint32_t srcb, uint32_t Db, float2 (&acc)[OWN],
+                                            float2 (&h)[MMAX]) {
+    constexpr int SB = OWN < 4 ? OWN : 4;
     if (lo >= hi || jlo >= jhi) return;
     const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
+    const int jbits = (int)range_bits(jlo, jhi);
     const uint32_t zoff = kUcolAddr + 32 * 8 - srcb;  // srcb + zoff: the zero slot
-    float2 dv[OWN];
 #pragma unroll
-    for (int s = 0; s < OWN; ++s) {
-        dv[s] = c_zero();
-        if (!slot_meets<BLOCK>(s, lo, hi)) continue;  // uniform
-        const int tc = min(max(fresh_v(tid) + s * BLOCK, lo), hi - 1);
-        dv[s] = lds_ld(Db + 8u * (uint32_t)tc);
-    }
-    for (int j = jlo; j < jhi; ++j) {
-        const uint32_t col = 4u * (uint32_t)(j & 3), goff = (uint32_t)(j >> 2) * gstride;
-        uint32_t sv[OWN];
+    for (int s0 = 0; s0 < OWN; s0 += SB) {
+        bool any = false;
 #pragma unroll
-        for (int s = 0; s < OWN; ++s) {
-            sv[s] = 0;
-            if (!slot_meets<BLOCK>(s, lo, hi)) continue;  // uniform
-            const int tc = min(max(fresh_v(tid) + s * BLOCK, lo), hi - 1);
-            sv[s] = buf_ld1(rs, (uint32_t)tc * 16u + col, goff);
+        for (int s = s0; s < s0 + SB && s < OWN; ++s) any = any || slot_meets<BLOCK>(s, lo, hi);
+        if (!any) continue;  // uniform
+        float2 dv[SB];
+        uint32_t vo[SB];
+        bool act[SB];
+#pragma unroll
+        for (int q = 0; q < SB; ++q) {
+            const int tp = fresh_v(tid) + (s0 + q) * BLOCK;
+            act[q] = s0 + q < OWN && tp >= lo && tp < hi;
+            const int tc = min(max(tp, lo), hi - 1);
+            vo[q] = (uint32_t)tc * 16u;
+            dv[q] = lds_ld(Db + 8u * (uint32_t)tc);
         }
-        const float2 uj = coeff(j);
-        constexpr int HQ = 4;  // partial sums (short dependence chains)
-        float2 hq[HQ] = {c_zero(), c_zero(), c_zero(), c_zero()};
 #pragma unroll
-        for (int s = 0; s < OWN; ++s) {
-            if (!slot_meets<BLOCK>(s, lo, hi)) continue;
-            const int tp = fresh_v(tid) + s * BLOCK;
-            const uint32_t so = (tp >= lo && tp < hi) ? sv[s] : zoff;
-            const float2 g = lds_ld(srcb + so);
-            c_fma_conj(acc[s], uj, g);
-            c_fma_conj(hq[s % HQ], dv[s], g);
-        }
-        const float2 hj = c_add(c_add(hq[0], hq[1]), c_add(hq[2], hq[3]));
-        const float re = wave_sum63(hj.x);
-        const float im = wave_sum63(hj.y);
-        if (lane == 63) {
-            const uint32_t a = Hn + 8u * (uint32_t)(wave * 32 + j);
-            lds_st(a, c_add(lds_ld(a), make_float2(re, im)));
+        for (int j = 0; j < MMAX; ++j) {
+            if (!has(jbits, j)) continue;  // uniform, once per mode and block
+            const float2 uj = coeff(j);
+            const uint32_t soff = (uint32_t)(j >> 2) * gstride + 4u * (uint32_t)(j & 3);
+            uint32_t sv[SB];
+#pragma unroll
+            for (int q = 0; q < SB; ++q) sv[q] = buf_ld1(rs, vo[q], soff);
+#pragma unroll
+            for (int q = 0; q < SB; ++q) {
+                if (s0 + q >= OWN) continue;
+                const float2 g = lds_ld(srcb + (act[q] ? sv[q] : zoff));
+                c_fma_conj(acc[s0 + q], uj, g);
+                c_fma_conj(h[j], dv[q], g);
+            }
         }
     }
 }
@@ -502,11 +500,10 @@ __device__ __forceinline__ void lower_h(int m, int Nkm1, __amdgpu_buffer_rsrc_t 
 }
 
 // Sums h[j] over the workgroup (per wave with DPP, then over the waves in a
-// fixed order) into the LDS column at GUcol, j < MMAX (h[j] = 0 for j >= m),
-// adding the per-wave sums at Hn if given.  Hw: [NW][32] LDS scratch.
+// fixed order) into the LDS column at GUcol, j < MMAX (h[j] = 0 for j >= m).
+// Hw: [NW][32] LDS scratch.
 template <int BLOCK, int MMAX>
-__device__ __forceinline__ void reduce_columns(const float2 (&h)[MMAX], int m, uint32_t Hw, uint32_t GUcol,
-                                               uint32_t Hn = 0xFFFFFFFFu) {
+__device__ __forceinline__ void reduce_columns(const float2 (&h)[MMAX], int m, uint32_t Hw, uint32_t GUcol) {
     constexpr int NW = BLOCK / 64;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -514,11 +511,7 @@ __device__ __forceinline__ void reduce_columns(const float2 (&h)[MMAX], int m, u
     for (int j = 0; j < MMAX; ++j) {
         const float re = wave_sum63(h[j].x);
         const float im = wave_sum63(h[j].y);
-        if (lane == 63) {
-            float2 v = make_float2(re, im);
-            if (Hn != 0xFFFFFFFFu) v = c_add(v, lds_ld(Hn + 8u * (uint32_t)(wave * 32 + j)));  // per-wave extra
-            lds_st(Hw + 8u * (uint32_t)(wave * 32 + j), v);
-        }
+        if (lane == 63) lds_st(Hw + 8u * (uint32_t)(wave * 32 + j), make_float2(re, im));
     }
     __syncthreads();
     if (tid < m) {
@@ -538,10 +531,9 @@ __global__ __launch_bounds__(BLOCK) void fused_bwd_kernel(int m, const LayerDev*
     // (the layer recomputes run while acc and h are dead: the forward's width)
     constexpr int GU = kLU;
     constexpr int GM = BLOCK <= 512 ? 4 : BLOCK <= 768 ? 2 : 1;  // wider gathers where registers allow
-    extern __shared__ float2 lds[];  // ucol | X[S] layers and chunks | Hw[NW][32] | GUacc[16][32] | Hn[NW][32]
+    extern __shared__ float2 lds[];  // ucol | X[S] layers and chunks | Hw[NW][32] | GUacc[16][32]
     const uint32_t Hw = kXAddr + 8u * (uint32_t)S;
     const uint32_t GUacc = Hw + 8u * NW * 32;
-    const uint32_t Hn = GUacc + 8u * kMaxPhotons * 32;  // [NW][32] per-wave G_U sums of single-mode pulls
     const int tid = threadIdx.x;
     if (tid < kUcolSlots) lds_st(kUcolAddr + 8 * tid, c_zero());  // slots m..32 stay zero
 
@@ -554,7 +546,7 @@ __global__ __launch_bounds__(BLOCK) void fused_bwd_kernel(int m, const LayerDev*
         const int32_t* modes = Bt.modes + (size_t)b * kMaxPhotons;
         float2* gUb = gU + (size_t)b * m * m;
 
-        for (int q = tid; q < kMaxPhotons * 32 + NW * 32; q += BLOCK) lds_st(GUacc + 8u * q, c_zero());  // GUacc, Hn
+        for (int q = tid; q < kMaxPhotons * 32; q += BLOCK) lds_st(GUacc + 8u * q, c_zero());
         __syncthreads();
 
         if (n == 1) {
@@ -646,7 +638,7 @@ __global__ __launch_bounds__(BLOCK) void fused_bwd_kernel(int m, const LayerDev*
                 // {min(t') in [a, bb), j >= a} and {min(t') >= bb, a <= j < bb}
                 const uint32_t srcb = C - 8u * (uint32_t)base;
                 pull<BLOCK, OWN, MMAX>(ldc(Lp.minoff + a), ldc(Lp.minoff + bb), a, m, rs, gstride, srcb, D, acc, h);
-                pull_few<BLOCK, OWN>(ldc(Lp.minoff + bb), Np, a, bb, rs, gstride, srcb, D, Hn, acc);
+                pull_narrow<BLOCK, OWN, MMAX>(ldc(Lp.minoff + bb), Np, a, bb, rs, gstride, srcb, D, acc, h);
                 __syncthreads();
                 a = bb;
             }
@@ -656,7 +648,7 @@ __global__ __launch_bounds__(BLOCK) void fused_bwd_kernel(int m, const LayerDev*
                 const int tp = tid + s * BLOCK;
                 if (tp < Np) lds_st(kXAddr + 8u * (uint32_t)tp, acc[s]);
             }
-            reduce_columns<BLOCK, MMAX>(h, m, Hw, GUacc + 8u * (uint32_t)((n - 1) * 32), Hn);
+            reduce_columns<BLOCK, MMAX>(h, m, Hw, GUacc + 8u * (uint32_t)((n - 1) * 32));
             // ---- lower layers.  d_0..d_{n-2} stored after g_{n-1} (layer k at
             // Np + number of states with < k photons); g ping-pongs between 0 and R.
             const int R = Np + (int)Lp.cum;
@@ -680,17 +672,34 @@ __global__ __launch_bounds__(BLOCK) void fused_bwd_kernel(int m, const LayerDev*
                 const uint32_t gsk = (uint32_t)Nkm1 * 16u;
                 const __amdgpu_buffer_rsrc_t rsk = buf_rsrc(ldc(&Ls[k].succ), (uint32_t)((m + 3) / 4) * gsk);
                 __syncthreads();
-                if (k >= 2) {
+                if (Nkm1 > BLOCK / 2) {
+                    // a layer that fills the lanes: g_{k-1} and G_U from one pull, then a column reduction
 #pragma unroll
                     for (int s = 0; s < OWN; ++s) acc[s] = c_zero();
-                    pull<BLOCK, OWN, MMAX, false>(0, Nkm1, 0, m, rsk, gsk, gk, dkm1, acc, h);
 #pragma unroll
-                    for (int s = 0; s < OWN; ++s) {
-                        const int tp = tid + s * BLOCK;
-                        if (tp < Nkm1) lds_st(gkm1 + 8u * (uint32_t)tp, acc[s]);
+                    for (int j = 0; j < MMAX; ++j) h[j] = c_zero();
+                    pull<BLOCK, OWN, MMAX, true>(0, Nkm1, 0, m, rsk, gsk, gk, dkm1, acc, h);
+                    if (k >= 2) {
+#pragma unroll
+                        for (int s = 0; s < OWN; ++s) {
+                            const int tp = tid + s * BLOCK;
+                            if (tp < Nkm1) lds_st(gkm1 + 8u * (uint32_t)tp, acc[s]);
+                        }
                     }
+                    reduce_columns<BLOCK, MMAX>(h, m, Hw, GUacc + 8u * (uint32_t)((k - 1) * 32));
+                } else {
+                    if (k >= 2) {
+#pragma unroll
+                        for (int s = 0; s < OWN; ++s) acc[s] = c_zero();
+                        pull<BLOCK, OWN, MMAX, false>(0, Nkm1, 0, m, rsk, gsk, gk, dkm1, acc, h);
+#pragma unroll
+                        for (int s = 0; s < OWN; ++s) {
+                            const int tp = tid + s * BLOCK;
+                            if (tp < Nkm1) lds_st(gkm1 + 8u * (uint32_t)tp, acc[s]);
+                        }
+                    }
+                    lower_h<BLOCK, MMAX>(m, Nkm1, rsk, gsk, gk, dkm1, GUacc + 8u * (uint32_t)((k - 1) * 32));
                 }
-                lower_h<BLOCK, MMAX>(m, Nkm1, rsk, gsk, gk, dkm1, GUacc + 8u * (uint32_t)((k - 1) * 32));
                 __syncthreads();
             }
         }
@@ -813,7 +822,7 @@ void* pick_bwd(int block, int m, int64_t Np) {
 }
 
 size_t bwd_lds_for_block(const slos_plan_s& P, int n_max, int block) {
-    return (size_t)(lds_bwd_states(P, n_max) + kUcolSlots + 2 * (block / 64) * 32 + kMaxPhotons * 32) * sizeof(float2);
+    return (size_t)(lds_bwd_states(P, n_max) + kUcolSlots + (block / 64) * 32 + kMaxPhotons * 32) * sizeof(float2);
 }
 
 int grid_for(const slos_plan_s& P, const void* fn, int block, size_t lds, int B) {
