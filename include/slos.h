@@ -113,6 +113,11 @@ extern "C" {
 #define SLOS_VARIANT_AUTO 0    /* library heuristic (or the last value set) */
 #define SLOS_VARIANT_FUSED 1   /* one persistent launch; each workgroup keeps a sample's photon layers in LDS */
 #define SLOS_VARIANT_LAYERED 2 /* one launch per photon layer; layers kept in the workspace (any size) */
+/* Two samples with equal photon numbers per workgroup, their layers
+ * interleaved in LDS so that one 128-bit read serves both: the forward of
+ * the amplitude and probability ops (also behind fock_threshold_probs and
+ * fock_sample); workgroup size 512 or 1024 (default 1024). */
+#define SLOS_VARIANT_FUSED_PAIRS 3
 
 typedef struct slos_plan_s* slos_plan_t;
 typedef struct slos_batch_s* slos_batch_t;

@@ -45,6 +45,7 @@ PLAN_THRESHOLD = 8
 VARIANT_AUTO = 0
 VARIANT_FUSED = 1
 VARIANT_LAYERED = 2
+VARIANT_FUSED_PAIRS = 3
 
 # every symbol the header declares, with (restype, argtypes)
 _c = ctypes

@@ -568,12 +568,26 @@ extern "C" int slos_batch_create(slos_plan_t plan, int B, const int32_t* occ_hos
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(),
                      [&](int a, int b) { return Bt->n_host[a] > Bt->n_host[b]; });
+    // two-sample work items: consecutive samples of the work order with equal photon numbers
+    std::vector<int2> pairs;
+    pairs.reserve((B + 1) / 2);
+    for (int i = 0; i < B;) {
+        if (i + 1 < B && Bt->n_host[order[i]] == Bt->n_host[order[i + 1]]) {
+            pairs.push_back(make_int2(order[i], order[i + 1]));
+            i += 2;
+        } else {
+            pairs.push_back(make_int2(order[i], -1));
+            i += 1;
+        }
+    }
+    Bt->npairs = (int)pairs.size();
 
     const size_t Bs = std::max(B, 1);
     size_t o_n = 0, o_modes = align256(Bs * 4), o_off = o_modes + align256(Bs * kMaxPhotons * 4);
     size_t o_in = o_off + align256((Bs + 1) * 8), o_ord = o_in + align256(Bs * 4);
     size_t o_thr = o_ord + align256(Bs * 4);
-    size_t total = o_thr + align256((Bs + 1) * 8);
+    size_t o_pair = o_thr + align256((Bs + 1) * 8);
+    size_t total = o_pair + align256(Bs * sizeof(int2));
     if (hipMalloc(&Bt->dmem, total) != hipSuccess) {
         delete Bt;
         return fail(SLOS_ENOMEM, "slos_batch_create: hipMalloc failed");
@@ -588,6 +602,8 @@ extern "C" int slos_batch_create(slos_plan_t plan, int B, const int32_t* occ_hos
     }
     if (e == hipSuccess) e = hipMemcpy(base + o_off, Bt->off_host.data(), (B + 1) * 8, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(base + o_thr, Bt->thr_off_host.data(), (B + 1) * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess && !pairs.empty())
+        e = hipMemcpy(base + o_pair, pairs.data(), pairs.size() * sizeof(int2), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         hipFree(Bt->dmem);
         delete Bt;
@@ -601,6 +617,8 @@ extern "C" int slos_batch_create(slos_plan_t plan, int B, const int32_t* occ_hos
     Bt->dev.innorm = (const float*)(base + o_in);
     Bt->dev.order = (const int32_t*)(base + o_ord);
     Bt->dev.thr_off = (const int64_t*)(base + o_thr);
+    Bt->dev.pairs = (const int2*)(base + o_pair);
+    Bt->dev.npairs = Bt->npairs;
     *out = Bt;
     return SLOS_OK;
 }
@@ -633,6 +651,11 @@ bool op_backward(int op) {
 }
 bool op_threshold(int op) { return op == SLOS_OP_THRESHOLD_PROBS || op == SLOS_OP_THRESHOLD_PROBS_BACKWARD; }
 bool op_expect(int op) { return op == SLOS_OP_MODE_EXPECTATIONS || op == SLOS_OP_MODE_EXPECTATIONS_BACKWARD; }
+// ops whose forward forms amplitudes or probabilities (the two-sample kernel's outputs)
+bool op_pairs_ok(int op) {
+    return op == SLOS_OP_AMPLITUDES || op == SLOS_OP_PROBS || op == SLOS_OP_THRESHOLD_PROBS || op == SLOS_OP_SAMPLE;
+}
+bool variant_fused(int v) { return v == SLOS_VARIANT_FUSED || v == SLOS_VARIANT_FUSED_PAIRS; }
 
 // the expectation ops keep dL/dp or p (out_len floats) at the start of their workspace
 size_t expect_head_bytes(const slos_batch_s& Bt) { return align256((size_t)Bt.off_host[Bt.B] * sizeof(float)); }
@@ -667,7 +690,9 @@ int resolve(const slos_batch_s& Bt, int op, int* variant, int* block) {
     }
     int blk = c.block;
     if (blk == 0)
-        blk = (v == SLOS_VARIANT_FUSED) ? fused_block_for(Bt, op) : layered_default_block(Bt);
+        blk = (v == SLOS_VARIANT_FUSED_PAIRS) ? 1024
+              : (v == SLOS_VARIANT_FUSED)     ? fused_block_for(Bt, op)
+                                              : layered_default_block(Bt);
     *variant = v;
     *block = blk;
     return SLOS_OK;
@@ -680,7 +705,7 @@ extern "C" int slos_workspace_bytes(slos_batch_t batch, int op, size_t* bytes) {
     if (!op_valid(op)) return fail(SLOS_EINVAL, "slos_workspace_bytes: bad op");
     int v, blk;
     resolve(*batch, op, &v, &blk);
-    *bytes = (v == SLOS_VARIANT_FUSED) ? 0 : layered_ws_bytes(*batch, op_backward(op));
+    *bytes = variant_fused(v) ? 0 : layered_ws_bytes(*batch, op_backward(op));
     // the expectation forward keeps p and partial sums in the workspace only
     // when layered; the backward always keeps dL/dp
     if (op == SLOS_OP_MODE_EXPECTATIONS_BACKWARD) *bytes += expect_head_bytes(*batch);
@@ -695,13 +720,21 @@ extern "C" int slos_workspace_bytes(slos_batch_t batch, int op, size_t* bytes) {
 extern "C" int slos_batch_set_config(slos_batch_t batch, int op, int variant, int block) {
     if (!batch) return fail(SLOS_EINVAL, "slos_batch_set_config: batch is NULL");
     if (!op_valid(op)) return fail(SLOS_EINVAL, "slos_batch_set_config: bad op");
-    if (variant < SLOS_VARIANT_AUTO || variant > SLOS_VARIANT_LAYERED)
+    if (variant < SLOS_VARIANT_AUTO || variant > SLOS_VARIANT_FUSED_PAIRS)
         return fail(SLOS_EINVAL, "slos_batch_set_config: bad variant");
     if (block != 0 && block != 64 && block != 128 && block != 256 && block != 512 && block != 768 && block != 1024)
         return fail(SLOS_EINVAL, "slos_batch_set_config: block must be 0, 64, 128, 256, 512, 768 or 1024");
     const bool bwd = op_backward(op);
     if (block == 768 && variant != SLOS_VARIANT_FUSED)
         return fail(SLOS_EUNSUPPORTED, "slos_batch_set_config: 768 is a fused-adjoint workgroup size only");
+    if (variant == SLOS_VARIANT_FUSED_PAIRS) {
+        if (!op_pairs_ok(op))
+            return fail(SLOS_EUNSUPPORTED, "slos_batch_set_config: the two-sample variant serves the amplitude and "
+                                           "probability forwards only");
+        std::string why;
+        if (!fused_pairs_supported(*batch->plan, batch->n_max, block ? block : 1024, &why))
+            return fail(SLOS_EUNSUPPORTED, "slos_batch_set_config: two-sample variant unavailable: " + why);
+    }
     if (variant == SLOS_VARIANT_FUSED) {
         std::string why;
         const int blk = block ? block : fused_block_for(*batch, op);
@@ -759,7 +792,7 @@ int run_threshold(const slos_batch_s& Bt, int op, int v, int blk, const float* U
     if (!(Bt.plan->flags & SLOS_PLAN_THRESHOLD))
         return fail(SLOS_EUNSUPPORTED, nm + ": plan was created without SLOS_PLAN_THRESHOLD");
     const bool bwd = op == SLOS_OP_THRESHOLD_PROBS_BACKWARD;
-    const bool fused = v == SLOS_VARIANT_FUSED;
+    const bool fused = variant_fused(v);
     const size_t head = expect_head_bytes(Bt);
     const size_t need = head + (fused ? 0 : layered_ws_bytes(Bt, bwd));
     if (!ws || ws_bytes < need)
@@ -768,8 +801,9 @@ int run_threshold(const slos_batch_s& Bt, int op, int v, int blk, const float* U
     void* rest = (char*)ws + head;
     int rc;
     if (!bwd) {
-        rc = fused ? launch_fused_fwd(Bt, blk, (const float2*)U, pv, 1, s)
-                   : launch_layered_fwd(Bt, blk, (const float2*)U, pv, true, rest, s);
+        rc = v == SLOS_VARIANT_FUSED_PAIRS ? launch_fused_pairs_fwd(Bt, blk, (const float2*)U, pv, true, s)
+             : fused                        ? launch_fused_fwd(Bt, blk, (const float2*)U, pv, 1, s)
+                                            : launch_layered_fwd(Bt, blk, (const float2*)U, pv, true, rest, s);
         if (rc == SLOS_OK) rc = launch_threshold_gather(Bt, pv, (float*)out, s);
         return rc;
     }
@@ -802,7 +836,9 @@ int run(slos_batch_t batch, int op, const float* U, const void* gin, void* out, 
         return run_expect(*batch, op, v, blk, U, gin, out, ws, ws_bytes, s, nm, detector == SLOS_DETECTOR_THRESHOLD);
     if (op_threshold(op)) return run_threshold(*batch, op, v, blk, U, gin, out, ws, ws_bytes, s, nm);
     int rc;
-    if (v == SLOS_VARIANT_FUSED) {
+    if (v == SLOS_VARIANT_FUSED_PAIRS && !bwd) {
+        rc = launch_fused_pairs_fwd(*batch, blk, (const float2*)U, out, probs, s);
+    } else if (v == SLOS_VARIANT_FUSED) {
         rc = bwd ? launch_fused_bwd(*batch, blk, (const float2*)U, gin, probs, (float2*)out, s)
                  : launch_fused_fwd(*batch, blk, (const float2*)U, out, probs ? 1 : 0, s);
     } else {
@@ -1199,7 +1235,7 @@ extern "C" int fock_sample(slos_batch_t batch, const float* U, const float* u, i
         return fail(SLOS_EUNSUPPORTED, nm + ": too many samples or shots for one launch");
     int v, blk;
     resolve(*batch, SLOS_OP_SAMPLE, &v, &blk);
-    const bool fused = v == SLOS_VARIANT_FUSED;
+    const bool fused = variant_fused(v);
     const size_t head = sample_head_bytes(*batch);
     const size_t need = head + (fused ? 0 : layered_ws_bytes(*batch, false));
     if (!ws || ws_bytes < need)
@@ -1209,8 +1245,9 @@ extern "C" int fock_sample(slos_batch_t batch, const float* U, const float* u, i
     double* cdf = (double*)(base + expect_head_bytes(*batch));
     double* part = (double*)(base + expect_head_bytes(*batch) + align256((size_t)batch->off_host[batch->B] * 8));
     hipStream_t s = (hipStream_t)stream;
-    int rc = fused ? launch_fused_fwd(*batch, blk, (const float2*)U, pv, 1, s)
-                   : launch_layered_fwd(*batch, blk, (const float2*)U, pv, true, base + head, s);
+    int rc = v == SLOS_VARIANT_FUSED_PAIRS ? launch_fused_pairs_fwd(*batch, blk, (const float2*)U, pv, true, s)
+             : fused                        ? launch_fused_fwd(*batch, blk, (const float2*)U, pv, 1, s)
+                                            : launch_layered_fwd(*batch, blk, (const float2*)U, pv, true, base + head, s);
     if (rc != SLOS_OK) return rc;
     return launch_sample(*batch, pv, part, cdf, u, S, shots, s);
 }

@@ -67,6 +67,10 @@ struct BatchDev {
     const float* innorm;     // [B] 1/sqrt(prod_i s_i!)
     const int32_t* order;    // [B] work order (largest photon number first)
     const int64_t* thr_off;  // [B+1] offsets of the click-pattern outputs
+    // work items of the two-sample kernels: consecutive samples of the work
+    // order with equal photon numbers, (a, b); b = -1 for a sample alone
+    const int2* pairs;       // [npairs]
+    int npairs;
 };
 
 struct Config {
@@ -97,6 +101,7 @@ struct slos_batch_s {
     void* dmem = nullptr;
     slos::BatchDev dev{};
     slos::Config cfg[9];
+    int npairs = 0;
 };
 
 namespace slos {
@@ -117,6 +122,11 @@ int launch_fused_fwd(const slos_batch_s& Bt, int block, const float2* U, void* o
                      hipStream_t stream);
 int launch_fused_bwd(const slos_batch_s& Bt, int block, const float2* U, const void* gin, bool probs,
                      float2* gU, hipStream_t stream);
+
+// ---- two samples per workgroup (forward amplitudes and probabilities): slos_fused2.hip ----
+bool fused_pairs_supported(const slos_plan_s& P, int n_max, int block, std::string* why);
+int launch_fused_pairs_fwd(const slos_batch_s& Bt, int block, const float2* U, void* out, bool probs,
+                           hipStream_t stream);
 
 // ---- layered (workspace-resident) kernels: slos_layered.hip ----
 size_t layered_ws_bytes(const slos_batch_s& Bt, bool backward);

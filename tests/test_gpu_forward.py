@@ -231,3 +231,76 @@ def test_clements_m20_n5_b512(variant, block):
     pb = p.reshape(wl.B, N)
     assert np.abs(pb.sum(axis=1, dtype=np.float64) - 1).max() < 2e-5
     assert np.abs(np.abs(a.reshape(wl.B, N)) ** 2 - pb).max() < 1e-6
+
+
+# ------------------------------------------------ two samples per workgroup
+
+@pytest.mark.parametrize("block", [512, 1024])
+def test_pairs_variant_clements_m20_n5_b512(block):
+    """The two-sample kernel at the benchmark's shape (its two largest layers
+    overlap in LDS, so the held-state path runs): oracle on the first and last
+    samples of the work order and on pairs' both halves, equal to the
+    one-sample kernel on every output."""
+    wl = W.make("clements_m20_n5_b512")
+    say("pairs variant clements_m20_n5_b512", block)
+    U = B.mesh_to_unitary(torch.from_numpy(wl.theta).to(DEV), torch.from_numpy(wl.x).to(DEV), wl.enc_scale)
+    batch = B.Batch(B.Plan(wl.m, 5), wl.occ)
+    ref = {}
+    for op, amp in ((B.OP_PROBS, False), (B.OP_AMPLITUDES, True)):
+        batch.set_config(op, B.VARIANT_FUSED, 1024)
+        ref[amp] = run_forward(batch, U, amp)
+        batch.set_config(op, B.VARIANT_FUSED_PAIRS, block)
+        assert batch.get_config(op) == (B.VARIANT_FUSED_PAIRS, block)
+    p = run_forward(batch, U, False)
+    a = run_forward(batch, U, True)
+    U64 = U.cpu().numpy()
+    picks = [0, 1, 2, 3, 254, 255, 510, 511]
+    worst_p = _check_against_oracle(batch, U64, wl.occ, p, False, samples=picks)
+    worst_a = _check_against_oracle(batch, U64, wl.occ, a, True, samples=picks)
+    say("  max |dp|", worst_p, "max |da|", worst_a)
+    assert np.abs(p - ref[False]).max() <= 1e-7
+    assert np.abs(a - ref[True]).max() <= 1e-7
+
+
+def test_pairs_variant_mixed_batch_with_lone_samples():
+    """Mixed photon numbers (odd counts leave samples without a partner),
+    vacua, bunched inputs, and pairs whose two samples have different input
+    modes: every sample against the oracle."""
+    rng = np.random.default_rng(77)
+    m = 9
+    occ = []
+    for n in [4, 4, 4, 3, 0, 2, 2, 5, 0, 3, 1]:
+        o = np.zeros(m, np.int32)
+        for j in rng.integers(0, m, n):
+            o[j] += 1
+        occ.append(o)
+    occ = np.array(occ)
+    U = _haar(rng, len(occ), m)
+    batch = B.Batch(B.Plan(m, 5), occ)
+    for op in (B.OP_PROBS, B.OP_AMPLITUDES):
+        batch.set_config(op, B.VARIANT_FUSED_PAIRS, 512)
+    Ud = to_dev_c64(U)
+    for amp in (False, True):
+        out = run_forward(batch, Ud, amp)
+        _check_against_oracle(batch, U, occ, out, amp)
+
+
+def test_pairs_variant_unsupported_and_measurement_forwards():
+    # layers of two samples that do not fit LDS are refused; measurement forwards built on probabilities use it
+    big = B.Batch(B.Plan(16, 6), np.tile(np.array([1] * 6 + [0] * 10, np.int32), (2, 1)))
+    with pytest.raises(B.SlosError):
+        big.set_config(B.OP_PROBS, B.VARIANT_FUSED_PAIRS, 1024)
+    with pytest.raises(B.SlosError):
+        big.set_config(B.OP_PROBS_BACKWARD, B.VARIANT_FUSED_PAIRS, 1024)
+    rng = np.random.default_rng(5)
+    m, Bn = 8, 9
+    U = _haar(rng, Bn, m)
+    occ = np.zeros((Bn, m), np.int32)
+    occ[:, :3] = 1
+    batch = B.Batch(B.Plan(m, 3, threshold=True), occ)
+    Ud = to_dev_c64(U)
+    batch.set_config(B.OP_THRESHOLD_PROBS, B.VARIANT_FUSED)
+    ref = B.fock_threshold_probs(batch, Ud).cpu().numpy()
+    batch.set_config(B.OP_THRESHOLD_PROBS, B.VARIANT_FUSED_PAIRS)
+    got = B.fock_threshold_probs(batch, Ud).cpu().numpy()
+    assert np.abs(got - ref).max() <= 1e-7
