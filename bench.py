@@ -47,6 +47,15 @@ def parse():
     return ap.parse_args()
 
 
+VARIANT_NAMES = {1: "fused", 2: "layered", 3: "fused-pairs"}
+
+
+def cfg_name(r):
+    """'variant/block' (or 'variant/block/tile') of an autotune report entry."""
+    s = "%s/%d" % (VARIANT_NAMES[r["variant"]], r["block"])
+    return s + ("/%d" % r["tile"] if r.get("tile") else "")
+
+
 def time_region(fn, iters, stream):
     import torch
     e0 = torch.cuda.Event(enable_timing=True)
@@ -107,10 +116,10 @@ def main():
     B.mesh_to_unitary(theta, x, wl.enc_scale, out=U, ws=mws)
     # kernel variant and workgroup size per op, picked by timing on this batch
     tuned = autotune(batch, U, ops=(B.OP_PROBS, B.OP_PROBS_BACKWARD), warmup=2, iters=3)
-    names = {B.VARIANT_FUSED: "fused", B.VARIANT_LAYERED: "layered"}
-    tuned_cfg = {op_name: "%s/%d" % (names[tuned[op]["variant"]], tuned[op]["block"])
+    names = VARIANT_NAMES
+    tuned_cfg = {op_name: cfg_name(tuned[op])
                  for op, op_name in ((B.OP_PROBS, "fock_probs"), (B.OP_PROBS_BACKWARD, "fock_probs_backward"))}
-    log("autotune: %s" % json.dumps({k: [(names[v], b, round(t, 1)) for v, b, t in tuned[op]["timings"]]
+    log("autotune: %s" % json.dumps({k: [(names[v], b, t, round(us, 1)) for v, b, t, us in tuned[op]["timings"]]
                                       for op, k in ((B.OP_PROBS, "fwd"), (B.OP_PROBS_BACKWARD, "bwd"))}))
     fws = batch.workspace(B.OP_PROBS, dev)
     bws = batch.workspace(B.OP_PROBS_BACKWARD, dev)
@@ -355,7 +364,6 @@ def bench_other(args, wl, dev):
         B.mesh_to_unitary(theta, x, wl.enc_scale, out=U, ws=mws)
     ops = (B.OP_PROBS, B.OP_PROBS_BACKWARD) if wl.backward else (B.OP_PROBS,)
     tuned = autotune(batch, U, ops=ops, warmup=1, iters=2)
-    names = {B.VARIANT_FUSED: "fused", B.VARIANT_LAYERED: "layered"}
     p = torch.empty(batch.out_len, dtype=torch.float32, device=dev)
     gU = torch.empty_like(U)
     fws = batch.workspace(B.OP_PROBS, dev)
@@ -391,7 +399,7 @@ def bench_other(args, wl, dev):
            "vs_baseline": None, "dtype": "c64", "data": "synthetic",
            "config": {"workload": wl.name, "m": m, "n": sorted(set(int(v) for v in wl.n)), "batch": Bn,
                       "outputs_per_step": amps, "launch": "eager",
-                      "autotuned": {str(op): "%s/%d" % (names[t["variant"]], t["block"]) for op, t in tuned.items()}},
+                      "autotuned": {str(op): cfg_name(t) for op, t in tuned.items()}},
            "roofline": None, "cpu_baseline": None}
     print(json.dumps(out), flush=True)
 

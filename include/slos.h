@@ -223,6 +223,13 @@ SLOS_API int slos_batch_set_config(slos_batch_t batch, int op, int variant, int 
 /* Reads back the configuration in use for `op` (variant, block). */
 SLOS_API int slos_batch_get_config(slos_batch_t batch, int op, int* variant, int* block);
 
+/* slos_batch_set_config with a tile size: the last-layer states each thread
+ * takes per iteration in the two-sample forward (2, 4 or 8; 0 = default 4).
+ * Other variants take tile = 0 only (SLOS_EINVAL otherwise). */
+SLOS_API int slos_batch_set_config_ex(slos_batch_t batch, int op, int variant, int block, int tile);
+/* Reads back (variant, block, tile); tile is 0 for variants without one. */
+SLOS_API int slos_batch_get_config_ex(slos_batch_t batch, int op, int* variant, int* block, int* tile);
+
 /* ---- Forward: amplitudes and probabilities (Sec. II-A-1/2/3, Sec. II-B) --- */
 
 /* amps (device, complex, [out_len]) <- a_t for every sample and output state.

@@ -71,6 +71,9 @@ SIGNATURES = {
     "slos_workspace_bytes": (_c.c_int, [_vp, _c.c_int, _c.POINTER(_c.c_size_t)]),
     "slos_batch_set_config": (_c.c_int, [_vp, _c.c_int, _c.c_int, _c.c_int]),
     "slos_batch_get_config": (_c.c_int, [_vp, _c.c_int, _c.POINTER(_c.c_int), _c.POINTER(_c.c_int)]),
+    "slos_batch_set_config_ex": (_c.c_int, [_vp, _c.c_int, _c.c_int, _c.c_int, _c.c_int]),
+    "slos_batch_get_config_ex": (_c.c_int, [_vp, _c.c_int, _c.POINTER(_c.c_int), _c.POINTER(_c.c_int),
+                                            _c.POINTER(_c.c_int)]),
     "fock_amplitudes": (_c.c_int, [_vp, _vp, _vp, _vp, _c.c_size_t, _vp]),
     "fock_probs": (_c.c_int, [_vp, _vp, _vp, _vp, _c.c_size_t, _vp]),
     "fock_amplitudes_backward": (_c.c_int, [_vp, _vp, _vp, _vp, _vp, _c.c_size_t, _vp]),
@@ -269,6 +272,7 @@ class Plan:
         self.n_max = n_max
         self.unbunched = unbunched
         self.dual_rail = dual_rail
+        self.threshold = threshold
 
     @property
     def handle(self):
@@ -319,13 +323,20 @@ class Batch:
         _check("slos_workspace_bytes", lib().slos_workspace_bytes(self._h, op, ctypes.byref(n)))
         return int(n.value)
 
-    def set_config(self, op: int, variant: int, block: int = 0):
-        _check("slos_batch_set_config", lib().slos_batch_set_config(self._h, op, variant, block))
+    def set_config(self, op: int, variant: int, block: int = 0, tile: int = 0):
+        _check("slos_batch_set_config_ex", lib().slos_batch_set_config_ex(self._h, op, variant, block, tile))
 
     def get_config(self, op: int) -> Tuple[int, int]:
         v, b = ctypes.c_int(0), ctypes.c_int(0)
         _check("slos_batch_get_config", lib().slos_batch_get_config(self._h, op, ctypes.byref(v), ctypes.byref(b)))
         return int(v.value), int(b.value)
+
+    def get_config_ex(self, op: int) -> Tuple[int, int, int]:
+        """(variant, block, tile) in use for `op`."""
+        v, b, t = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int(0)
+        _check("slos_batch_get_config_ex", lib().slos_batch_get_config_ex(self._h, op, ctypes.byref(v),
+                                                                          ctypes.byref(b), ctypes.byref(t)))
+        return int(v.value), int(b.value), int(t.value)
 
     def workspace(self, op: int, device) -> Optional[torch.Tensor]:
         """Device workspace for `op` on the current stream, kept by the batch

@@ -31,7 +31,7 @@ __device__ __forceinline__ void lds_st4(uint32_t a, f4v v) { *(lds_f4v*)(size_t)
 
 constexpr uint32_t kCol2Addr = 0;                         // [33] coefficient pairs; slot 32 stays zero
 constexpr uint32_t kX2Addr = (uint32_t)kUcolSlots * 16u;  // state pairs
-constexpr int kSU2 = 4;                                    // states per thread per iteration
+constexpr int kSU2 = 4;                                    // lower layers: states per thread per iteration
 constexpr int kLP2 = 2;                                    // states whose gathers issue together
 // A compact entry (mode << 25) | (rank << 3) gives the 16-byte coefficient
 // slot as e >> 21 when the rank is below 2^18, and the 16-byte state slot
@@ -171,7 +171,8 @@ __host__ __device__ __forceinline__ int64_t layer_start(int n, int k, int64_t N_
 }
 
 // EPI 0: amplitudes, 1: probabilities ([out_len], each sample at its offset).
-template <int BLOCK, int EPI>
+// TU: last-layer states per thread per iteration (the tile the autotuner picks).
+template <int BLOCK, int EPI, int TU>
 __global__ __launch_bounds__(BLOCK) void fused_pairs_fwd_kernel(int m, const LayerDev* __restrict__ Ls, BatchDev Bt,
                                                                 const float2* __restrict__ U, void* __restrict__ out,
                                                                 int C) {
@@ -231,14 +232,14 @@ __global__ __launch_bounds__(BLOCK) void fused_pairs_fwd_kernel(int m, const Lay
                 const __amdgpu_buffer_rsrc_t rb =
                     buf_rsrc(PROBS ? (const void*)((float*)out + offb) : (const void*)((float2*)out + offb),
                              two ? (uint32_t)N * (PROBS ? 4u : 8u) : 0u);
-                for (int t0 = tid; t0 < N; t0 += BLOCK * kSU2) {
-                    float c[kSU2];
+                for (int t0 = tid; t0 < N; t0 += BLOCK * TU) {
+                    float c[TU];
 #pragma unroll
-                    for (int u = 0; u < kSU2; ++u) c[u] = buf_ldf(rn, (uint32_t)min(t0 + u * BLOCK, N - 1) * 4u, 0);
-                    f4v acc[kSU2];
-                    gather2_states<BLOCK, kSU2, kLP2>(L, k, t0, N, kX2Addr, acc);
+                    for (int u = 0; u < TU; ++u) c[u] = buf_ldf(rn, (uint32_t)min(t0 + u * BLOCK, N - 1) * 4u, 0);
+                    f4v acc[TU];
+                    gather2_states<BLOCK, TU, kLP2>(L, k, t0, N, kX2Addr, acc);
 #pragma unroll
-                    for (int u = 0; u < kSU2; ++u) {
+                    for (int u = 0; u < TU; ++u) {
                         const int t = t0 + u * BLOCK;
                         if (t >= N) continue;
                         const float cA = c[u] * ina, cB = c[u] * inb;
@@ -298,9 +299,14 @@ bool pair_layout(const slos_plan_s& P, int n_max, int block, size_t lds, int64_t
     return true;
 }
 
-template <int BLOCK>
+template <int BLOCK, int TU>
 void* pairs_fn(bool probs) {
-    return probs ? (void*)&fused_pairs_fwd_kernel<BLOCK, 1> : (void*)&fused_pairs_fwd_kernel<BLOCK, 0>;
+    return probs ? (void*)&fused_pairs_fwd_kernel<BLOCK, 1, TU> : (void*)&fused_pairs_fwd_kernel<BLOCK, 0, TU>;
+}
+
+template <int BLOCK>
+void* pairs_fn_tile(bool probs, int tile) {
+    return tile == 2 ? pairs_fn<BLOCK, 2>(probs) : tile == 8 ? pairs_fn<BLOCK, 8>(probs) : pairs_fn<BLOCK, 4>(probs);
 }
 
 }  // namespace
@@ -319,7 +325,7 @@ bool fused_pairs_supported(const slos_plan_s& P, int n_max, int block, std::stri
     return pair_layout(P, n_max, block, P.max_lds, &C, why);
 }
 
-int launch_fused_pairs_fwd(const slos_batch_s& Bt, int block, const float2* U, void* out, bool probs,
+int launch_fused_pairs_fwd(const slos_batch_s& Bt, int block, int tile, const float2* U, void* out, bool probs,
                            hipStream_t stream) {
     const slos_plan_s& P = *Bt.plan;
     std::string why;
@@ -327,7 +333,7 @@ int launch_fused_pairs_fwd(const slos_batch_s& Bt, int block, const float2* U, v
     int64_t C = 0;
     pair_layout(P, Bt.n_max, block, P.max_lds, &C, nullptr);
     const size_t lds = (size_t)(kUcolSlots + C) * 16;
-    void* fn = block == 512 ? pairs_fn<512>(probs) : pairs_fn<1024>(probs);
+    void* fn = block == 512 ? pairs_fn_tile<512>(probs, tile) : pairs_fn_tile<1024>(probs, tile);
     (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, block, lds) != hipSuccess || per_cu < 1) per_cu = 1;

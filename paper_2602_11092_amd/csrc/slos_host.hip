@@ -718,6 +718,10 @@ extern "C" int slos_workspace_bytes(slos_batch_t batch, int op, size_t* bytes) {
 }
 
 extern "C" int slos_batch_set_config(slos_batch_t batch, int op, int variant, int block) {
+    return slos_batch_set_config_ex(batch, op, variant, block, 0);
+}
+
+extern "C" int slos_batch_set_config_ex(slos_batch_t batch, int op, int variant, int block, int tile) {
     if (!batch) return fail(SLOS_EINVAL, "slos_batch_set_config: batch is NULL");
     if (!op_valid(op)) return fail(SLOS_EINVAL, "slos_batch_set_config: bad op");
     if (variant < SLOS_VARIANT_AUTO || variant > SLOS_VARIANT_FUSED_PAIRS)
@@ -742,8 +746,11 @@ extern "C" int slos_batch_set_config(slos_batch_t batch, int op, int variant, in
                             : fused_fwd_supported(*batch->plan, batch->n_max, blk, &why, op_expect(op));
         if (!ok) return fail(SLOS_EUNSUPPORTED, "slos_batch_set_config: fused variant unavailable: " + why);
     }
+    if (tile != 0 && !(variant == SLOS_VARIANT_FUSED_PAIRS && (tile == 2 || tile == 4 || tile == 8)))
+        return fail(SLOS_EINVAL, "slos_batch_set_config_ex: tile must be 0, or 2, 4 or 8 with the two-sample variant");
     batch->cfg[op].variant = variant;
     batch->cfg[op].block = block;
+    batch->cfg[op].tile = tile;
     return SLOS_OK;
 }
 
@@ -751,6 +758,14 @@ extern "C" int slos_batch_get_config(slos_batch_t batch, int op, int* variant, i
     if (!batch || !variant || !block) return fail(SLOS_EINVAL, "slos_batch_get_config: NULL argument");
     if (!op_valid(op)) return fail(SLOS_EINVAL, "slos_batch_get_config: bad op");
     return resolve(*batch, op, variant, block);
+}
+
+extern "C" int slos_batch_get_config_ex(slos_batch_t batch, int op, int* variant, int* block, int* tile) {
+    if (!tile) return fail(SLOS_EINVAL, "slos_batch_get_config_ex: NULL argument");
+    const int rc = slos_batch_get_config(batch, op, variant, block);
+    if (rc != SLOS_OK) return rc;
+    *tile = batch->cfg[op].tile != 0 ? batch->cfg[op].tile : (*variant == SLOS_VARIANT_FUSED_PAIRS ? 4 : 0);
+    return SLOS_OK;
 }
 
 namespace {
@@ -801,7 +816,7 @@ int run_threshold(const slos_batch_s& Bt, int op, int v, int blk, const float* U
     void* rest = (char*)ws + head;
     int rc;
     if (!bwd) {
-        rc = v == SLOS_VARIANT_FUSED_PAIRS ? launch_fused_pairs_fwd(Bt, blk, (const float2*)U, pv, true, s)
+        rc = v == SLOS_VARIANT_FUSED_PAIRS ? launch_fused_pairs_fwd(Bt, blk, Bt.cfg[op].tile, (const float2*)U, pv, true, s)
              : fused                        ? launch_fused_fwd(Bt, blk, (const float2*)U, pv, 1, s)
                                             : launch_layered_fwd(Bt, blk, (const float2*)U, pv, true, rest, s);
         if (rc == SLOS_OK) rc = launch_threshold_gather(Bt, pv, (float*)out, s);
@@ -837,7 +852,7 @@ int run(slos_batch_t batch, int op, const float* U, const void* gin, void* out, 
     if (op_threshold(op)) return run_threshold(*batch, op, v, blk, U, gin, out, ws, ws_bytes, s, nm);
     int rc;
     if (v == SLOS_VARIANT_FUSED_PAIRS && !bwd) {
-        rc = launch_fused_pairs_fwd(*batch, blk, (const float2*)U, out, probs, s);
+        rc = launch_fused_pairs_fwd(*batch, blk, batch->cfg[op].tile, (const float2*)U, out, probs, s);
     } else if (v == SLOS_VARIANT_FUSED) {
         rc = bwd ? launch_fused_bwd(*batch, blk, (const float2*)U, gin, probs, (float2*)out, s)
                  : launch_fused_fwd(*batch, blk, (const float2*)U, out, probs ? 1 : 0, s);
@@ -1245,7 +1260,7 @@ extern "C" int fock_sample(slos_batch_t batch, const float* U, const float* u, i
     double* cdf = (double*)(base + expect_head_bytes(*batch));
     double* part = (double*)(base + expect_head_bytes(*batch) + align256((size_t)batch->off_host[batch->B] * 8));
     hipStream_t s = (hipStream_t)stream;
-    int rc = v == SLOS_VARIANT_FUSED_PAIRS ? launch_fused_pairs_fwd(*batch, blk, (const float2*)U, pv, true, s)
+    int rc = v == SLOS_VARIANT_FUSED_PAIRS ? launch_fused_pairs_fwd(*batch, blk, batch->cfg[SLOS_OP_SAMPLE].tile, (const float2*)U, pv, true, s)
              : fused                        ? launch_fused_fwd(*batch, blk, (const float2*)U, pv, 1, s)
                                             : launch_layered_fwd(*batch, blk, (const float2*)U, pv, true, base + head, s);
     if (rc != SLOS_OK) return rc;

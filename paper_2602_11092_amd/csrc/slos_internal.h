@@ -76,6 +76,7 @@ struct BatchDev {
 struct Config {
     int variant = SLOS_VARIANT_AUTO;
     int block = 0;
+    int tile = 0;  // states per thread of the variant's main loop (0: its default)
 };
 
 }  // namespace slos
@@ -125,7 +126,8 @@ int launch_fused_bwd(const slos_batch_s& Bt, int block, const float2* U, const v
 
 // ---- two samples per workgroup (forward amplitudes and probabilities): slos_fused2.hip ----
 bool fused_pairs_supported(const slos_plan_s& P, int n_max, int block, std::string* why);
-int launch_fused_pairs_fwd(const slos_batch_s& Bt, int block, const float2* U, void* out, bool probs,
+// tile: last-layer states per thread per iteration, 2, 4 or 8 (0: 4)
+int launch_fused_pairs_fwd(const slos_batch_s& Bt, int block, int tile, const float2* U, void* out, bool probs,
                            hipStream_t stream);
 
 // ---- layered (workspace-resident) kernels: slos_layered.hip ----

@@ -41,10 +41,11 @@ def test_autotune_choice_and_parity(case):
     for op in (B.OP_PROBS, B.OP_PROBS_BACKWARD):
         r = rep[op]
         assert r["timings"], op
-        assert (r["variant"], r["block"]) in [(v, b) for v, b, _ in r["timings"]]
-        assert r["us"] == min(t for _, _, t in r["timings"])
+        assert (r["variant"], r["block"], r["tile"]) in [(v, b, t) for v, b, t, _ in r["timings"]]
+        assert r["us"] == min(us for _, _, _, us in r["timings"])
+        assert not r["rejected"], r["rejected"]  # every supported configuration agrees with the reference
         assert batch.get_config(op) == (r["variant"], r["block"])
-        say(op, [(v, b, round(t, 1)) for v, b, t in r["timings"]])
+        say(op, [(v, b, t, round(us, 1)) for v, b, t, us in r["timings"]])
     # the tuned batch still matches the oracle
     p = B.fock_probs(batch, Ud)
     rng = np.random.default_rng(3)
@@ -68,7 +69,7 @@ def test_autotune_skips_unsupported_candidates():
     plan = B.Plan(22, int(occ.sum(1).max()))
     batch = B.Batch(plan, occ)
     rep = autotune(batch, to_dev_c64(U64), ops=(B.OP_PROBS_BACKWARD,), warmup=1, iters=1)
-    blocks = [(v, b) for v, b, _ in rep[B.OP_PROBS_BACKWARD]["timings"]]
+    blocks = [(v, b) for v, b, _, _ in rep[B.OP_PROBS_BACKWARD]["timings"]]
     assert (B.VARIANT_FUSED, 768) not in blocks
     assert (B.VARIANT_LAYERED, 256) in blocks
     with pytest.raises(B.SlosError):
@@ -88,3 +89,28 @@ def test_autotune_measurement_ops():
     e = B.fock_mode_expectations(batch, Ud).cpu().numpy()
     for b in range(batch.B):
         assert np.abs(e[b] - O.mode_expectations(widen(U64[b]), occ[b])).max() <= 2e-5
+
+
+def test_autotune_cache_round_trip(tmp_path):
+    """The choice is stored under the batch's key and reused without timing;
+    a stored choice the batch no longer accepts is tuned again."""
+    import json
+    U64, occ = _mixed_batch(seed=11, B_=10, m=6)
+    batch = B.Batch(B.Plan(6, int(occ.sum(1).max())), occ)
+    Ud = to_dev_c64(U64)
+    path = str(tmp_path / "tune.json")
+    rep1 = autotune(batch, Ud, ops=(B.OP_PROBS, B.OP_PROBS_BACKWARD), warmup=1, iters=1, cache=path)
+    data = json.load(open(path))
+    from paper_2602_11092_amd.autotune import cache_key
+    key = cache_key(batch, Ud.device)
+    assert key in data and set(data[key]) == {str(B.OP_PROBS), str(B.OP_PROBS_BACKWARD)}
+    fresh = B.Batch(batch.plan, occ)
+    rep2 = autotune(fresh, Ud, ops=(B.OP_PROBS, B.OP_PROBS_BACKWARD), warmup=1, iters=1, cache=path)
+    for op in (B.OP_PROBS, B.OP_PROBS_BACKWARD):
+        assert rep2[op]["cached"] and not rep2[op]["timings"]
+        assert fresh.get_config_ex(op) == (rep1[op]["variant"], rep1[op]["block"], rep1[op]["tile"])
+    # a stored configuration this batch rejects (768 threads is an adjoint size only) is tuned again
+    data[key][str(B.OP_PROBS)] = {"variant": B.VARIANT_FUSED, "block": 768, "tile": 0, "us": 1.0}
+    json.dump(data, open(path, "w"))
+    rep3 = autotune(B.Batch(batch.plan, occ), Ud, ops=(B.OP_PROBS,), warmup=1, iters=1, cache=path)
+    assert not rep3[B.OP_PROBS]["cached"] and rep3[B.OP_PROBS]["timings"]

@@ -312,3 +312,33 @@ def test_workspace_cache_retires_instead_of_freeing():
     assert other is not b
     assert c.get(("op", 1), 0, "cpu") is b
     assert B.WorkspaceCache._round(1) == 256 and B.WorkspaceCache._round(257) == 512
+
+
+def test_autotune_gate_comparison_and_cache_files(tmp_path):
+    """Host logic of the autotuner: the gate's comparison rejects a
+    perturbed output, a non-finite one and a shape mismatch; the cache file
+    round-trips entries and survives a missing or corrupt file."""
+    from paper_2602_11092_amd import autotune as T
+    ref = np.linspace(0, 1, 50).astype(np.float32)
+    assert T.agrees(B.OP_PROBS, ref.copy(), ref)
+    assert not T.agrees(B.OP_PROBS, ref + 2e-6, ref)
+    bad = ref.copy()
+    bad[3] = np.nan
+    assert not T.agrees(B.OP_PROBS, bad, ref)
+    assert not T.agrees(B.OP_PROBS, ref[:-1], ref)
+    g = np.ones((2, 3, 3), np.complex64)
+    assert T.agrees(B.OP_PROBS_BACKWARD, g * (1 + 5e-6), g)
+    assert not T.agrees(B.OP_PROBS_BACKWARD, g * (1 + 5e-5), g)
+    shots = np.arange(100, dtype=np.int32).reshape(2, 50)
+    near = shots.copy()
+    near[0, 0] += 1  # one shot of 100 on the other side of a boundary
+    assert T.agrees(B.OP_SAMPLE, near, shots)
+    near[1, :5] += 1
+    assert not T.agrees(B.OP_SAMPLE, near, shots)
+    path = str(tmp_path / "sub" / "tune.json")
+    assert T._load_cache(path) == {}
+    T._store_cache(path, "k1", 1, {"variant": 3, "block": 1024, "tile": 4, "us": 50.0})
+    T._store_cache(path, "k1", 3, {"variant": 1, "block": 768, "tile": 0, "us": 200.0})
+    assert T._load_cache(path)["k1"]["1"]["tile"] == 4 and T._load_cache(path)["k1"]["3"]["block"] == 768
+    open(path, "w").write("{ not json")
+    assert T._load_cache(path) == {}
