@@ -56,6 +56,41 @@ def cfg_name(r):
     return s + ("/%d" % r["tile"] if r.get("tile") else "")
 
 
+def replay_percentiles(run, stream, n=100):
+    """Median, 10th and 90th percentile (ms) of n single replays, each
+    bracketed by its own HIP events on the launch stream."""
+    import numpy as np
+    import torch
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+    torch.cuda.synchronize()
+    for a, b in ev:
+        a.record(stream)
+        run()
+        b.record(stream)
+    torch.cuda.synchronize()
+    t = np.array([a.elapsed_time(b) for a, b in ev])
+    return {"n": n, "median_ms": round(float(np.median(t)), 5), "p10_ms": round(float(np.percentile(t, 10)), 5),
+            "p90_ms": round(float(np.percentile(t, 90)), 5)}
+
+
+def roofline_of(kernel, avg_ms, flops, nbytes):
+    """Roofline entry of one kernel from its algorithmic flops and HBM bytes
+    per launch: the bound is the resource it comes closer to saturating
+    (FP32 vector ALUs without packed math, or HBM)."""
+    alu = flops / (avg_ms * 1e-3) / 1e12
+    hbm = nbytes / (avg_ms * 1e-3) / 1e9
+    fa, fh = alu / ALU_PEAK_TFLOPS, hbm / HBM_PEAK_GBS
+    r = {"kernel": kernel, "avg_us": round(avg_ms * 1e3, 3), "algorithmic_flop": flops, "algorithmic_bytes": nbytes,
+         "alu_tflops": round(alu, 3), "alu_frac": round(fa, 4), "hbm_gbs": round(hbm, 1), "hbm_frac": round(fh, 4)}
+    if fa >= fh:
+        r.update({"bound": "alu", "achieved": round(alu, 3), "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                  "frac": round(fa, 4)})
+    else:
+        r.update({"bound": "hbm", "achieved": round(hbm, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(fh, 4)})
+    r["traffic"] = load_traffic(kernel)
+    return r
+
+
 def time_region(fn, iters, stream):
     import torch
     e0 = torch.cuda.Event(enable_timing=True)
@@ -167,6 +202,7 @@ def main():
     torch.cuda.synchronize()
     wall_ms = (time.perf_counter() - t_start) * 1e3
     ms_per_step = e0.elapsed_time(e1) / args.steps
+    replays = replay_percentiles(run, stream)
     amps_per_step = Bn * N
     value = amps_per_step / (ms_per_step * 1e-3)
     log("step %.4f ms (wall %.4f ms/step), %.3e amps/s" % (ms_per_step, wall_ms / args.steps, value))
@@ -203,15 +239,7 @@ def main():
         dur, flops, nbytes = k_bwd, flop_bwd, bwd_bytes
     else:
         dur, flops, nbytes = k_fwd, flop_fwd, fwd_bytes
-    alu_tflops = flops / (dur * 1e-3) / 1e12
-    hbm_gbs = nbytes / (dur * 1e-3) / 1e9
-    roofline = {"kernel": dominant, "bound": "alu", "achieved": round(alu_tflops, 3), "peak": ALU_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(alu_tflops / ALU_PEAK_TFLOPS, 4), "traffic": None,
-                "hbm_gbs": round(hbm_gbs, 1), "hbm_frac": round(hbm_gbs / HBM_PEAK_GBS, 4),
-                "algorithmic_bytes": nbytes, "algorithmic_flop": flops, "avg_us": round(dur * 1e3, 3)}
-    tr = load_traffic(dominant)
-    if tr is not None:
-        roofline["traffic"] = tr
+    roofline = roofline_of(dominant, dur, flops, nbytes)
     hbm_frac_step = step_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS
 
     # ---- readout + cross-entropy + its backward, for the full training step
@@ -238,7 +266,9 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(wl, U, p, gp, N)
+        run()  # U, p and dL/dU of one step, for the comparison with the oracle
+        torch.cuda.synchronize()
+        cpu = cpu_baseline(wl, U, p, gp, gU, N)
 
     out = {
         "metric": METRIC,
@@ -258,12 +288,14 @@ def main():
                    "launch": "eager" if args.eager else "hip_graph", "autotuned": tuned_cfg},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "replays": replays,
         "hbm_frac_step": round(hbm_frac_step, 4),
         "kernels_us": {k: round(v, 3) for k, v in kernels_us.items()},
         "train_step_ms": round(ms_per_step + readout_ms, 4),
         "readout_ms": round(readout_ms, 4),
         "plain_path": plain,
         "max_abs_dp": cpu.get("max_abs_dp") if cpu else None,
+        "grad_rel_err": cpu.get("grad_rel_err") if cpu else None,
     }
     print(json.dumps(out), flush=True)
 
@@ -304,23 +336,29 @@ def plain_path(B, wl, theta, x, gp, plan, N, dev, stream, ms_batched):
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3
     return {"ms_per_step": round(ms, 3), "speedup_of_batched_fused": round(ms / ms_batched, 1),
-            "variant": "layered, B=1 per call, eager"}
+            "variant": "layered, B=1 per call, eager: about 13 kernel launches per sample, so the factor is "
+                       "mostly launch overhead"}
 
 
-def cpu_baseline(wl, U, p, gp, N):
+def cpu_baseline(wl, U, p, gp, gU, N):
     """The FP64 oracle (Ryser permanents and minor permanents) timed on the
-    host for a bounded sample of the workload's samples."""
+    host for a bounded sample of the workload's samples; also the largest
+    |p_gpu - p| and the relative error of dL/dU over the sampled samples."""
     import numpy as np
     from oracle import oracle as O
     threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
     U64 = U.cpu().numpy().astype(np.complex128)
     pn = p.cpu().numpy()
     gpn = gp.cpu().numpy().astype(np.float64)
+    gUn = gU.cpu().numpy().astype(np.complex128)
     worst = 0.0
+    gerr = [0.0, 0.0]
 
     def one(b):
         a = O.amplitudes(U64[b], wl.occ[b])
-        O.probs_grad(U64[b], wl.occ[b], gpn[b * N:(b + 1) * N])
+        g = O.probs_grad(U64[b], wl.occ[b], gpn[b * N:(b + 1) * N])
+        gerr[0] += float(np.linalg.norm(gUn[b] - g) ** 2)
+        gerr[1] += float(np.linalg.norm(g) ** 2)
         return float(np.abs(np.abs(a) ** 2 - pn[b * N:(b + 1) * N]).max())
 
     O.build(force=False)
@@ -335,14 +373,20 @@ def cpu_baseline(wl, U, p, gp, N):
     return {"value": S * N / dt, "unit": "Fock amplitudes/s", "cores": threads, "kind": "oracle",
             "sample": "%d of %d samples, forward amplitudes + minor-permanent gradient, FP64 Ryser, OpenMP" % (
                 S, wl.B),
-            "seconds": round(dt, 2), "max_abs_dp": worst}
+            "seconds": round(dt, 2), "max_abs_dp": worst,
+            "grad_rel_err": math.sqrt(gerr[0] / max(gerr[1], 1e-300)),
+            "grad_samples": S + 1}
 
 
 def bench_other(args, wl, dev):
-    """The other workloads (given unitaries, mixed photon numbers, forward
-    only): one step is mesh forward (if the workload has a mesh) + fock_probs
-    (+ fock_probs_backward with the workload's dL/dp).  A secondary line: the
-    benchmark's metric is quoted on the m=20, n=5 training step."""
+    """The metric's other configurations, each as a line of its own: m=6 n=3
+    B=64 and m=16 n=6 B=256 (Haar unitaries, forward), m=12 Clements mesh
+    with n in 2..6 mixed in one batch of 4096 (mesh + forward), m=24 n=8 B=16
+    (Haar, forward + adjoint of L = sum_b sum_t w_t p_bt, layers recomputed).
+    One step is [mesh forward] + fock_probs [+ fock_probs_backward], replayed
+    as a HIP graph.  The line carries the headline's fields: roofline of the
+    dominant kernel, the oracle timed beside it, max |dp|, the gradient error
+    where there is an adjoint, replay percentiles and device memory."""
     import numpy as np
     import torch
 
@@ -351,6 +395,7 @@ def bench_other(args, wl, dev):
 
     stream = torch.cuda.current_stream()
     m, Bn = wl.m, wl.B
+    torch.cuda.reset_peak_memory_stats()
     plan = B.Plan(m, int(wl.n.max()))
     batch = B.Batch(plan, wl.occ)
     if wl.U is not None:
@@ -368,11 +413,9 @@ def bench_other(args, wl, dev):
     gU = torch.empty_like(U)
     fws = batch.workspace(B.OP_PROBS, dev)
     bws = batch.workspace(B.OP_PROBS_BACKWARD, dev) if wl.backward else None
-    if wl.backward:
-        if wl.loss_w is not None:  # L = sum_b sum_t w_t p_bt: dL/dp = w for every sample
-            gp = torch.from_numpy(np.tile(wl.loss_w, Bn)).to(dev)
-        else:
-            gp = torch.ones(batch.out_len, dtype=torch.float32, device=dev)
+    gp = None
+    if wl.backward:  # L = sum_b sum_t w_t p_bt: dL/dp = w for every sample
+        gp = torch.from_numpy(np.tile(wl.loss_w, Bn)).to(dev)
 
     def step():
         if theta is not None:
@@ -381,27 +424,128 @@ def bench_other(args, wl, dev):
         if wl.backward:
             B.fock_probs_backward(batch, U, gp, out=gU, ws=bws)
 
+    step()
+    torch.cuda.synchronize()
+    if args.eager:
+        run = step
+    else:
+        side = torch.cuda.Stream()
+        side.wait_stream(stream)
+        with torch.cuda.stream(side):
+            step()
+        stream.wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            step()
+        run = graph.replay
     for _ in range(args.warmup):
-        step()
+        run()
     torch.cuda.synchronize()
     a = torch.cuda.Event(enable_timing=True)
     b = torch.cuda.Event(enable_timing=True)
     a.record(stream)
     for _ in range(args.steps):
-        step()
+        run()
     b.record(stream)
     b.synchronize()
     ms = a.elapsed_time(b) / args.steps
+    replays = replay_percentiles(run, stream)
+    free, total = torch.cuda.mem_get_info(dev)
+    memory = {"torch_peak_gb": round(torch.cuda.max_memory_allocated(dev) / 1e9, 3),
+              "device_used_gb": round((total - free) / 1e9, 3)}
     amps = int(batch.out_len)
+    log("%s: step %.4f ms, %.3e amps/s" % (wl.name, ms, amps / (ms * 1e-3)))
+
+    # per-kernel times and the dominant kernel's roofline (algorithmic work:
+    # n_b * N_b complex MACs per forward sample, three times that per adjoint
+    # sample with recomputation; U in and p out, plus dL/dp in and dL/dU out)
+    kiters = max(10, min(100, args.steps))
+    kernels = {"fock_probs": time_region(lambda: B.fock_probs(batch, U, out=p, ws=fws), kiters, stream)}
+    if wl.backward:
+        kernels["fock_probs_backward"] = time_region(lambda: B.fock_probs_backward(batch, U, gp, out=gU, ws=bws),
+                                                     kiters, stream)
+    if theta is not None:
+        kernels["mesh_to_unitary"] = time_region(lambda: B.mesh_to_unitary(theta, x, wl.enc_scale, out=U, ws=mws),
+                                                 kiters, stream)
+    edges = float(sum(int(n) * math.comb(m + int(n) - 1, int(n)) for n in wl.n))
+    u_bytes = 8 * m * m * Bn
+    work = {"fock_probs": (8.0 * edges, u_bytes + 4 * amps),
+            "fock_probs_backward": (8.0 * 3 * edges, 2 * u_bytes + 4 * amps)}
+    dominant = max((k for k in kernels if k in work), key=lambda k: kernels[k])
+    roofline = roofline_of(dominant, kernels[dominant], *work[dominant])
+    torch.cuda.synchronize()
+    cpu = None if args.no_cpu_baseline else cpu_baseline_other(wl, U, p, gU, gp)
     out = {"metric": "Fock amplitudes/sec, batched %s (%s)" % ("fwd+bwd" if wl.backward else "fwd", wl.name),
            "value": amps / (ms * 1e-3), "unit": "Fock amplitudes/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "c64", "data": "synthetic",
            "config": {"workload": wl.name, "m": m, "n": sorted(set(int(v) for v in wl.n)), "batch": Bn,
-                      "outputs_per_step": amps, "launch": "eager",
+                      "outputs_per_step": amps, "launch": "eager" if args.eager else "hip_graph",
+                      "pass": ("mesh fwd + " if theta is not None else "") + "fock_probs" +
+                              (" + fock_probs_backward" if wl.backward else ""),
                       "autotuned": {str(op): cfg_name(t) for op, t in tuned.items()}},
-           "roofline": None, "cpu_baseline": None}
+           "roofline": roofline, "cpu_baseline": cpu, "replays": replays, "memory": memory,
+           "kernels_us": {k: round(v * 1e3, 3) for k, v in kernels.items()},
+           "max_abs_dp": cpu.get("max_abs_dp") if cpu else None,
+           "grad_rel_err": cpu.get("grad_rel_err") if cpu else None}
     print(json.dumps(out), flush=True)
+
+
+def cpu_baseline_other(wl, U, p, gU, gp):
+    """The FP64 oracle beside the GPU for the other configurations, on a
+    bounded sample: every output of as many samples as about 12 s allow, or
+    for the m=24, n=8 workload 300 seeded outputs per sample (its samples have
+    7.9 million outputs each).  Where there is an adjoint: the relative error
+    of <dL/dU, V> against FP64 central differences (h = 1e-6) of the oracle
+    loss, for two directions V on one output mode's row of sample 0 each (the
+    outputs with t_j = 0 do not change along such a V and drop out)."""
+    import numpy as np
+    from oracle import oracle as O
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
+    O.build(force=False)
+    U64 = U.cpu().numpy().astype(np.complex128)
+    pn = p.cpu().numpy()
+    off = np.concatenate([[0], np.cumsum([math.comb(wl.m + int(n) - 1, int(n)) for n in wl.n])])
+    rng = np.random.default_rng(31)
+    worst, done, units = 0.0, 0, 0
+    t0 = time.perf_counter()
+    big = off[1] - off[0] > 1_000_000
+    while done < wl.B and time.perf_counter() - t0 < 12.0:
+        b = done
+        n = int(wl.n[b])
+        if big:
+            ranks = np.unique(rng.integers(0, off[b + 1] - off[b], 300))
+            outs = np.stack([O.fock_unrank(wl.m, n, int(r)) for r in ranks])
+            ref = O.probabilities(U64[b], wl.occ[b], outputs=outs)
+            got = pn[off[b] + ranks]
+        else:
+            ref = O.probabilities(U64[b], wl.occ[b])
+            got = pn[off[b]:off[b + 1]]
+        worst = max(worst, float(np.abs(got - ref).max()))
+        units += ref.size
+        done += 1
+    dt = time.perf_counter() - t0
+    res = {"value": units / dt, "unit": "Fock amplitudes/s", "cores": threads, "kind": "oracle",
+           "sample": ("%d of %d samples, 300 seeded outputs each" if big else "%d of %d samples, every output") % (
+               done, wl.B) + ", FP64 Ryser, OpenMP", "seconds": round(dt, 2), "max_abs_dp": worst}
+    if gp is not None:
+        w = wl.loss_w.astype(np.float64)
+        basis = O.fock_basis(wl.m, int(wl.n[0]))
+        G = gU.cpu().numpy().astype(np.complex128)
+        got, fd = [], []
+        h = 1e-6
+        for j in (3, 17):
+            V = np.zeros((wl.m, wl.m), np.complex128)
+            V[j, :] = rng.standard_normal(wl.m) + 1j * rng.standard_normal(wl.m)
+            sel = basis[:, j] >= 1
+            Lp = float(w[sel] @ O.probabilities(U64[0] + h * V, wl.occ[0], basis[sel]))
+            Lm = float(w[sel] @ O.probabilities(U64[0] - h * V, wl.occ[0], basis[sel]))
+            fd.append((Lp - Lm) / (2 * h))
+            got.append(float(np.real(np.sum(np.conj(G[0]) * V))))
+        res["grad_rel_err"] = float(np.linalg.norm(np.array(got) - fd) / np.linalg.norm(fd))
+        res["grad_check"] = "sample 0, two row directions, FP64 central differences of the oracle loss"
+    return res
 
 
 # Workloads of the measurement, encoding and kernel extensions (one line each).

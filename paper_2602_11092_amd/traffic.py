@@ -14,12 +14,12 @@ import os
 import sqlite3
 import sys
 
-# kernel symbol fragment -> C-ABI entry point that launches it
+# C-ABI entry point -> symbol fragments of the kernels it may launch
 KERNELS = {
-    "fused_fwd_kernel": "fock_probs",
-    "fused_bwd_kernel": "fock_probs_backward",
-    "mesh_factors_kernel": "mesh_to_unitary",
-    "mesh_bwd_sweep_kernel": "mesh_to_unitary_backward",
+    "fock_probs": ("fused_fwd_kernel", "fused_pairs_fwd_kernel"),
+    "fock_probs_backward": ("fused_bwd_kernel",),
+    "mesh_to_unitary": ("mesh_factors_kernel",),
+    "mesh_to_unitary_backward": ("mesh_bwd_sweep_kernel",),
 }
 PROBE = "neg_kernel"
 PROBE_BYTES = float(1 << 30)
@@ -55,10 +55,10 @@ def main(fetch_db, write_db, out_dir, command):
     kf = PROBE_BYTES / (probe_f[0][0] * 1024.0)
     kw = PROBE_BYTES / (probe_w[0][0] * 1024.0)
     sha = sources_sha256(root)
-    for frag, entry in KERNELS.items():
+    for entry, frags in KERNELS.items():
         # the instance the timed step runs: the one with the most dispatches
         # (the autotuner launches the others a few times each)
-        fs = sorted(((k, v) for k, v in fetch.items() if frag in k), key=lambda kv: -kv[1][1])
+        fs = sorted(((k, v) for k, v in fetch.items() if any(f in k for f in frags)), key=lambda kv: -kv[1][1])
         ws = [(k, v) for k, v in write.items() if fs and k == fs[0][0]]
         if not fs or not ws:
             continue
