@@ -645,7 +645,7 @@ __global__ __launch_bounds__(BLOCK) void fused_bwd_kernel(int m, const LayerDev*
             // g_{n-1} replaces d_{n-1}; the top layer's column of G_U
 #pragma unroll
             for (int s = 0; s < OWN; ++s) {
-                const int tp = tid + s * BLOCK;
+                const int tp = fresh_v(tid) + s * BLOCK;
                 if (tp < Np) lds_st(kXAddr + 8u * (uint32_t)tp, acc[s]);
             }
             reduce_columns<BLOCK, MMAX>(h, m, Hw, GUacc + 8u * (uint32_t)((n - 1) * 32));
@@ -682,7 +682,7 @@ __global__ __launch_bounds__(BLOCK) void fused_bwd_kernel(int m, const LayerDev*
                     if (k >= 2) {
 #pragma unroll
                         for (int s = 0; s < OWN; ++s) {
-                            const int tp = tid + s * BLOCK;
+                            const int tp = fresh_v(tid) + s * BLOCK;
                             if (tp < Nkm1) lds_st(gkm1 + 8u * (uint32_t)tp, acc[s]);
                         }
                     }
@@ -694,7 +694,7 @@ __global__ __launch_bounds__(BLOCK) void fused_bwd_kernel(int m, const LayerDev*
                         pull<BLOCK, OWN, MMAX, false>(0, Nkm1, 0, m, rsk, gsk, gk, dkm1, acc, h);
 #pragma unroll
                         for (int s = 0; s < OWN; ++s) {
-                            const int tp = tid + s * BLOCK;
+                            const int tp = fresh_v(tid) + s * BLOCK;
                             if (tp < Nkm1) lds_st(gkm1 + 8u * (uint32_t)tp, acc[s]);
                         }
                     }
