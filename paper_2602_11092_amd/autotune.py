@@ -40,10 +40,11 @@ from . import _binding as B
 FORWARD_CANDIDATES = [(B.VARIANT_FUSED_PAIRS, 1024, 2), (B.VARIANT_FUSED_PAIRS, 1024, 4),
                       (B.VARIANT_FUSED_PAIRS, 1024, 8), (B.VARIANT_FUSED_PAIRS, 512, 4),
                       (B.VARIANT_FUSED, 256, 0), (B.VARIANT_FUSED, 512, 0), (B.VARIANT_FUSED, 1024, 0),
-                      (B.VARIANT_LAYERED, 128, 0), (B.VARIANT_LAYERED, 256, 0), (B.VARIANT_LAYERED, 512, 0)]
+                      (B.VARIANT_LAYERED, 128, 0), (B.VARIANT_LAYERED, 256, 0), (B.VARIANT_LAYERED, 512, 0),
+                      (B.VARIANT_LAYERED, 1024, 0)]
 BACKWARD_CANDIDATES = [(B.VARIANT_FUSED, 256, 0), (B.VARIANT_FUSED, 512, 0), (B.VARIANT_FUSED, 768, 0),
                        (B.VARIANT_FUSED, 1024, 0), (B.VARIANT_LAYERED, 128, 0), (B.VARIANT_LAYERED, 256, 0),
-                       (B.VARIANT_LAYERED, 512, 0)]
+                       (B.VARIANT_LAYERED, 512, 0), (B.VARIANT_LAYERED, 1024, 0)]
 REFERENCE = (B.VARIANT_LAYERED, 256, 0)
 _BACKWARD = (B.OP_AMPLITUDES_BACKWARD, B.OP_PROBS_BACKWARD, B.OP_MODE_EXPECTATIONS_BACKWARD,
              B.OP_THRESHOLD_PROBS_BACKWARD)

@@ -20,17 +20,19 @@ namespace {
 struct Shape {
     int SG;    // samples per group (lanes sharing a state)
     int NGRP;  // number of groups
-    int GX;    // blocks along the state axis in the pull launches (about 2048 blocks in all)
+    int GX;    // blocks along the state axis in the pull launches
 };
 
 Shape shape_of(const slos_batch_s& Bt) {
     int sg = 1;
     while (sg < Bt.B && sg < 64) sg <<= 1;
     const int ngrp = (Bt.B + sg - 1) / sg;
-    // no more blocks than the largest pull range needs (256 threads each)
+    // no more blocks than the largest pull range needs (256 threads each); with
+    // one group, 1024 blocks (four per CU, what the pull's LDS allows) keep 4
+    // waves per SIMD waiting on the gathers
     const int64_t Nmax = Bt.n_max >= 1 ? Bt.plan->N[Bt.n_max - 1] : 1;
     const int64_t need = (Nmax * sg + 255) / 256;
-    const int cap = std::max(8, std::min(512, 2048 / ngrp));
+    const int cap = std::max(8, std::min(1024, 2048 / ngrp));
     return Shape{sg, ngrp, (int)std::max<int64_t>(1, std::min<int64_t>(need, cap))};
 }
 
@@ -41,6 +43,7 @@ struct Layout {
     size_t store_off[kMaxPhotons + 1];  // bwd: layer k at store_off[k] (k = 1..n_max-1)
     size_t buf0, buf1;                  // fwd: ping-pong layers; bwd: g ping-pong
     size_t partial;                     // bwd: [n_max][NGRP][GX][SG][32] float2
+    size_t col;                         // bwd: [B][kMaxPhotons][32] float2, G_U[:, i_k] per layer
     size_t total;
 };
 
@@ -66,6 +69,8 @@ Layout layout_of(const slos_batch_s& Bt, bool backward) {
     off += align256((size_t)maxN * per_state);
     L.partial = off;
     if (backward) off += align256((size_t)std::max(Bt.n_max, 1) * sh.NGRP * sh.GX * sh.SG * 32 * sizeof(float2));
+    L.col = off;
+    if (backward) off += align256((size_t)Bt.B * kMaxPhotons * 32 * sizeof(float2));
     L.total = off;
     return L;
 }
@@ -242,36 +247,54 @@ __global__ __launch_bounds__(BLOCK) void layered_pull_kernel(int m, const LayerD
     }
 }
 
-// G_U[b][j][i] = sum over photon layers k with i_k = i of the partial sums.
-// One block per sample: for each layer, the 256 threads add the GX block
-// partials of each mode in 8 interleaved slices (coalesced over the modes),
-// then the slices are combined in a fixed order.
-__global__ __launch_bounds__(256) void layered_final_kernel(int m, BatchDev Bt, const float2* __restrict__ partial,
-                                                            float2* __restrict__ gU, int SG, int NGRP, int GX) {
-    __shared__ float2 part[8][32];
-    __shared__ float2 col[kMaxPhotons][32];
+// Column i_k of G_U for sample b from layer k's block partials.  One block
+// per (sample, layer): 32 slices of 32 lanes (one lane per mode) each add
+// every 32nd block partial with eight independent accumulators, then the
+// slices are added in order.  The order is fixed, so results are
+// reproducible; the loads of a slice are all independent.
+__global__ __launch_bounds__(1024) void layered_reduce_kernel(BatchDev Bt, const float2* __restrict__ partial,
+                                                              float2* __restrict__ col, int SG, int NGRP, int GX) {
+    __shared__ float2 part[32][33];
     const int b = blockIdx.x;
+    const int k = blockIdx.y + 1;
+    if (k > Bt.n[b]) return;  // uniform over the block
     const int g = b / SG, bl = b % SG;
+    const int tid = threadIdx.x, j = tid & 31, sl = tid >> 5;
+    const float2* src = partial + (((size_t)(k - 1) * NGRP + g) * GX * SG + bl) * 32 + j;
+    const size_t xs = (size_t)SG * 32;  // stride between consecutive block partials
+    float2 a[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) a[q] = c_zero();
+    int x = sl;
+    for (; x + 7 * 32 < GX; x += 8 * 32) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) a[q] = c_add(a[q], src[(size_t)(x + q * 32) * xs]);
+    }
+    for (; x < GX; x += 32) a[0] = c_add(a[0], src[(size_t)x * xs]);
+    float2 v = c_zero();
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v = c_add(v, a[q]);
+    part[sl][j] = v;
+    __syncthreads();
+    if (tid < 32) {
+        float2 sum = c_zero();
+        for (int q = 0; q < 32; ++q) sum = c_add(sum, part[q][tid]);
+        col[((size_t)b * kMaxPhotons + k - 1) * 32 + tid] = sum;
+    }
+}
+
+// G_U[b][j][i] = sum over photon layers k with i_k = i of column k, in k order.
+__global__ __launch_bounds__(256) void layered_final_kernel(int m, BatchDev Bt, const float2* __restrict__ col,
+                                                            float2* __restrict__ gU) {
+    const int b = blockIdx.x;
     const int n_b = Bt.n[b];
     const int32_t* modes = Bt.modes + (size_t)b * kMaxPhotons;
-    const int tid = threadIdx.x, j = tid & 31, sl = tid >> 5;
-    for (int k = 1; k <= n_b; ++k) {
-        float2 v = c_zero();
-        for (int x = sl; x < GX; x += 8) v = c_add(v, partial[((((size_t)(k - 1) * NGRP + g) * GX + x) * SG + bl) * 32 + j]);
-        part[sl][j] = v;
-        __syncthreads();
-        if (tid < 32) {
-            float2 sum = c_zero();
-            for (int q = 0; q < 8; ++q) sum = c_add(sum, part[q][tid]);
-            col[k - 1][tid] = sum;
-        }
-        __syncthreads();
-    }
-    for (int q = tid; q < m * m; q += blockDim.x) {
+    const float2* cb = col + (size_t)b * kMaxPhotons * 32;
+    for (int q = threadIdx.x; q < m * m; q += blockDim.x) {
         const int jj = q / m, i = q % m;
         float2 v = c_zero();
         for (int k = 1; k <= n_b; ++k)
-            if (modes[k - 1] == i) v = c_add(v, col[k - 1][jj]);
+            if (modes[k - 1] == i) v = c_add(v, cb[(k - 1) * 32 + jj]);
         gU[(size_t)b * m * m + q] = v;
     }
 }
@@ -382,8 +405,14 @@ int launch_layered_bwd(const slos_batch_s& Bt, int block, const float2* U, const
     for (int k = Bt.n_max; k >= 1; --k) {
         float2* gk = gbuf[(Bt.n_max - k) & 1];
         float2* gkm1 = gbuf[(Bt.n_max - k + 1) & 1];
-        rc = launch_layer(Bt, block, U, k, kSeed, store(k - 1), gk, nullptr, gin, probs, stream);
-        if (rc != SLOS_OK) return rc;
+        // the seed writes g_k of the samples whose top layer is k; with none, g_k
+        // is the previous pull's output as it stands
+        bool any_top = false;
+        for (int b = 0; b < Bt.B && !any_top; ++b) any_top = (Bt.n_host[b] == k);
+        if (any_top) {
+            rc = launch_layer(Bt, block, U, k, kSeed, store(k - 1), gk, nullptr, gin, probs, stream);
+            if (rc != SLOS_OK) return rc;
+        }
         const float2* dkm1 = store(k - 1);
         void* args[] = {(void*)&m, (void*)&Ls, (void*)&Bt.dev, (void*)&U, (void*)&k, (void*)&gk,
                         (void*)&gkm1, (void*)&dkm1, (void*)&partial, (void*)&SG, (void*)&NGRP};
@@ -392,7 +421,13 @@ int launch_layered_bwd(const slos_batch_s& Bt, int block, const float2* U, const
         if (e != hipSuccess) return fail(SLOS_EHIP, std::string("layered pull launch: ") + hipGetErrorString(e));
     }
     int GX = sh.GX;
-    void* args[] = {(void*)&m, (void*)&Bt.dev, (void*)&partial, (void*)&gU, (void*)&SG, (void*)&NGRP, (void*)&GX};
+    float2* col = (float2*)(base + L.col);
+    {
+        void* args[] = {(void*)&Bt.dev, (void*)&partial, (void*)&col, (void*)&SG, (void*)&NGRP, (void*)&GX};
+        hipError_t e = hipLaunchKernel((void*)&layered_reduce_kernel, dim3(Bt.B, std::max(Bt.n_max, 1)), dim3(1024), args, 0, stream);
+        if (e != hipSuccess) return fail(SLOS_EHIP, std::string("layered reduce launch: ") + hipGetErrorString(e));
+    }
+    void* args[] = {(void*)&m, (void*)&Bt.dev, (void*)&col, (void*)&gU};
     hipError_t e = hipLaunchKernel((void*)&layered_final_kernel, dim3(Bt.B), dim3(256), args, 0, stream);
     if (e != hipSuccess) return fail(SLOS_EHIP, std::string("layered final launch: ") + hipGetErrorString(e));
     return SLOS_OK;
