@@ -622,7 +622,9 @@ def bench_extension(args, dev):
         oracle_one = lambda b: O.threshold_probs(Uh[b], occ[b])
         toff = batch.threshold_offsets
         check = lambda b, r: float(np.abs(out[toff[b]:toff[b + 1]].cpu().numpy() - r).max())
-        cfg = "probabilities, then per-pattern gather"
+        cfg = ("fused forward summing whole click patterns in LDS (p never written)"
+               if batch.get_config(B.OP_THRESHOLD_PROBS)[0] == B.VARIANT_FUSED
+               else "probabilities, then per-pattern gather")
     elif name.startswith("sample"):
         S = 1024
         batch = B.Batch(B.Plan(m, n), occ)

@@ -146,30 +146,38 @@ __device__ __forceinline__ void gather_groups(__amdgpu_buffer_rsrc_t r, const ui
     gather_loaded<SU, SP, NGX>(e, g0, k, pb, acc);
 }
 
-// acc[u] = d_k[t0 + u*BLOCK] for u < SU, pulled from layer k-1 at LDS address
-// pb with coefficients U[j][i_k] from the coefficient column.  Lanes past
-// tlim compute the value of state tlim-1 (callers do not store it).
-template <int BLOCK, int SU, int SPR, int NG>
-__device__ __forceinline__ void gather_states(const LayerDev& L, int k, int t0, int tlim, uint32_t pb,
-                                              float2 (&acc)[SU]) {
+// acc[u] = d_k of the state whose table row starts at byte vo[u] (row * 16),
+// pulled from layer k-1 at LDS address pb with coefficients U[j][i_k] from
+// the coefficient column.  With k = 1 the row is the state itself.
+template <int SU, int SPR, int NG>
+__device__ __forceinline__ void gather_rows(const LayerDev& L, int k, const uint32_t (&vo)[SU], uint32_t pb,
+                                            float2 (&acc)[SU]) {
     constexpr int SP = SPR < SU ? SPR : SU;
     static_assert(SU % SP == 0, "states must split evenly into gather sets");
 #pragma unroll
     for (int u = 0; u < SU; ++u) acc[u] = c_zero();
     if (k == 1) {  // d_1[t] = U[t][i_1]
 #pragma unroll
-        for (int u = 0; u < SU; ++u) acc[u] = lds_ld(kUcolAddr + 8u * (uint32_t)min(t0 + u * BLOCK, tlim - 1));
+        for (int u = 0; u < SU; ++u) acc[u] = lds_ld(kUcolAddr + (vo[u] >> 1));
         return;
     }
     const uint32_t gstride = (uint32_t)L.N * 16u;
     const __amdgpu_buffer_rsrc_t r = buf_rsrc(L.predv, (uint32_t)L.ngrp * gstride);
-    uint32_t vo[SU];
-#pragma unroll
-    for (int u = 0; u < SU; ++u) vo[u] = (uint32_t)min(t0 + u * BLOCK, tlim - 1) * 16u;
     int g0 = 0;
     if (NG >= 2)
         for (; g0 + 2 <= L.ngrp; g0 += 2) gather_groups<SU, SP, 2>(r, vo, gstride, g0, k, pb, acc);
     for (; g0 < L.ngrp; ++g0) gather_groups<SU, SP, 1>(r, vo, gstride, g0, k, pb, acc);
+}
+
+// acc[u] = d_k of table row t0 + u*BLOCK for u < SU.  Lanes past tlim
+// compute the value of row tlim-1 (callers do not store it).
+template <int BLOCK, int SU, int SPR, int NG>
+__device__ __forceinline__ void gather_states(const LayerDev& L, int k, int t0, int tlim, uint32_t pb,
+                                              float2 (&acc)[SU]) {
+    uint32_t vo[SU];
+#pragma unroll
+    for (int u = 0; u < SU; ++u) vo[u] = (uint32_t)min(t0 + u * BLOCK, tlim - 1) * 16u;
+    gather_rows<SU, SPR, NG>(L, k, vo, pb, acc);
 }
 
 // One layer of the recursion, LDS to LDS, SU states per thread per iteration.
@@ -243,12 +251,19 @@ __device__ __forceinline__ void photons_into_lds(const LayerDev& L, int k, int t
 // of the [m][BLOCK] array after the state buffers, so no atomics), and the
 // columns are summed once per sample; p is never written.  3: the same with
 // one count per occupied mode, sum_t [t_j > 0] p_t (threshold detectors).
+// 4: threshold-detector click probabilities, out[thr_off_b + q] = sum of p
+// over click pattern q's states: the last layer is taken in runs of whole
+// patterns, state by state in pattern order (the plan keeps its predecessor
+// rows and norms in that order as well), p into an LDS float array, then one
+// thread per pattern adds its states' p in ascending state order; p is never
+// written.
 template <int BLOCK, int EPI>
 __global__ __launch_bounds__(BLOCK) void fused_fwd_kernel(int m, const LayerDev* __restrict__ Ls, BatchDev Bt,
                                                           const float2* __restrict__ U, void* __restrict__ out,
                                                           int S) {
     constexpr bool PROBS = EPI >= 1;
-    constexpr bool EXPECT = EPI >= 2;  // 2: per photon (<n_j>), 3: per occupied mode (clicks)
+    constexpr bool EXPECT = EPI == 2 || EPI == 3;  // 2: per photon (<n_j>), 3: per occupied mode (clicks)
+    constexpr bool THR = EPI == 4;
     extern __shared__ float2 lds[];  // ucol at kUcolAddr, photon layers from kXAddr, accumulators after them
     const int tid = threadIdx.x;
     const uint32_t accb = kXAddr + 8u * (uint32_t)S;
@@ -263,6 +278,8 @@ __global__ __launch_bounds__(BLOCK) void fused_fwd_kernel(int m, const LayerDev*
         if (n == 0) {
             if (EXPECT) {
                 if (tid < m) ((float*)out)[(size_t)b * m + tid] = 0.f;  // the vacuum has no photons
+            } else if (THR) {
+                if (tid == 0) ((float*)out)[ldc(Bt.thr_off + b)] = 1.f;  // the empty pattern
             } else if (tid == 0) {
                 if (PROBS) ((float*)out)[off] = 1.f;
                 else ((float2*)out)[off] = make_float2(1.f, 0.f);
@@ -282,6 +299,43 @@ __global__ __launch_bounds__(BLOCK) void fused_fwd_kernel(int m, const LayerDev*
                 const uint32_t prev = kXAddr + 8u * (uint32_t)((((n - k) & 1) == 0) ? 0 : S - Np);
                 const uint32_t cur = kXAddr + 8u * (uint32_t)((((n - 1 - k) & 1) == 0) ? 0 : S - N);
                 layer_into_lds<BLOCK, kLU>(L, k, prev, cur);
+            } else if (THR) {
+                const int32_t* tptr = ldc(&Ls[k].thr_ptr);
+                const int32_t* tch = ldc(&Ls[k].thr_chunk);
+                const int nch = ldc(&Ls[k].thr_nchunk);
+                float* ob = (float*)out + ldc(Bt.thr_off + b);
+                // the tables in pattern order (with one photon that is the state order
+                // itself, which the k = 1 gather assumes)
+                LayerDev Lp = L;
+                Lp.predv = ldc(&Ls[k].thr_predv);
+                const __amdgpu_buffer_rsrc_t rn = buf_rsrc(ldc(&Ls[k].thr_nrm), (uint32_t)N * 4u);
+                for (int r = 0; r < nch; ++r) {
+                    const int q0 = ldc(tch + r), q1 = ldc(tch + r + 1);
+                    const int P0 = ldc(tptr + q0), P1 = ldc(tptr + q1);
+                    for (int s0 = P0 + tid; s0 < P1; s0 += BLOCK * kLU) {
+                        float c[kLU];
+#pragma unroll
+                        for (int u = 0; u < kLU; ++u)
+                            c[u] = buf_ldf(rn, (uint32_t)min(s0 + u * BLOCK, P1 - 1) * 4u, 0) * innorm;
+                        float2 acc[kLU];
+                        gather_states<BLOCK, kLU, kLP, 2>(Lp, k, s0, P1, kXAddr, acc);
+#pragma unroll
+                        for (int u = 0; u < kLU; ++u) {
+                            const int sp = s0 + u * BLOCK;
+                            if (sp < P1)
+                                lds_stf(accb + 4u * (uint32_t)(sp - P0),
+                                        c[u] * c[u] * (acc[u].x * acc[u].x + acc[u].y * acc[u].y));
+                        }
+                    }
+                    __syncthreads();
+                    for (int q = q0 + tid; q < q1; q += BLOCK) {
+                        const int lo = ldg(tptr + q) - P0, hi = ldg(tptr + q + 1) - P0;
+                        float v = 0.f;
+                        for (int i = lo; i < hi; ++i) v += lds_ldf(accb + 4u * (uint32_t)i);
+                        ob[q] = v;
+                    }
+                    __syncthreads();  // before the next run overwrites the array
+                }
             } else {
                 const __amdgpu_buffer_rsrc_t rn = buf_rsrc(L.nrm, (uint32_t)N * 4u);
                 const __amdgpu_buffer_rsrc_t ro =
@@ -757,7 +811,8 @@ void* fwd_fn(int epi) {
     return epi == 0   ? (void*)&fused_fwd_kernel<BLOCK, 0>
            : epi == 1 ? (void*)&fused_fwd_kernel<BLOCK, 1>
            : epi == 2 ? (void*)&fused_fwd_kernel<BLOCK, 2>
-                      : (void*)&fused_fwd_kernel<BLOCK, 3>;
+           : epi == 3 ? (void*)&fused_fwd_kernel<BLOCK, 3>
+                      : (void*)&fused_fwd_kernel<BLOCK, 4>;
 }
 
 void* pick_fwd(int block, int epi) {
@@ -770,10 +825,11 @@ void* pick_fwd(int block, int epi) {
 }
 
 // LDS bytes of the fused forward: the coefficient column, the state
-// buffers and, for the expectation epilogue, [m][block] float accumulators
-size_t fwd_lds_for(const slos_plan_s& P, int n_max, int block, bool expect) {
+// buffers and, for the expectation epilogues, [m][block] float
+// accumulators; for the click-pattern epilogue, a run's probabilities
+size_t fwd_lds_for(const slos_plan_s& P, int n_max, int block, bool expect, bool thr = false) {
     return (size_t)(lds_fwd_states(P, n_max) + kUcolSlots) * sizeof(float2) +
-           (expect ? (size_t)P.m * block * sizeof(float) : 0);
+           (expect ? (size_t)P.m * block * sizeof(float) : 0) + (thr ? (size_t)kThrChunkStates * sizeof(float) : 0);
 }
 
 int mmax_for(int m) { return m <= 8 ? 8 : m <= 12 ? 12 : m <= 16 ? 16 : m <= 20 ? 20 : m <= 24 ? 24 : 32; }
@@ -898,14 +954,23 @@ int fused_default_block(const slos_plan_s& P, int n_max, bool backward) {
     return Nbig >= 8192 ? 1024 : 256;
 }
 
+bool fused_threshold_supported(const slos_plan_s& P, int n_max, int block) {
+    return fused_fwd_supported(P, n_max, block, nullptr) && P.layers.size() > (size_t)n_max &&
+           (n_max == 0 || P.layers[n_max].thr_chunk != nullptr) &&
+           fwd_lds_for(P, n_max, block, false, true) <= P.max_lds;
+}
+
 int launch_fused_fwd(const slos_batch_s& Bt, int block, const float2* U, void* out, int epi,
                      hipStream_t stream) {
     const slos_plan_s& P = *Bt.plan;
     std::string why;
-    if (!fused_fwd_supported(P, Bt.n_max, block, &why, epi >= 2))
+    const bool expect = epi == 2 || epi == 3, thr = epi == 4;
+    if (!fused_fwd_supported(P, Bt.n_max, block, &why, expect))
         return fail(SLOS_EUNSUPPORTED, "fused forward: " + why);
+    if (thr && !fused_threshold_supported(P, Bt.n_max, block))
+        return fail(SLOS_EUNSUPPORTED, "fused forward: click-pattern runs do not fit in LDS");
     void* fn = pick_fwd(block, epi);
-    const size_t lds = fwd_lds_for(P, Bt.n_max, block, epi >= 2);
+    const size_t lds = fwd_lds_for(P, Bt.n_max, block, expect, thr);
     hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     const int grid = grid_for(P, fn, block, lds, Bt.B);
     const int S = (int)lds_fwd_states(P, Bt.n_max);

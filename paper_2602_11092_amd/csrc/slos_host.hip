@@ -177,6 +177,9 @@ struct HostLayer {
     std::vector<int32_t> pred, succ, minoff;
     std::vector<float> nrm;
     std::vector<int32_t> thr_ptr, thr_idx;  // click-pattern tables (SLOS_PLAN_THRESHOLD)
+    std::vector<int32_t> thr_chunk;         // runs of whole patterns of at most kThrChunkStates states
+    std::vector<int32_t> thr_pred;          // packed pred rows in click-pattern order
+    std::vector<float> thr_nrm;             // nrm in click-pattern order
 };
 
 // Transition graph of layer k (k >= 1): predecessor entries for every
@@ -446,7 +449,28 @@ extern "C" int slos_plan_create(int m, int n_max, int flags, slos_plan_t* out) {
             }
         H[k].pred.swap(packed);
         shifts[k] = shift;
-        if (flags & SLOS_PLAN_THRESHOLD) build_threshold(m, k, C[k], Nk, H[k].thr_ptr, H[k].thr_idx);
+        if (flags & SLOS_PLAN_THRESHOLD) {
+            build_threshold(m, k, C[k], Nk, H[k].thr_ptr, H[k].thr_idx);
+            // greedy runs of whole patterns (a pattern holds at most C(15, 7) states, fewer than a run)
+            const int32_t Qk = (int32_t)H[k].thr_ptr.size() - 1;
+            for (int32_t q0 = 0; q0 < Qk;) {
+                H[k].thr_chunk.push_back(q0);
+                int32_t q1 = q0 + 1;
+                while (q1 < Qk && H[k].thr_ptr[q1 + 1] - H[k].thr_ptr[q0] <= kThrChunkStates) ++q1;
+                q0 = q1;
+            }
+            H[k].thr_chunk.push_back(Qk);
+            // the predecessor rows and norms in pattern order
+            H[k].thr_pred.resize(H[k].pred.size());
+            H[k].thr_nrm.resize((size_t)Nk);
+            for (int64_t sp = 0; sp < Nk; ++sp) {
+                const int64_t t = H[k].thr_idx[(size_t)sp];
+                H[k].thr_nrm[(size_t)sp] = H[k].nrm[(size_t)t];
+                for (int g = 0; g < ngrp; ++g)
+                    for (int q = 0; q < 4; ++q)
+                        H[k].thr_pred[((size_t)g * Nk + sp) * 4 + q] = H[k].pred[((size_t)g * Nk + t) * 4 + q];
+            }
+        }
         // device successors: groups of four modes, [j/4][t'][4], byte offsets rank * 8
         if (want_succ) {
             const int64_t Nkm1 = P->N[k - 1];
@@ -463,7 +487,7 @@ extern "C" int slos_plan_create(int m, int n_max, int flags, slos_plan_t* out) {
     // one device allocation for every table
     size_t total = align256(sizeof(LayerDev) * (n_max + 1));
     std::vector<size_t> o_pred(n_max + 1), o_succ(n_max + 1), o_nrm(n_max + 1), o_min(n_max + 1);
-    std::vector<size_t> o_tp(n_max + 1), o_ti(n_max + 1);
+    std::vector<size_t> o_tp(n_max + 1), o_ti(n_max + 1), o_tc(n_max + 1), o_tpr(n_max + 1), o_tnr(n_max + 1);
     for (int k = 1; k <= n_max; ++k) {
         o_pred[k] = total; total += align256(H[k].pred.size() * 4);
         o_succ[k] = total; total += align256(H[k].succ.size() * 4);
@@ -471,6 +495,9 @@ extern "C" int slos_plan_create(int m, int n_max, int flags, slos_plan_t* out) {
         o_min[k] = total;  total += align256(H[k].minoff.size() * 4);
         o_tp[k] = total;   total += align256(H[k].thr_ptr.size() * 4);
         o_ti[k] = total;   total += align256(H[k].thr_idx.size() * 4);
+        o_tc[k] = total;   total += align256(H[k].thr_chunk.size() * 4);
+        o_tpr[k] = total;  total += align256(H[k].thr_pred.size() * 4);
+        o_tnr[k] = total;  total += align256(H[k].thr_nrm.size() * 4);
     }
     if (hipMalloc(&P->dmem, total) != hipSuccess) {
         delete P;
@@ -495,11 +522,21 @@ extern "C" int slos_plan_create(int m, int n_max, int flags, slos_plan_t* out) {
         L.thr_ptr = thr ? (const int32_t*)(base + o_tp[k]) : nullptr;
         L.thr_idx = thr ? (const int32_t*)(base + o_ti[k]) : nullptr;
         L.Q = thr ? (int64_t)H[k].thr_ptr.size() - 1 : 0;
+        L.thr_chunk = thr ? (const int32_t*)(base + o_tc[k]) : nullptr;
+        L.thr_nchunk = thr ? (int32_t)H[k].thr_chunk.size() - 1 : 0;
+        L.thr_predv = thr ? (const uint4*)(base + o_tpr[k]) : nullptr;
+        L.thr_nrm = thr ? (const float*)(base + o_tnr[k]) : nullptr;
         e = hipMemcpy(base + o_pred[k], H[k].pred.data(), H[k].pred.size() * 4, hipMemcpyHostToDevice);
         if (e == hipSuccess && thr)
             e = hipMemcpy(base + o_tp[k], H[k].thr_ptr.data(), H[k].thr_ptr.size() * 4, hipMemcpyHostToDevice);
         if (e == hipSuccess && thr)
             e = hipMemcpy(base + o_ti[k], H[k].thr_idx.data(), H[k].thr_idx.size() * 4, hipMemcpyHostToDevice);
+        if (e == hipSuccess && thr)
+            e = hipMemcpy(base + o_tc[k], H[k].thr_chunk.data(), H[k].thr_chunk.size() * 4, hipMemcpyHostToDevice);
+        if (e == hipSuccess && thr)
+            e = hipMemcpy(base + o_tpr[k], H[k].thr_pred.data(), H[k].thr_pred.size() * 4, hipMemcpyHostToDevice);
+        if (e == hipSuccess && thr)
+            e = hipMemcpy(base + o_tnr[k], H[k].thr_nrm.data(), H[k].thr_nrm.size() * 4, hipMemcpyHostToDevice);
         if (e == hipSuccess && want_succ)
             e = hipMemcpy(base + o_succ[k], H[k].succ.data(), H[k].succ.size() * 4, hipMemcpyHostToDevice);
         if (e == hipSuccess)
@@ -801,7 +838,8 @@ int run_expect(const slos_batch_s& Bt, int op, int v, int blk, const float* U, c
 
 // Threshold-detector click probabilities and their adjoint: p (or dL/dp)
 // lives at the start of the workspace; the forward gathers each pattern's
-// states, the adjoint scatters dL/dP back onto them.
+// states (inside the fused forward where its LDS holds a run of patterns),
+// the adjoint scatters dL/dP back onto them.
 int run_threshold(const slos_batch_s& Bt, int op, int v, int blk, const float* U, const void* gin, void* out,
                   void* ws, size_t ws_bytes, hipStream_t s, const std::string& nm) {
     if (!(Bt.plan->flags & SLOS_PLAN_THRESHOLD))
@@ -816,6 +854,9 @@ int run_threshold(const slos_batch_s& Bt, int op, int v, int blk, const float* U
     void* rest = (char*)ws + head;
     int rc;
     if (!bwd) {
+        // the fused variant sums the patterns inside the forward (p never leaves LDS)
+        if (v == SLOS_VARIANT_FUSED && fused_threshold_supported(*Bt.plan, Bt.n_max, blk))
+            return launch_fused_fwd(Bt, blk, (const float2*)U, out, 4, s);
         rc = v == SLOS_VARIANT_FUSED_PAIRS ? launch_fused_pairs_fwd(Bt, blk, Bt.cfg[op].tile, (const float2*)U, pv, true, s)
              : fused                        ? launch_fused_fwd(Bt, blk, (const float2*)U, pv, 1, s)
                                             : launch_layered_fwd(Bt, blk, (const float2*)U, pv, true, rest, s);

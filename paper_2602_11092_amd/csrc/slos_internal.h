@@ -55,7 +55,19 @@ struct LayerDev {
     const int32_t* thr_ptr; // [Q + 1]
     const int32_t* thr_idx; // [N]
     int64_t Q;              // number of click patterns of k photons
+    // the patterns cut into runs of whole patterns holding at most
+    // kThrChunkStates states: run r is patterns [thr_chunk[r], thr_chunk[r+1])
+    const int32_t* thr_chunk; // [thr_nchunk + 1]
+    int32_t thr_nchunk;
+    // predv and nrm with the states in click-pattern order (row s is state
+    // thr_idx[s]), so that a pass in that order loads them coalesced
+    const uint4* thr_predv;   // [ngrp][N]
+    const float* thr_nrm;     // [N]
 };
+
+// States per run of whole click patterns in the fused threshold epilogue
+// (their probabilities are staged in LDS as floats).
+constexpr int kThrChunkStates = 16384;
 
 // Per-sample description of a batch (device pointers).
 struct BatchDev {
@@ -115,6 +127,8 @@ size_t fused_fwd_lds_bytes(const slos_plan_s& P, int n_max);
 size_t fused_bwd_lds_bytes(const slos_plan_s& P, int n_max);
 // expect: the per-mode expectation epilogue (per-lane LDS accumulators)
 bool fused_fwd_supported(const slos_plan_s& P, int n_max, int block, std::string* why, bool expect = false);
+// whether the fused forward's click-pattern epilogue (epi 4) serves this plan and block
+bool fused_threshold_supported(const slos_plan_s& P, int n_max, int block);
 bool fused_bwd_supported(const slos_plan_s& P, int n_max, int block, std::string* why);
 int fused_default_block(const slos_plan_s& P, int n_max, bool backward);
 // epi: 0 amplitudes, 1 probabilities, 2 per-mode expectations, 3 per-mode

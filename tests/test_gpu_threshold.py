@@ -73,6 +73,70 @@ def test_threshold_probs_clements_m20_n5_b512(variant):
         assert np.abs(P[b] - O.threshold_probs(widen(U[b]), wl.occ[b])).max() <= T_TOL
 
 
+
+def _sequential_pattern_sums(m, n, p):
+    """FP32 sums of p [B, N] over each click pattern's states, added in
+    ascending state order one at a time (the order the library uses)."""
+    index = {c: i for i, c in enumerate(O.click_patterns(m, n))}
+    pat = np.array([index[tuple(int(j) for j in np.nonzero(t)[0])] for t in O.fock_basis(m, n)])
+    order = np.lexsort((np.arange(pat.size), pat))  # by pattern, then by state
+    counts = np.bincount(pat, minlength=len(index))
+    starts = np.concatenate([[0], np.cumsum(counts)[:-1]])
+    ps = p[:, order].astype(np.float32)
+    acc = np.zeros((p.shape[0], len(index)), dtype=np.float32)
+    for i in range(int(counts.max())):
+        take = i < counts
+        acc[:, take] += ps[:, starts[take] + i]
+    return acc
+
+
+@pytest.mark.parametrize("block", [256, 512, 1024])
+def test_fused_click_epilogue_equals_sums_of_the_probabilities(block):
+    # the fused forward sums each pattern inside the kernel, in runs of whole
+    # patterns staged in LDS (three runs at m = 20, n = 5); its result is the
+    # FP32 sum of the fused probability forward's own p in ascending state order
+    m, n, Bn = 20, 5, 24
+    rng = np.random.default_rng(55)
+    U = W.haar_unitaries(rng, Bn, m).astype(np.complex64)
+    occ = np.zeros((Bn, m), dtype=np.int32)
+    for b in range(Bn):
+        np.add.at(occ[b], rng.choice(m, size=n, replace=True), 1)
+    say("fused click epilogue block", block)
+    plan = B.Plan(m, n, threshold=True)
+    batch = B.Batch(plan, occ)
+    batch.set_config(B.OP_THRESHOLD_PROBS, B.VARIANT_FUSED, block)
+    batch.set_config(B.OP_PROBS, B.VARIANT_FUSED, block)
+    Ud = to_dev_c64(U)
+    P = B.fock_threshold_probs(batch, Ud)
+    p = B.fock_probs(batch, Ud)
+    torch.cuda.synchronize()
+    P = P.cpu().numpy().reshape(Bn, -1)
+    ref = _sequential_pattern_sums(m, n, p.cpu().numpy().reshape(Bn, -1))
+    assert np.array_equal(P, ref)
+    for b in (0, Bn - 1):
+        assert np.abs(P[b] - O.threshold_probs(widen(U[b]), occ[b])).max() <= T_TOL
+
+
+def test_fused_click_epilogue_edge_cases():
+    # the vacuum (the empty pattern, P = 1), one photon (m patterns, one state
+    # each) and a bunched input, with n_max = 1 and n_max = 3 plans
+    m = 7
+    rng = np.random.default_rng(8)
+    U = W.haar_unitaries(rng, 3, m).astype(np.complex64)
+    for occ in (np.array([[0] * m, [0, 1, 0, 0, 0, 0, 0], [0, 0, 0, 0, 0, 0, 1]], dtype=np.int32),
+                np.array([[0] * m, [3, 0, 0, 0, 0, 0, 0], [1, 0, 1, 0, 0, 1, 0]], dtype=np.int32)):
+        say("fused click epilogue edge", occ.sum(1).tolist())
+        batch = B.Batch(B.Plan(m, int(occ.sum(1).max()), threshold=True), occ)
+        batch.set_config(B.OP_THRESHOLD_PROBS, B.VARIANT_FUSED, 256)
+        P = B.fock_threshold_probs(batch, to_dev_c64(U))
+        torch.cuda.synchronize()
+        P = P.cpu().numpy()
+        toff = batch.threshold_offsets
+        assert P[toff[0]] == 1.0 and toff[1] - toff[0] == 1
+        for b in (1, 2):
+            ref = O.threshold_probs(widen(U[b]), occ[b])
+            assert np.abs(P[toff[b]:toff[b + 1]] - ref).max() <= T_TOL
+
 def test_threshold_on_unbunched_plan_places_the_restricted_probabilities():
     # on the unbunched space each state is its own click pattern
     m, n = 8, 4
