@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libslos_hip.so")
-SOURCES = ["slos_host.hip", "slos_fused.hip", "slos_fused2.hip", "slos_layered.hip", "slos_measure.hip", "fidelity.hip", "mesh.hip"]
+SOURCES = ["slos_host.hip", "slos_fused.hip", "slos_fused2.hip", "slos_fused_r.hip", "slos_layered.hip", "slos_measure.hip", "fidelity.hip", "mesh.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -412,7 +412,7 @@ __device__ __forceinline__ float2 coeff(uint32_t j) {
 // accumulators), and modes outside [jlo, jhi) are skipped by uniform tests.
 // The coefficient column conj(u_j) sits in registers for the whole call
 // where the workgroup shape leaves room (below 1024 threads).
-template <int BLOCK, int OWN, int MMAX, bool WITH_H = true>
+template <int BLOCK, int OWN, int MMAX, bool WITH_H = true, bool RS = false>
 __device__ __forceinline__ void pull(int lo, int hi, int jlo, int jhi, __amdgpu_buffer_rsrc_t rs, uint32_t gstride,
                                      uint32_t srcb, uint32_t Db, float2 (&acc)[OWN], float2 (&h)[MMAX]) {
     constexpr int NG = MMAX / 4;
@@ -446,7 +446,14 @@ __device__ __forceinline__ void pull(int lo, int hi, int jlo, int jhi, __amdgpu_
                 const int j = 4 * g + q;
                 // a select, not a branch, so that the group's gathers issue together
                 const bool jin = has(jbits, j);
-                const uint32_t so = (act & jin) ? comp(sv[g], q) : zoff;
+                uint32_t so;
+                if constexpr (RS) {
+                    // restricted spaces: a successor outside the space was never formed
+                    const uint32_t c = comp(sv[g], q);
+                    so = (act & jin & (c != kNoSuccessor)) ? c : zoff;
+                } else {
+                    so = (act & jin) ? comp(sv[g], q) : zoff;
+                }
                 const float2 gv = lds_ld(srcb + so);
                 c_fma_conj(acc[s], kCoefRegs ? cu[kCoefRegs ? j : 0] : coeff(j), gv);
                 if (WITH_H) c_fma_conj(h[j], dv, gv);
@@ -461,7 +468,7 @@ __device__ __forceinline__ void pull(int lo, int hi, int jlo, int jhi, __amdgpu_
 // the block's successor loads and gathers issue together, the mode's
 // successor column chosen by the load's scalar offset.  G_U shares go to the
 // same per-lane h[j] as the wide pull.
-template <int BLOCK, int OWN, int MMAX>
+template <int BLOCK, int OWN, int MMAX, bool RS = false>
 __device__ __forceinline__ void pull_narrow(int lo, int hi, int jlo, int jhi, __amdgpu_buffer_rsrc_t rs,
                                             uint32_t gstride, uint32_t srcb, uint32_t Db, float2 (&acc)[OWN],
                                             float2 (&h)[MMAX]) {
@@ -498,7 +505,9 @@ __device__ __forceinline__ void pull_narrow(int lo, int hi, int jlo, int jhi, __
 #pragma unroll
             for (int q = 0; q < SB; ++q) {
                 if (s0 + q >= OWN) continue;
-                const float2 g = lds_ld(srcb + (act[q] ? sv[q] : zoff));
+                float2 g;
+                if constexpr (RS) g = lds_ld(srcb + ((act[q] && sv[q] != kNoSuccessor) ? sv[q] : zoff));
+                else g = lds_ld(srcb + (act[q] ? sv[q] : zoff));
                 c_fma_conj(acc[s0 + q], uj, g);
                 c_fma_conj(h[j], dv[q], g);
             }
@@ -511,7 +520,7 @@ __device__ __forceinline__ void pull_narrow(int lo, int hi, int jlo, int jhi, __
 // loads overlap), its lanes stride over t', and lane 63 writes each mode's
 // fixed-order wave sum straight to GUcol[j] (one wave per mode, so no
 // cross-wave step).  Modes past m read the zero slot and are not written.
-template <int BLOCK, int MMAX>
+template <int BLOCK, int MMAX, bool RS = false>
 __device__ __forceinline__ void lower_h(int m, int Nkm1, __amdgpu_buffer_rsrc_t rs, uint32_t gstride, uint32_t gk,
                                         uint32_t Dk, uint32_t GUcol) {
     constexpr int NW = BLOCK / 64;
@@ -538,7 +547,8 @@ __device__ __forceinline__ void lower_h(int m, int Nkm1, __amdgpu_buffer_rsrc_t 
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 // past the layer or past m: the zero slot
-                const bool ok = tp < Nkm1 && wave + NW * r < m;
+                bool ok = tp < Nkm1 && wave + NW * r < m;
+                if constexpr (RS) ok = ok && sv[r][u] != kNoSuccessor;
                 const float2 g = lds_ld(ok ? gk + sv[r][u] : zero);
                 c_fma_conj(hj[r], dv, g);
             }
@@ -575,7 +585,9 @@ __device__ __forceinline__ void reduce_columns(const float2 (&h)[MMAX], int m, u
     }
 }
 
-template <int BLOCK, int OWN, int MMAX>
+// RS: plans of a restricted space (unbunched, dual-rail), whose successor
+// tables mark successors outside the space; those pairs read the zero slot.
+template <int BLOCK, int OWN, int MMAX, bool RS>
 __global__ __launch_bounds__(BLOCK) void fused_bwd_kernel(int m, const LayerDev* __restrict__ Ls, BatchDev Bt,
                                                           const float2* __restrict__ U,
                                                           const void* __restrict__ gin,
@@ -691,8 +703,9 @@ __global__ __launch_bounds__(BLOCK) void fused_bwd_kernel(int m, const LayerDev*
                 __syncthreads();
                 // {min(t') in [a, bb), j >= a} and {min(t') >= bb, a <= j < bb}
                 const uint32_t srcb = C - 8u * (uint32_t)base;
-                pull<BLOCK, OWN, MMAX>(ldc(Lp.minoff + a), ldc(Lp.minoff + bb), a, m, rs, gstride, srcb, D, acc, h);
-                pull_narrow<BLOCK, OWN, MMAX>(ldc(Lp.minoff + bb), Np, a, bb, rs, gstride, srcb, D, acc, h);
+                pull<BLOCK, OWN, MMAX, true, RS>(ldc(Lp.minoff + a), ldc(Lp.minoff + bb), a, m, rs, gstride, srcb, D,
+                                                acc, h);
+                pull_narrow<BLOCK, OWN, MMAX, RS>(ldc(Lp.minoff + bb), Np, a, bb, rs, gstride, srcb, D, acc, h);
                 __syncthreads();
                 a = bb;
             }
@@ -732,7 +745,7 @@ __global__ __launch_bounds__(BLOCK) void fused_bwd_kernel(int m, const LayerDev*
                     for (int s = 0; s < OWN; ++s) acc[s] = c_zero();
 #pragma unroll
                     for (int j = 0; j < MMAX; ++j) h[j] = c_zero();
-                    pull<BLOCK, OWN, MMAX, true>(0, Nkm1, 0, m, rsk, gsk, gk, dkm1, acc, h);
+                    pull<BLOCK, OWN, MMAX, true, RS>(0, Nkm1, 0, m, rsk, gsk, gk, dkm1, acc, h);
                     if (k >= 2) {
 #pragma unroll
                         for (int s = 0; s < OWN; ++s) {
@@ -745,14 +758,14 @@ __global__ __launch_bounds__(BLOCK) void fused_bwd_kernel(int m, const LayerDev*
                     if (k >= 2) {
 #pragma unroll
                         for (int s = 0; s < OWN; ++s) acc[s] = c_zero();
-                        pull<BLOCK, OWN, MMAX, false>(0, Nkm1, 0, m, rsk, gsk, gk, dkm1, acc, h);
+                        pull<BLOCK, OWN, MMAX, false, RS>(0, Nkm1, 0, m, rsk, gsk, gk, dkm1, acc, h);
 #pragma unroll
                         for (int s = 0; s < OWN; ++s) {
                             const int tp = fresh_v(tid) + s * BLOCK;
                             if (tp < Nkm1) lds_st(gkm1 + 8u * (uint32_t)tp, acc[s]);
                         }
                     }
-                    lower_h<BLOCK, MMAX>(m, Nkm1, rsk, gsk, gk, dkm1, GUacc + 8u * (uint32_t)((k - 1) * 32));
+                    lower_h<BLOCK, MMAX, RS>(m, Nkm1, rsk, gsk, gk, dkm1, GUacc + 8u * (uint32_t)((k - 1) * 32));
                 }
                 __syncthreads();
             }
@@ -772,6 +785,67 @@ __global__ __launch_bounds__(BLOCK) void fused_bwd_kernel(int m, const LayerDev*
 
 // ------------------------------------------------------------------ host side
 
+// photon-layer-(n-1) states per thread in the register-resident pulls
+int own_for(int block, int64_t Np) {
+    const int64_t need = (Np + block - 1) / block;
+    if (block == 256) return need <= 1 ? 1 : need <= 2 ? 2 : need <= 4 ? 4 : -1;
+    if (block == 512) return need <= 4 ? 4 : need <= 10 ? 10 : need <= 18 ? 18 : -1;
+    if (block == 768) return need <= 12 ? 12 : -1;
+    if (block == 1024) return need <= 10 ? 10 : -1;
+    return -1;
+}
+
+int mmax_for(int m) { return m <= 8 ? 8 : m <= 12 ? 12 : m <= 16 ? 16 : m <= 20 ? 20 : m <= 24 ? 24 : 32; }
+
+template <int BLOCK, int OWN, bool R>
+void* bwd_by_m(int mm) {
+    if constexpr (BLOCK >= 768) {
+        if (mm > 20) return nullptr;  // h and acc do not fit the registers of 12 or 16 waves
+    }
+    switch (mm) {
+        case 8: return (void*)&fused_bwd_kernel<BLOCK, OWN, 8, R>;
+        case 12: return (void*)&fused_bwd_kernel<BLOCK, OWN, 12, R>;
+        case 16: return (void*)&fused_bwd_kernel<BLOCK, OWN, 16, R>;
+        case 20: return (void*)&fused_bwd_kernel<BLOCK, OWN, 20, R>;
+        case 24:
+            if constexpr (BLOCK < 768) return (void*)&fused_bwd_kernel<BLOCK, OWN, 24, R>;
+            return nullptr;
+        case 32:
+            // h and acc do not fit the registers; no restricted instances at 32 modes
+            if constexpr (OWN <= 10 && BLOCK < 768 && !R) return (void*)&fused_bwd_kernel<BLOCK, OWN, 32, R>;
+            return nullptr;
+    }
+    return nullptr;
+}
+
+#ifdef SLOS_FUSED_RESTRICTED_INSTANCES
+}  // namespace
+
+// The adjoint instances for restricted spaces (workgroups of 256 and 512,
+// at most 24 modes); this translation unit holds only them.
+void* pick_bwd_restricted(int block, int m, int64_t Np) {
+    const int own = own_for(block, Np);
+    const int mm = mmax_for(m);
+    if (mm > 24) return nullptr;
+    if (block == 256) {
+        switch (own) {
+            case 1: return bwd_by_m<256, 1, true>(mm);
+            case 2: return bwd_by_m<256, 2, true>(mm);
+            case 4: return bwd_by_m<256, 4, true>(mm);
+        }
+    } else if (block == 512) {
+        switch (own) {
+            case 4: return bwd_by_m<512, 4, true>(mm);
+            case 10: return bwd_by_m<512, 10, true>(mm);
+            case 18: return bwd_by_m<512, 18, true>(mm);
+        }
+    }
+    return nullptr;
+}
+
+}  // namespace slos
+#else
+
 int64_t lds_fwd_states(const slos_plan_s& P, int n_max) {
     int64_t S = 0;
     for (int k = 1; k <= n_max - 1; ++k) S = std::max<int64_t>(S, (k >= 2 ? P.N[k - 1] : 0) + P.N[k]);
@@ -787,16 +861,6 @@ int64_t lds_bwd_states(const slos_plan_s& P, int n_max) {
     for (int k = 0; k <= n_max - 2; ++k) R += P.N[k];
     S = std::max<int64_t>(S, R + P.N[n_max - 2]);
     return S;
-}
-
-// photon-layer-(n-1) states per thread in the register-resident pulls
-int own_for(int block, int64_t Np) {
-    const int64_t need = (Np + block - 1) / block;
-    if (block == 256) return need <= 1 ? 1 : need <= 2 ? 2 : need <= 4 ? 4 : -1;
-    if (block == 512) return need <= 4 ? 4 : need <= 10 ? 10 : need <= 18 ? 18 : -1;
-    if (block == 768) return need <= 12 ? 12 : -1;
-    if (block == 1024) return need <= 10 ? 10 : -1;
-    return -1;
 }
 
 // every layer's predecessor entries must be compact (LDS byte offsets)
@@ -832,47 +896,26 @@ size_t fwd_lds_for(const slos_plan_s& P, int n_max, int block, bool expect, bool
            (expect ? (size_t)P.m * block * sizeof(float) : 0) + (thr ? (size_t)kThrChunkStates * sizeof(float) : 0);
 }
 
-int mmax_for(int m) { return m <= 8 ? 8 : m <= 12 ? 12 : m <= 16 ? 16 : m <= 20 ? 20 : m <= 24 ? 24 : 32; }
-
-template <int BLOCK, int OWN>
-void* bwd_by_m(int mm) {
-    if constexpr (BLOCK >= 768) {
-        if (mm > 20) return nullptr;  // h and acc do not fit the registers of 12 or 16 waves
-    }
-    switch (mm) {
-        case 8: return (void*)&fused_bwd_kernel<BLOCK, OWN, 8>;
-        case 12: return (void*)&fused_bwd_kernel<BLOCK, OWN, 12>;
-        case 16: return (void*)&fused_bwd_kernel<BLOCK, OWN, 16>;
-        case 20: return (void*)&fused_bwd_kernel<BLOCK, OWN, 20>;
-        case 24:
-            if constexpr (BLOCK < 768) return (void*)&fused_bwd_kernel<BLOCK, OWN, 24>;
-            return nullptr;
-        case 32:
-            if constexpr (OWN <= 10 && BLOCK < 768) return (void*)&fused_bwd_kernel<BLOCK, OWN, 32>;
-            return nullptr;  // h and acc do not fit the registers
-    }
-    return nullptr;
-}
-
-void* pick_bwd(int block, int m, int64_t Np) {
+void* pick_bwd(int block, int m, int64_t Np, bool restricted) {
+    if (restricted) return pick_bwd_restricted(block, m, Np);
     const int own = own_for(block, Np);
     const int mm = mmax_for(m);
     if (block == 256) {
         switch (own) {
-            case 1: return bwd_by_m<256, 1>(mm);
-            case 2: return bwd_by_m<256, 2>(mm);
-            case 4: return bwd_by_m<256, 4>(mm);
+            case 1: return bwd_by_m<256, 1, false>(mm);
+            case 2: return bwd_by_m<256, 2, false>(mm);
+            case 4: return bwd_by_m<256, 4, false>(mm);
         }
     } else if (block == 512) {
         switch (own) {
-            case 4: return bwd_by_m<512, 4>(mm);
-            case 10: return bwd_by_m<512, 10>(mm);
-            case 18: return bwd_by_m<512, 18>(mm);
+            case 4: return bwd_by_m<512, 4, false>(mm);
+            case 10: return bwd_by_m<512, 10, false>(mm);
+            case 18: return bwd_by_m<512, 18, false>(mm);
         }
     } else if (block == 768) {
-        if (own == 12) return bwd_by_m<768, 12>(mm);
+        if (own == 12) return bwd_by_m<768, 12, false>(mm);
     } else if (block == 1024) {
-        if (own == 10) return bwd_by_m<1024, 10>(mm);
+        if (own == 10) return bwd_by_m<1024, 10, false>(mm);
     }
     return nullptr;
 }
@@ -918,10 +961,6 @@ bool fused_bwd_supported(const slos_plan_s& P, int n_max, int block, std::string
         if (why) *why = "block must be 256, 512, 768 or 1024";
         return false;
     }
-    if (P.flags & (SLOS_PLAN_UNBUNCHED | SLOS_PLAN_DUAL_RAIL)) {
-        if (why) *why = "restricted spaces use the layered adjoint";
-        return false;
-    }
     if (!compact_tables(P, n_max)) {
         if (why) *why = "photon layers too large for compact tables";
         return false;
@@ -938,7 +977,7 @@ bool fused_bwd_supported(const slos_plan_s& P, int n_max, int block, std::string
         if (why) *why = "layer n-1 too large for the register-resident adjoint at this block size";
         return false;
     }
-    if (n_max >= 2 && pick_bwd(block, P.m, P.N[n_max - 1]) == nullptr) {
+    if (n_max >= 2 && pick_bwd(block, P.m, P.N[n_max - 1], restricted_plan(P)) == nullptr) {
         if (why) *why = "no register-resident adjoint for this block size and mode count";
         return false;
     }
@@ -948,7 +987,8 @@ bool fused_bwd_supported(const slos_plan_s& P, int n_max, int block, std::string
 int fused_default_block(const slos_plan_s& P, int n_max, bool backward) {
     if (backward) {
         const int64_t Np = n_max >= 2 ? P.N[n_max - 1] : 1;
-        return Np <= 1024 ? 256 : (Np <= 5120 || P.m > 20) ? 512 : 768;
+        // restricted spaces have adjoint instances at 256 and 512 threads only
+        return Np <= 1024 ? 256 : (Np <= 5120 || P.m > 20 || restricted_plan(P)) ? 512 : 768;
     }
     const int64_t Nbig = n_max >= 1 ? P.N[n_max] : 1;
     return Nbig >= 8192 ? 1024 : 256;
@@ -986,7 +1026,7 @@ int launch_fused_bwd(const slos_batch_s& Bt, int block, const float2* U, const v
     std::string why;
     if (!fused_bwd_supported(P, Bt.n_max, block, &why)) return fail(SLOS_EUNSUPPORTED, "fused backward: " + why);
     const int64_t Np = Bt.n_max >= 2 ? P.N[Bt.n_max - 1] : 1;
-    void* fn = pick_bwd(block, P.m, Np);
+    void* fn = pick_bwd(block, P.m, Np, restricted_plan(P));
     if (!fn) return fail(SLOS_EUNSUPPORTED, "fused backward: no kernel instance for this shape");
     const size_t lds = bwd_lds_for_block(P, Bt.n_max, block);
     hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -1001,3 +1041,4 @@ int launch_fused_bwd(const slos_batch_s& Bt, int block, const float2* U, const v
 }
 
 }  // namespace slos
+#endif  // SLOS_FUSED_RESTRICTED_INSTANCES

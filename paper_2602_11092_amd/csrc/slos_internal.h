@@ -127,6 +127,11 @@ size_t fused_fwd_lds_bytes(const slos_plan_s& P, int n_max);
 size_t fused_bwd_lds_bytes(const slos_plan_s& P, int n_max);
 // expect: the per-mode expectation epilogue (per-lane LDS accumulators)
 bool fused_fwd_supported(const slos_plan_s& P, int n_max, int block, std::string* why, bool expect = false);
+// the fused adjoint's instances for restricted-space plans (slos_fused_r.hip)
+void* pick_bwd_restricted(int block, int m, int64_t Np);
+// successors that leave a restricted space are marked so in the successor tables
+constexpr uint32_t kNoSuccessor = 0xFFFFFFF8u;  // (uint32)(-1) << 3
+inline bool restricted_plan(const slos_plan_s& P) { return (P.flags & (SLOS_PLAN_UNBUNCHED | SLOS_PLAN_DUAL_RAIL)) != 0; }
 // whether the fused forward's click-pattern epilogue (epi 4) serves this plan and block
 bool fused_threshold_supported(const slos_plan_s& P, int n_max, int block);
 bool fused_bwd_supported(const slos_plan_s& P, int n_max, int block, std::string* why);

@@ -161,7 +161,6 @@ __global__ __launch_bounds__(BLOCK) void layered_layer_kernel(int m, const Layer
 // RESTRICTED: plans of a restricted space, whose successor tables mark
 // successors outside the space with kNoSuccessor; those pairs contribute
 // nothing (the forward never formed such states).
-constexpr uint32_t kNoSuccessor = 0xFFFFFFF8u;  // (uint32)(-1) << 3
 
 template <int BLOCK, int MMAX, bool RESTRICTED>
 __global__ __launch_bounds__(BLOCK) void layered_pull_kernel(int m, const LayerDev* __restrict__ Ls, BatchDev Bt,

@@ -133,28 +133,18 @@ def test_unbunched_m24_n8_sampled():
         assert np.abs(pb[b, ranks] - ref).max() <= P_TOL
 
 
-@pytest.mark.parametrize("space", ["unbunched", "dual_rail"])
-def test_restricted_backward_against_oracle(space):
-    # the layered adjoint on a restricted plan: the gradient of a loss of the
-    # restricted probabilities only (successors outside the space contribute nothing)
-    m = 8
-    dual = space == "dual_rail"
-    rng = np.random.default_rng(11)
-    U, occ = _batch(rng, 12, m, 1, 4, True)
-    plan = B.Plan(m, 4, unbunched=not dual, dual_rail=dual)
-    batch = B.Batch(plan, occ)
-    assert batch.get_config(B.OP_PROBS_BACKWARD)[0] == B.VARIANT_LAYERED
-    with pytest.raises(B.SlosError):
-        batch.set_config(B.OP_PROBS_BACKWARD, B.VARIANT_FUSED, 256)
+ADJOINTS = [(B.VARIANT_FUSED, 256), (B.VARIANT_FUSED, 512), (B.VARIANT_LAYERED, 256)]
+
+
+def _restricted_grad_check(batch, U, occ, m, dual, rng):
     Ud = to_dev_c64(U)
     gp = rng.standard_normal(batch.out_len).astype(np.float32)
-    say("restricted backward", space)
     gU = B.fock_probs_backward(batch, Ud, torch.from_numpy(gp).to(DEV))
     ga = (rng.standard_normal(batch.out_len) + 1j * rng.standard_normal(batch.out_len)).astype(np.complex64)
     gUa = B.fock_amplitudes_backward(batch, Ud, torch.from_numpy(ga).to(DEV))
     torch.cuda.synchronize()
     gU, gUa = gU.cpu().numpy(), gUa.cpu().numpy()
-    for b in range(12):
+    for b in range(batch.B):
         n = int(occ[b].sum())
         outs = O.fock_basis(m, n)
         keep = outs.reshape(len(outs), -1, 2).sum(2).max(1) <= 1 if dual else outs.max(1) <= 1
@@ -163,6 +153,51 @@ def test_restricted_backward_against_oracle(space):
         assert rel_err(gU[b], ref) <= G_RTOL, (b, rel_err(gU[b], ref))
         refa = O.amplitude_grad(widen(U[b]), occ[b], ga[o0:o1].astype(np.complex128), outputs=outs[keep])
         assert rel_err(gUa[b], refa) <= G_RTOL, (b, rel_err(gUa[b], refa))
+
+
+@pytest.mark.parametrize("space", ["unbunched", "dual_rail"])
+@pytest.mark.parametrize("adjoint", ADJOINTS)
+def test_restricted_backward_against_oracle(space, adjoint):
+    # the adjoint on a restricted plan: the gradient of a loss of the
+    # restricted probabilities (amplitudes) only; successors outside the space
+    # contribute nothing.  The fused adjoint's restricted instances select the
+    # zero slot for marked successors.
+    m = 8
+    dual = space == "dual_rail"
+    rng = np.random.default_rng(11)
+    U, occ = _batch(rng, 12, m, 1, 4, True)
+    plan = B.Plan(m, 4, unbunched=not dual, dual_rail=dual)
+    batch = B.Batch(plan, occ)
+    assert batch.get_config(B.OP_PROBS_BACKWARD)[0] == B.VARIANT_FUSED  # the default
+    for op in (B.OP_PROBS_BACKWARD, B.OP_AMPLITUDES_BACKWARD):
+        batch.set_config(op, *adjoint)
+    say("restricted backward", space, adjoint)
+    _restricted_grad_check(batch, U, occ, m, dual, rng)
+
+
+@pytest.mark.parametrize("block", [256, 512])
+def test_fused_restricted_adjoint_larger_spaces(block):
+    # unbunched m = 12 (256 threads: layer n-1 of 495 states) or m = 16 (512
+    # threads: 4368 outputs, layer n-1 of 1820 states) up to n = 5, and
+    # dual-rail up to 5 or 6 qubits; mixed photon numbers, bunched inputs
+    shapes = ((12, False, 5), (10, True, 5)) if block == 256 else ((16, False, 5), (12, True, 6))
+    for m, dual, n_hi in shapes:
+        rng = np.random.default_rng(70 + m)
+        U, occ = _batch(rng, 10, m, 1, n_hi, True)
+        occ[0] = 0
+        occ[0, :n_hi] = 1  # one sample at the top photon number
+        batch = B.Batch(B.Plan(m, n_hi, unbunched=not dual, dual_rail=dual), occ)
+        for op in (B.OP_PROBS_BACKWARD, B.OP_AMPLITUDES_BACKWARD):
+            batch.set_config(op, B.VARIANT_FUSED, block)
+        say("fused restricted adjoint", m, "dual" if dual else "unbunched", block)
+        _restricted_grad_check(batch, U, occ, m, dual, rng)
+
+
+def test_fused_restricted_adjoint_has_no_768_or_1024_instances():
+    batch = B.Batch(B.Plan(8, 3, unbunched=True), np.array([[1, 1, 1, 0, 0, 0, 0, 0]], dtype=np.int32))
+    for blk in (768, 1024):
+        with pytest.raises(B.SlosError):
+            batch.set_config(B.OP_PROBS_BACKWARD, B.VARIANT_FUSED, blk)
 
 
 def test_restricted_layer_trains():
