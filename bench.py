@@ -15,6 +15,7 @@ import argparse
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -42,6 +43,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--eager", action="store_true", help="launch the step eagerly instead of replaying a HIP graph")
+    ap.add_argument("--autotune-cache", default=None,
+                    help="JSON file of autotuner choices to reuse and extend (default: $SLOS_AUTOTUNE_CACHE, else none)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration under rocprofv3 --pmc)")
     return ap.parse_args()
@@ -121,7 +124,7 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
-    if args.workload in EXTENSIONS:
+    if args.workload in EXTENSIONS or re.fullmatch(FIDELITY_NAME, args.workload):
         return bench_extension(args, dev)
     wl = W.make(args.workload)
     if wl.theta is None or not wl.backward or not (wl.n == wl.n.max()).all():
@@ -150,7 +153,7 @@ def main():
     mws = B.mesh_workspace(m, Bn, dev)
     B.mesh_to_unitary(theta, x, wl.enc_scale, out=U, ws=mws)
     # kernel variant and workgroup size per op, picked by timing on this batch
-    tuned = autotune(batch, U, ops=(B.OP_PROBS, B.OP_PROBS_BACKWARD), warmup=2, iters=3)
+    tuned = autotune(batch, U, ops=(B.OP_PROBS, B.OP_PROBS_BACKWARD), warmup=2, iters=3, cache=args.autotune_cache)
     names = VARIANT_NAMES
     tuned_cfg = {op_name: cfg_name(tuned[op])
                  for op, op_name in ((B.OP_PROBS, "fock_probs"), (B.OP_PROBS_BACKWARD, "fock_probs_backward"))}
@@ -408,7 +411,7 @@ def bench_other(args, wl, dev):
         mws = B.mesh_workspace(m, Bn, dev)
         B.mesh_to_unitary(theta, x, wl.enc_scale, out=U, ws=mws)
     ops = (B.OP_PROBS, B.OP_PROBS_BACKWARD) if wl.backward else (B.OP_PROBS,)
-    tuned = autotune(batch, U, ops=ops, warmup=1, iters=2)
+    tuned = autotune(batch, U, ops=ops, warmup=1, iters=2, cache=args.autotune_cache)
     p = torch.empty(batch.out_len, dtype=torch.float32, device=dev)
     gU = torch.empty_like(U)
     fws = batch.workspace(B.OP_PROBS, dev)
@@ -550,8 +553,10 @@ def cpu_baseline_other(wl, U, p, gU, gp):
 
 # Workloads of the measurement, encoding and kernel extensions (one line each).
 EXTENSIONS = ("expectations_clements_m20_n5_b512", "threshold_clements_m20_n5_b512",
-              "sample_clements_m20_n5_b512_s1024", "unbunched_haar_m24_n8_b16",
+              "sample_clements_m20_n5_b512_s1024", "unbunched_haar_m24_n8_b16", "unbunched_train_clements_m20_n5_b512",
               "superposition_m6_n3_g1024", "superposition_shared_m8_n4_g4096", "fidelity_m6_n4_b1024")
+# fidelity kernels of other shapes: fidelity_m<modes>_n<photons>_b<Gram size>, photons in the first n modes
+FIDELITY_NAME = r"fidelity_m(\d+)_n(\d+)_b(\d+)"
 FP32_MFMA_PEAK = 157.3  # TFLOP/s, MI355X dense FP32 matrix-core rate
 FP64_PEAK = 78.6  # TFLOP/s, MI355X vector FP64 (equal to its unpacked FP32 rate)
 
@@ -595,9 +600,10 @@ def bench_extension(args, dev):
         basis = O.fock_basis(m, n)
         occ = np.tile(basis, (Bn, 1)).astype(np.int32)
         U64 = W.haar_unitaries(rng, Bn, m)
-    else:  # fidelity_m6_n4_b1024: the paper's kernel example shape, Gram of 1024 states
-        m, n, Bn = 6, 4, 1024
-        occ = np.array([1, 1, 1, 1, 0, 0], dtype=np.int32)
+    else:  # fidelity_m<m>_n<n>_b<B> (fidelity_m6_n4_b1024: the paper's kernel example shape)
+        m, n, Bn = (int(v) for v in re.fullmatch(FIDELITY_NAME, name).groups())
+        occ = np.zeros(m, dtype=np.int32)
+        occ[:n] = 1
         U64 = W.haar_unitaries(rng, Bn, m)
     U = torch.from_numpy(U64.astype(np.complex64)).to(dev)
     Uh = U.cpu().numpy().astype(np.complex128)
@@ -638,6 +644,29 @@ def bench_extension(args, dev):
         oracle_one = lambda b: O.sample_shots(Uh[b], occ[b], uh[b])
         check = lambda b, r: float(np.mean(out[b].cpu().numpy() != r))  # fraction differing (boundary ties)
         cfg = "probabilities, FP64 cumulative sums, binary search; 1024 shots per sample"
+    elif name.startswith("unbunched_train"):
+        # forward + adjoint on the unbunched space (the fused adjoint's restricted instances)
+        batch = B.Batch(B.Plan(m, n, unbunched=True), occ)
+        out = torch.empty(batch.out_len, dtype=torch.float32, device=dev)
+        gp = torch.from_numpy(rng.standard_normal(batch.out_len).astype(np.float32)).to(dev)
+        gU = torch.empty_like(U)
+        ws_f, ws_b = batch.workspace(B.OP_PROBS, dev), batch.workspace(B.OP_PROBS_BACKWARD, dev)
+
+        def step():
+            B.fock_probs(batch, U, out=out, ws=ws_f)
+            B.fock_probs_backward(batch, U, gp, out=gU, ws=ws_b)
+        work, unit = batch.out_len, "Fock amplitudes/s"
+        flop = 4 * Bn * slos_fwd_flop(m, n, B.PLAN_UNBUNCHED)  # forward + the adjoint's three products
+        outs = np.zeros((math.comb(m, n), m), dtype=np.int32)
+        for r, c in enumerate(__import__("itertools").combinations(range(m), n)):
+            outs[r, list(c)] = 1
+        gph = gp.cpu().numpy().astype(np.float64)
+        N = len(outs)
+        oracle_one = lambda b: O.probs_grad(Uh[b], occ[b], gph[b * N:(b + 1) * N], outputs=outs)
+        check = lambda b, r: float(np.abs(gU[b].cpu().numpy() - r).max() / np.abs(r).max())
+        cfg = "unbunched space, probabilities + adjoint (%s/%s); error: max relative gradient error" % tuple(
+            {B.VARIANT_FUSED: "fused", B.VARIANT_LAYERED: "layered"}.get(batch.get_config(op)[0], "?")
+            for op in (B.OP_PROBS, B.OP_PROBS_BACKWARD))
     elif name.startswith("unbunched"):
         batch = B.Batch(B.Plan(m, n, unbunched=True), occ)
         out = torch.empty(batch.out_len, dtype=torch.float32, device=dev)
