@@ -267,6 +267,16 @@ def main():
             torch.neg(src, out=dst)
         torch.cuda.synchronize()
 
+    # ---- achievable HBM bandwidth on this machine: a STREAM-like elementwise copy
+    # (torch.neg, 1 GiB read + 1 GiB written), HIP events over 10 calls
+    src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        torch.neg(src, out=dst)
+    copy_ms = time_region(lambda: torch.neg(src, out=dst), 10, stream)
+    copy_gbs = 2.0 * (1 << 30) / (copy_ms * 1e-3) / 1e9
+    del src, dst
+
     cpu = None
     if not args.no_cpu_baseline:
         run()  # U, p and dL/dU of one step, for the comparison with the oracle
@@ -293,6 +303,8 @@ def main():
         "cpu_baseline": cpu,
         "replays": replays,
         "hbm_frac_step": round(hbm_frac_step, 4),
+        "hbm_copy_gbs": round(copy_gbs, 1),  # achievable: a 1 GiB elementwise copy on this machine
+        "hbm_frac_step_of_copy": round(hbm_frac_step * HBM_PEAK_GBS / copy_gbs, 4),
         "kernels_us": {k: round(v, 3) for k, v in kernels_us.items()},
         "train_step_ms": round(ms_per_step + readout_ms, 4),
         "readout_ms": round(readout_ms, 4),
