@@ -91,9 +91,11 @@ extern "C" {
  * QuantumBridge example of Sec. II-D uses it): only unbunched outputs,
  * t_j <= 1, C(m, n) of them, in the basis order above restricted to them.
  * The recursion stays exact (removing a photon keeps a state unbunched).
- * Input states may be bunched.  The adjoint runs in the layered variant
- * (successors outside the space contribute nothing); the fused adjoint
- * reports SLOS_EUNSUPPORTED.  Requires n_max <= m. */
+ * Input states may be bunched.  In the adjoint, successors outside the
+ * space contribute nothing; the fused adjoint serves these plans with
+ * workgroups of 256 or 512 threads and at most 24 modes (other sizes report
+ * SLOS_EUNSUPPORTED for the fused variant and run layered by default).
+ * Requires n_max <= m. */
 #define SLOS_PLAN_UNBUNCHED 2
 /* Dual-rail computation space (Sec. II-B: computation spaces; Sec. II-D:
  * the qubit-photon bridge): qubit g is the mode pair (2g, 2g+1) and every
@@ -106,7 +108,10 @@ extern "C" {
 #define SLOS_PLAN_DUAL_RAIL 4
 /* Also build the threshold-detector tables (Sec. II-B: detector models)
  * used by fock_threshold_probs: per photon layer, the states of each click
- * pattern.  Costs about 4 bytes per state. */
+ * pattern (about 4 bytes per state), runs of whole patterns of at most 16384
+ * states, and the predecessor rows and norms in pattern order
+ * (16 ceil(k/4) + 4 bytes per state), which the fused forward reads when it
+ * sums the patterns itself. */
 #define SLOS_PLAN_THRESHOLD 8
 
 /* Kernel variants for slos_batch_set_config. */
@@ -380,10 +385,12 @@ SLOS_API int slos_batch_threshold_offsets(slos_batch_t batch, int64_t* off_host)
 /* out (device, float, [threshold_len]) <- P(c) = sum of p_t over the states
  * t whose occupied modes are exactly c (threshold detectors register
  * presence, not number).  Needs a plan created with SLOS_PLAN_THRESHOLD
- * (else SLOS_EUNSUPPORTED).  Forms p in the workspace with the
- * configuration set for SLOS_OP_THRESHOLD_PROBS, then sums each pattern's
- * states in ascending order (deterministic).  ws: slos_workspace_bytes(batch,
- * SLOS_OP_THRESHOLD_PROBS) bytes. */
+ * (else SLOS_EUNSUPPORTED).  Each pattern's states are summed in ascending
+ * order (deterministic): with the fused variant inside the forward, in runs
+ * of whole patterns held in LDS (p is never written), where they fit; else p
+ * is formed in the workspace with the configuration set for
+ * SLOS_OP_THRESHOLD_PROBS and a second kernel sums it.  ws:
+ * slos_workspace_bytes(batch, SLOS_OP_THRESHOLD_PROBS) bytes either way. */
 SLOS_API int fock_threshold_probs(slos_batch_t batch, const float* U, float* out,
                                   void* ws, size_t ws_bytes, void* stream);
 
