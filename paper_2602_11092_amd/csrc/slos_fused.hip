@@ -32,6 +32,8 @@
 // mode's G_U share reduced per wave), two contiguous ranges of t', so the
 // pull stays a plain gather from LDS.  The smaller lower layers take g_{k-1}
 // from the same pull and G_U from mode-per-wave dot products.
+#include <type_traits>
+
 #include "slos_internal.h"
 
 namespace slos {
@@ -83,6 +85,39 @@ template <int BLOCK>
 __device__ __forceinline__ bool slot_meets(int s, int lo, int hi) {
     return (s + 1) * BLOCK > fresh(lo) && s * BLOCK < fresh(hi);
 }
+// does this wave's piece of slot s, [s*BLOCK + 64*wave, +64), meet [lo, hi)?
+// (a wave whose lanes all fall outside the range skips the slot)
+template <int BLOCK>
+__device__ __forceinline__ bool piece_meets(int s, int lo, int hi) {
+    const int p = s * BLOCK + 64 * fresh((int)threadIdx.x >> 6);
+    return p + 64 > fresh(lo) && p < fresh(hi);
+}
+// f(std::integral_constant<int, i>) for the one i in [LO, HI) equal to the
+// wave-uniform s, through a binary tree of scalar branches: element s of a
+// register array without a copy through memory.  The branch bodies pin the
+// element they touch so that no level turns into selects over every element.
+template <int LO, int HI, typename F>
+__device__ __forceinline__ void on_index(int s, F&& f) {
+    if constexpr (HI - LO == 1) {
+        f(std::integral_constant<int, LO>{});
+    } else {
+        constexpr int MID = (LO + HI) / 2;
+        if (fresh(s) < MID) on_index<LO, MID>(s, f);
+        else on_index<MID, HI>(s, f);
+    }
+}
+__device__ __forceinline__ void pin(float2& v) { asm volatile("" : "+v"(v.x), "+v"(v.y)); }
+template <int N>
+__device__ __forceinline__ float2 elem_get(const float2 (&a)[N], int s) {
+    float2 v;
+    on_index<0, N>(s, [&](auto I) { v = a[decltype(I)::value]; pin(v); });
+    return v;
+}
+template <int N>
+__device__ __forceinline__ void elem_set(float2 (&a)[N], int s, float2 v) {
+    on_index<0, N>(s, [&](auto I) { a[decltype(I)::value] = v; pin(a[decltype(I)::value]); });
+}
+
 __host__ __device__ constexpr uint32_t range_bits(int lo, int hi) {
     return (hi >= 32 ? 0xFFFFFFFFu : ((1u << hi) - 1u)) & ~((1u << lo) - 1u);
 }
@@ -405,13 +440,19 @@ __device__ __forceinline__ float2 coeff(uint32_t j) {
     return __builtin_bit_cast(float2, *(lds_vu64*)(size_t)(kUcolAddr + 8 * j));
 }
 
-// Owned t' in [lo, hi), modes j in [jlo, jhi), by groups of four modes: per
-// owned state, one 16-byte successor load per group, all issued before the
-// first gather.  Branch-free per pair: a lane whose t' lies outside the range
-// gathers the zero slot (a select, no divergent region around the
-// accumulators), and modes outside [jlo, jhi) are skipped by uniform tests.
-// The coefficient column conj(u_j) sits in registers for the whole call
-// where the workgroup shape leaves room (below 1024 threads).
+// Owned t' in [lo, hi), modes j in [jlo, jhi), by groups of four modes, one
+// owned slot (t' = tid + s*BLOCK) per iteration of a loop over the slots that
+// meet the range: the slot's successor loads (one 16-byte load per group)
+// issue together, then per group its four LDS gathers, then their products;
+// g_{k-1} of the slot is taken out of and put back into acc[s] by a scalar
+// branch tree, so the code holds one slot's pairs, not OWN of them (the
+// kernel's instruction footprint is what this keeps small).  Branch-free per
+// pair: a lane whose t' lies outside the range gathers the zero slot (one
+// select on the slot's lane mask), and so do the modes outside [jlo, jhi) of
+// the (at most two) groups that straddle its ends, whose successor offsets
+// are replaced by the zero slot's once per group.  The coefficient column
+// conj(u_j) sits in registers for the whole call where the workgroup shape
+// leaves room (below 1024 threads).
 template <int BLOCK, int OWN, int MMAX, bool WITH_H = true, bool RS = false>
 __device__ __forceinline__ void pull(int lo, int hi, int jlo, int jhi, __amdgpu_buffer_rsrc_t rs, uint32_t gstride,
                                      uint32_t srcb, uint32_t Db, float2 (&acc)[OWN], float2 (&h)[MMAX]) {
@@ -419,18 +460,18 @@ __device__ __forceinline__ void pull(int lo, int hi, int jlo, int jhi, __amdgpu_
     constexpr bool kCoefRegs = BLOCK < 1024;
     if (lo >= hi || jlo >= jhi) return;
     const int tid = threadIdx.x;
-    const int jbits = (int)range_bits(jlo, jhi);
-    const int gbits = (int)range_bits(jlo >> 2, (jhi + 3) >> 2);
+    const int gbits = (int)range_bits(jlo >> 2, (jhi + 3) >> 2);  // the groups that meet [jlo, jhi)
+    const int fbits = (int)range_bits((jlo + 3) >> 2, jhi >> 2);  // the groups inside it
     const uint32_t zoff = kUcolAddr + 32 * 8 - srcb;  // srcb + zoff: the zero slot
     float2 cu[kCoefRegs ? MMAX : 1];
     if (kCoefRegs) {
 #pragma unroll
         for (int j = 0; j < (kCoefRegs ? MMAX : 1); ++j) cu[j] = lds_ld(kUcolAddr + 8u * (uint32_t)j);
     }
-#pragma unroll
-    for (int s = 0; s < OWN; ++s) {
-        if (!slot_meets<BLOCK>(s, lo, hi)) continue;  // no owned state in range (uniform)
-        const int tp = fresh_v(tid) + s * BLOCK;
+    const int s_end = min(OWN, (hi + BLOCK - 1) / BLOCK);
+    for (int s = lo / BLOCK; s < s_end; ++s) {  // the owned slots that meet [lo, hi) (uniform)
+        if (!piece_meets<BLOCK>(s, lo, hi)) continue;  // none of this wave's lanes in range
+        const int tp = tid + s * BLOCK;
         const bool act = tp >= lo && tp < hi;
         const int tc = min(max(tp, lo), hi - 1);
         const uint32_t vo = (uint32_t)tc * 16u;
@@ -438,79 +479,99 @@ __device__ __forceinline__ void pull(int lo, int hi, int jlo, int jhi, __amdgpu_
 #pragma unroll
         for (int g = 0; g < NG; ++g) sv[g] = buf_ld4(rs, vo, (uint32_t)g * gstride);
         const float2 dv = lds_ld(Db + 8u * (uint32_t)tc);
+        float2 a = elem_get<OWN>(acc, s);
 #pragma unroll
         for (int g = 0; g < NG; ++g) {
             if (!has(gbits, g)) continue;  // no mode of this group in range (uniform)
+            uint32_t c[4] = {sv[g].x, sv[g].y, sv[g].z, sv[g].w};
+            if (!has(fbits, g)) {  // a group straddling an end of the range (uniform)
+                const int jl = fresh(jlo), jh = fresh(jhi);  // tests formed here, not hoisted
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (4 * g + q < jl || 4 * g + q >= jh) c[q] = zoff;
+            }
+            // the group's four gathers, then its products
+            float2 gv[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                bool ok = act;
+                // restricted spaces: a successor outside the space was never formed
+                if constexpr (RS) ok = ok && c[q] != kNoSuccessor;
+                gv[q] = lds_ld(srcb + (ok ? c[q] : zoff));
+            }
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int j = 4 * g + q;
-                // a select, not a branch, so that the group's gathers issue together
-                const bool jin = has(jbits, j);
-                uint32_t so;
-                if constexpr (RS) {
-                    // restricted spaces: a successor outside the space was never formed
-                    const uint32_t c = comp(sv[g], q);
-                    so = (act & jin & (c != kNoSuccessor)) ? c : zoff;
-                } else {
-                    so = (act & jin) ? comp(sv[g], q) : zoff;
-                }
-                const float2 gv = lds_ld(srcb + so);
-                c_fma_conj(acc[s], kCoefRegs ? cu[kCoefRegs ? j : 0] : coeff(j), gv);
-                if (WITH_H) c_fma_conj(h[j], dv, gv);
+                c_fma_conj(a, kCoefRegs ? cu[kCoefRegs ? j : 0] : coeff(j), gv[q]);
+                if (WITH_H) c_fma_conj(h[j], dv, gv[q]);
             }
         }
+        elem_set<OWN>(acc, s, a);
     }
 }
 
-// A few modes j in [jlo, jhi) over owned t' in [lo, hi), owned states in
-// blocks of SB: per block, each state's successor row offset, range mask and
-// conj(d_{k-1}) are formed once; then mode by mode (a uniform test per mode)
-// the block's successor loads and gathers issue together, the mode's
-// successor column chosen by the load's scalar offset.  G_U shares go to the
-// same per-lane h[j] as the wide pull.
+// A few modes j in [jlo, jhi) below the smallest occupied mode of every
+// owned t' in [lo, hi) (t' from the end of layer k-1: its smallest mode is at
+// least jhi).  Such a successor needs no table: in the basis order the
+// states of layer k whose smallest mode is j and holds one photon are e_j + t'
+// for the t' whose smallest mode exceeds j, in the order of t', and they end
+// the block of smallest mode j, so rank(t' + e_j) = t' + minoff_k(j+1) - N_{k-1}
+// (a per-mode constant).  conj(d_{k-1}) of the owned states is read once;
+// then mode by mode (a uniform test per mode): the mode's coefficient and
+// offset, the gathers of every owned slot from the first that meets the
+// range, issued together (lanes out of range gather the zero slot), then
+// their products.  G_U shares go to the same per-lane h[j] as
+// the wide pull.  Restricted spaces (where such a successor may leave the
+// space) read their successor tables instead, slot by slot.
 template <int BLOCK, int OWN, int MMAX, bool RS = false>
 __device__ __forceinline__ void pull_narrow(int lo, int hi, int jlo, int jhi, __amdgpu_buffer_rsrc_t rs,
                                             uint32_t gstride, uint32_t srcb, uint32_t Db, float2 (&acc)[OWN],
-                                            float2 (&h)[MMAX]) {
-    constexpr int SB = OWN < 4 ? OWN : 4;
+                                            float2 (&h)[MMAX], uint32_t MOk, int Nkm1) {
     if (lo >= hi || jlo >= jhi) return;
     const int tid = threadIdx.x;
     const int jbits = (int)range_bits(jlo, jhi);
-    const uint32_t zoff = kUcolAddr + 32 * 8 - srcb;  // srcb + zoff: the zero slot
+    const uint32_t zaddr = kUcolAddr + 32 * 8;  // the zero slot
+    const uint32_t zoff = zaddr - srcb;         // srcb + zoff: the zero slot
+    // slots below s_first hold no owned state in range (uniform)
+    const int s_first = fresh(lo) / BLOCK;
+    float2 dv[OWN];  // conj(d_{k-1}) of the owned states, read once
 #pragma unroll
-    for (int s0 = 0; s0 < OWN; s0 += SB) {
-        bool any = false;
+    for (int s = 0; s < OWN; ++s) {
+        if (s < s_first) continue;
+        const int tp = fresh_v(tid) + s * BLOCK;
+        dv[s] = lds_ld(Db + 8u * (uint32_t)min(max(tp, lo), hi - 1));
+    }
 #pragma unroll
-        for (int s = s0; s < s0 + SB && s < OWN; ++s) any = any || slot_meets<BLOCK>(s, lo, hi);
-        if (!any) continue;  // uniform
-        float2 dv[SB];
-        uint32_t vo[SB];
-        bool act[SB];
+    for (int j = 0; j < MMAX; ++j) {
+        if (!has(jbits, j)) continue;  // uniform, once per mode
+        const float2 uj = coeff(j);
+        float2 g[OWN];
+        if constexpr (RS) {
+            const uint32_t soff = (uint32_t)(j >> 2) * gstride + 4u * (uint32_t)(j & 3);
 #pragma unroll
-        for (int q = 0; q < SB; ++q) {
-            const int tp = fresh_v(tid) + (s0 + q) * BLOCK;
-            act[q] = s0 + q < OWN && tp >= lo && tp < hi;
-            const int tc = min(max(tp, lo), hi - 1);
-            vo[q] = (uint32_t)tc * 16u;
-            dv[q] = lds_ld(Db + 8u * (uint32_t)tc);
+            for (int s = 0; s < OWN; ++s) {
+                if (s < s_first) continue;
+                const int tp = fresh_v(tid) + s * BLOCK;
+                const bool act = tp >= lo && tp < hi;
+                const uint32_t sv = buf_ld1(rs, (uint32_t)min(max(tp, lo), hi - 1) * 16u, soff);
+                g[s] = lds_ld(srcb + ((act && sv != kNoSuccessor) ? sv : zoff));
+            }
+        } else {
+            // successor t' + minoff_k(j+1) - N_{k-1}: a uniform byte offset from the state's own
+            const uint32_t dj = srcb + 8u * (uint32_t)(__builtin_amdgcn_readfirstlane(lds_ldi(MOk + 4u * (uint32_t)(j + 1))) - Nkm1);
+#pragma unroll
+            for (int s = 0; s < OWN; ++s) {
+                if (s < s_first) continue;
+                const int tp = fresh_v(tid) + s * BLOCK;
+                const bool act = tp >= lo && tp < hi;
+                g[s] = lds_ld(act ? dj + 8u * (uint32_t)tp : zaddr);
+            }
         }
 #pragma unroll
-        for (int j = 0; j < MMAX; ++j) {
-            if (!has(jbits, j)) continue;  // uniform, once per mode and block
-            const float2 uj = coeff(j);
-            const uint32_t soff = (uint32_t)(j >> 2) * gstride + 4u * (uint32_t)(j & 3);
-            uint32_t sv[SB];
-#pragma unroll
-            for (int q = 0; q < SB; ++q) sv[q] = buf_ld1(rs, vo[q], soff);
-#pragma unroll
-            for (int q = 0; q < SB; ++q) {
-                if (s0 + q >= OWN) continue;
-                float2 g;
-                if constexpr (RS) g = lds_ld(srcb + ((act[q] && sv[q] != kNoSuccessor) ? sv[q] : zoff));
-                else g = lds_ld(srcb + (act[q] ? sv[q] : zoff));
-                c_fma_conj(acc[s0 + q], uj, g);
-                c_fma_conj(h[j], dv[q], g);
-            }
+        for (int s = 0; s < OWN; ++s) {
+            if (s < s_first) continue;
+            c_fma_conj(acc[s], uj, g[s]);
+            c_fma_conj(h[j], dv[s], g[s]);
         }
     }
 }
@@ -597,9 +658,24 @@ __global__ __launch_bounds__(BLOCK) void fused_bwd_kernel(int m, const LayerDev*
     // (the layer recomputes run while acc and h are dead: the forward's width)
     constexpr int GU = kLU;
     constexpr int GM = BLOCK <= 512 ? 4 : BLOCK <= 768 ? 2 : 1;  // wider gathers where registers allow
-    extern __shared__ float2 lds[];  // ucol | X[S] layers and chunks | Hw[NW][32] | GUacc[16][32]
+    // LDS: ucol | X[S] layers and chunks | Hw[NW][32] | GUacc[16][32] | the
+    // sample's U [m][m] | minoff of layers n and n-1 [2][m+1] | photon modes
+    extern __shared__ float2 lds[];
     const uint32_t Hw = kXAddr + 8u * (uint32_t)S;
     const uint32_t GUacc = Hw + 8u * NW * 32;
+    const uint32_t Ust = GUacc + 8u * kMaxPhotons * 32;
+    const uint32_t MOn = Ust + 8u * (uint32_t)(m * m);
+    const uint32_t MOp = MOn + 4u * (uint32_t)(m + 1);
+    const uint32_t MDs = MOp + 4u * (uint32_t)(m + 1);
+    // wave-uniform reads of the staged index rows
+    auto mode_of = [&](int i) { return __builtin_amdgcn_readfirstlane(lds_ldi(MDs + 4u * (uint32_t)i)); };
+    auto minoff_n = [&](int c) { return __builtin_amdgcn_readfirstlane(lds_ldi(MOn + 4u * (uint32_t)c)); };
+    auto minoff_p = [&](int c) { return __builtin_amdgcn_readfirstlane(lds_ldi(MOp + 4u * (uint32_t)c)); };
+    // column i_k of U into the coefficient column (slots m..32 stay zero)
+    auto load_ucol = [&](int k) {
+        const int tid = threadIdx.x;
+        if (tid < m) lds_st(kUcolAddr + 8 * tid, lds_ld(Ust + 8u * (uint32_t)(tid * m + mode_of(k - 1))));
+    };
     const int tid = threadIdx.x;
     if (tid < kUcolSlots) lds_st(kUcolAddr + 8 * tid, c_zero());  // slots m..32 stay zero
 
@@ -613,13 +689,25 @@ __global__ __launch_bounds__(BLOCK) void fused_bwd_kernel(int m, const LayerDev*
         float2* gUb = gU + (size_t)b * m * m;
 
         for (int q = tid; q < kMaxPhotons * 32; q += BLOCK) lds_st(GUacc + 8u * q, c_zero());
+        // the sample's U, the index rows its layers consult, and its photon
+        // modes, staged once (one round of loads instead of one per layer)
+        for (int q = tid; q < m * m; q += BLOCK) lds_st(Ust + 8u * q, Ub[q]);
+        if (n >= 2) {
+            const int32_t* mon = ldc(&Ls[n].minoff);
+            const int32_t* mop = ldc(&Ls[n - 1].minoff);
+            for (int q = tid; q <= m; q += BLOCK) {
+                lds_sti(MOn + 4u * q, ldg(mon + q));
+                lds_sti(MOp + 4u * q, ldg(mop + q));
+            }
+        }
+        if (tid < kMaxPhotons) lds_sti(MDs + 4u * tid, tid < n ? ldg(modes + tid) : -1);
         __syncthreads();
 
         if (n == 1) {
             // g_1[j] is G_U[j][i_1] itself (d_0 = 1)
             if (tid < m) {
                 const float c = ldg(layer(Ls, 1).nrm + tid) * innorm;
-                const float2 v = PROBS ? c_scale(Ub[tid * m + ldc(modes)], 2.f * ((const float*)gin)[off + tid] * c * c)
+                const float2 v = PROBS ? c_scale(lds_ld(Ust + 8u * (uint32_t)(tid * m + mode_of(0))), 2.f * ((const float*)gin)[off + tid] * c * c)
                                        : c_scale(((const float2*)gin)[off + tid], c);
                 lds_st(GUacc + 8u * tid, v);
             }
@@ -630,7 +718,7 @@ __global__ __launch_bounds__(BLOCK) void fused_bwd_kernel(int m, const LayerDev*
             const int Np = (int)Lp.N;
             // ---- recompute layers 1..n-1; layer n-1 ends at the start of X
             for (int k = 1; k <= n - 1; ++k) {
-                if (tid < m) lds_st(kUcolAddr + 8 * tid, Ub[tid * m + ldc(modes + k - 1)]);
+                load_ucol(k);
                 __syncthreads();
                 const LayerDev Lk = layer(Ls, k);
                 const int Nk = (int)Lk.N;
@@ -640,7 +728,7 @@ __global__ __launch_bounds__(BLOCK) void fused_bwd_kernel(int m, const LayerDev*
                 __syncthreads();
             }
             // ---- top layer, in chunks of smallest-mode blocks
-            if (tid < m) lds_st(kUcolAddr + 8 * tid, Ub[tid * m + ldc(modes + n - 1)]);
+            load_ucol(n);
             const uint32_t D = kXAddr;                     // d_{n-1}
             const uint32_t C = kXAddr + 8u * (uint32_t)Np;  // the chunk of g_n
             const int cap = S - Np;
@@ -660,9 +748,9 @@ __global__ __launch_bounds__(BLOCK) void fused_bwd_kernel(int m, const LayerDev*
             int a = 0;
             while (a < m) {
                 int bb = a + 1;
-                while (bb < m && ldc(Ln.minoff + bb + 1) - ldc(Ln.minoff + a) <= cap) ++bb;
-                const int base = ldc(Ln.minoff + a);
-                const int end = ldc(Ln.minoff + bb);
+                const int base = minoff_n(a);
+                while (bb < m && minoff_n(bb + 1) - base <= cap) ++bb;
+                const int end = minoff_n(bb);
                 // g_n on the chunk: 2 dL/dp_t c_t^2 d_n[t] (probabilities; the
                 // factor loads issue together with the gather's table loads) or
                 // c_t G_a[t] (amplitudes, a streaming pass).
@@ -703,9 +791,9 @@ __global__ __launch_bounds__(BLOCK) void fused_bwd_kernel(int m, const LayerDev*
                 __syncthreads();
                 // {min(t') in [a, bb), j >= a} and {min(t') >= bb, a <= j < bb}
                 const uint32_t srcb = C - 8u * (uint32_t)base;
-                pull<BLOCK, OWN, MMAX, true, RS>(ldc(Lp.minoff + a), ldc(Lp.minoff + bb), a, m, rs, gstride, srcb, D,
-                                                acc, h);
-                pull_narrow<BLOCK, OWN, MMAX, RS>(ldc(Lp.minoff + bb), Np, a, bb, rs, gstride, srcb, D, acc, h);
+                const int wlo = minoff_p(a), whi = minoff_p(bb);
+                pull<BLOCK, OWN, MMAX, true, RS>(wlo, whi, a, m, rs, gstride, srcb, D, acc, h);
+                pull_narrow<BLOCK, OWN, MMAX, RS>(whi, Np, a, bb, rs, gstride, srcb, D, acc, h, MOn, Np);
                 __syncthreads();
                 a = bb;
             }
@@ -722,7 +810,7 @@ __global__ __launch_bounds__(BLOCK) void fused_bwd_kernel(int m, const LayerDev*
             if (tid == 0) lds_st(kXAddr + 8u * (uint32_t)Np, make_float2(1.f, 0.f));
             __syncthreads();
             for (int k = 1; k <= n - 2; ++k) {
-                if (tid < m) lds_st(kUcolAddr + 8 * tid, Ub[tid * m + ldc(modes + k - 1)]);
+                load_ucol(k);
                 __syncthreads();
                 const LayerDev Lk = layer(Ls, k);
                 layer_into_lds<BLOCK, GU>(Lk, k, kXAddr + 8u * (uint32_t)(Np + (int)ldc(&Ls[k - 1].cum)),
@@ -730,7 +818,7 @@ __global__ __launch_bounds__(BLOCK) void fused_bwd_kernel(int m, const LayerDev*
                 __syncthreads();
             }
             for (int k = n - 1; k >= 1; --k) {
-                if (tid < m) lds_st(kUcolAddr + 8 * tid, Ub[tid * m + ldc(modes + k - 1)]);
+                load_ucol(k);
                 const uint32_t gk = kXAddr + 8u * (uint32_t)((((n - 1 - k) & 1) == 0) ? 0 : R);
                 const uint32_t gkm1 = kXAddr + 8u * (uint32_t)((((n - k) & 1) == 0) ? 0 : R);
                 const LayerDev Lkm1 = layer(Ls, k - 1);
@@ -776,7 +864,7 @@ __global__ __launch_bounds__(BLOCK) void fused_bwd_kernel(int m, const LayerDev*
             const int j = q / m, i = q % m;
             float2 v = c_zero();
             for (int k = 1; k <= n; ++k)
-                if (ldc(modes + k - 1) == i) v = c_add(v, lds_ld(GUacc + 8u * (uint32_t)((k - 1) * 32 + j)));
+                if (mode_of(k - 1) == i) v = c_add(v, lds_ld(GUacc + 8u * (uint32_t)((k - 1) * 32 + j)));
             gUb[q] = v;
         }
         __syncthreads();
@@ -921,7 +1009,10 @@ void* pick_bwd(int block, int m, int64_t Np, bool restricted) {
 }
 
 size_t bwd_lds_for_block(const slos_plan_s& P, int n_max, int block) {
-    return (size_t)(lds_bwd_states(P, n_max) + kUcolSlots + (block / 64) * 32 + kMaxPhotons * 32) * sizeof(float2);
+    // + the staged U [m][m] and the int rows (two minoff rows, the photon modes)
+    const size_t rows = (size_t)(2 * (P.m + 1) + kMaxPhotons) * 4;
+    return (size_t)(lds_bwd_states(P, n_max) + kUcolSlots + (block / 64) * 32 + kMaxPhotons * 32 + P.m * P.m) *
+               sizeof(float2) + rows;
 }
 
 int grid_for(const slos_plan_s& P, const void* fn, int block, size_t lds, int B) {

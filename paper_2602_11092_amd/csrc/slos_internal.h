@@ -271,6 +271,9 @@ __device__ __forceinline__ float buf_ldf_stream(__amdgpu_buffer_rsrc_t r, uint32
 typedef __attribute__((address_space(3))) float lds_f32;
 __device__ __forceinline__ float lds_ldf(uint32_t a) { return *(const lds_f32*)(size_t)a; }
 __device__ __forceinline__ void lds_stf(uint32_t a, float v) { *(lds_f32*)(size_t)a = v; }
+typedef __attribute__((address_space(3))) int lds_i32;
+__device__ __forceinline__ int lds_ldi(uint32_t a) { return *(const lds_i32*)(size_t)a; }
+__device__ __forceinline__ void lds_sti(uint32_t a, int v) { *(lds_i32*)(size_t)a = v; }
 
 
 // Calls f(mode) once per photon of state t of photon layer L (k photons),

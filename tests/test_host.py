@@ -90,6 +90,26 @@ def test_transition_tables_against_enumeration(m, k):
         assert minoff[c] == first
 
 
+@pytest.mark.parametrize("m,k", [(2, 2), (5, 3), (8, 4), (12, 5), (20, 5), (24, 3)])
+def test_successor_below_the_smallest_mode_is_a_shift(m, k):
+    # the fused adjoint forms rank(t' + e_j) for a mode j below the smallest
+    # occupied mode of t' as t' + minoff_k(j+1) - N_{k-1} (the states of layer
+    # k whose smallest mode j holds one photon end that mode's block, in the
+    # order of t'); checked against the successor table and, for small
+    # spaces, against the oracle's ranking
+    _, succ, _, minoff = B.slos_transition_tables(m, k)
+    _, _, _, minoff_p = B.slos_transition_tables(m, k - 1, want_succ=False)
+    Nkm1 = math.comb(m + k - 2, k - 1)
+    for j in range(m):
+        t = np.arange(minoff_p[j + 1], Nkm1)
+        assert np.array_equal(succ[j, t], t + minoff[j + 1] - Nkm1)
+        if m <= 8:
+            for r in t:
+                tp = O.fock_unrank(m, k - 1, int(r)).copy()
+                tp[j] += 1
+                assert O.fock_rank(m, k, tp) == r + minoff[j + 1] - Nkm1
+
+
 def test_transition_table_edge_counts():
     # every (k-1)-photon state has m successors, so layer k has m * N_{k-1} edges
     for m, k in [(5, 3), (7, 4), (20, 3)]:
