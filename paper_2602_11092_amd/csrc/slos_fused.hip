@@ -706,10 +706,13 @@ __global__ __launch_bounds__(BLOCK) void fused_bwd_kernel(int m, const LayerDev*
         if (n == 1) {
             // g_1[j] is G_U[j][i_1] itself (d_0 = 1)
             if (tid < m) {
-                const float c = ldg(layer(Ls, 1).nrm + tid) * innorm;
-                const float2 v = PROBS ? c_scale(lds_ld(Ust + 8u * (uint32_t)(tid * m + mode_of(0))), 2.f * ((const float*)gin)[off + tid] * c * c)
-                                       : c_scale(((const float2*)gin)[off + tid], c);
-                lds_st(GUacc + 8u * tid, v);
+                // (addresses formed here: hoisted out of the sample loop they would
+                // hold registers through the whole kernel)
+                const int j = fresh_v(tid);
+                const float c = ldg(layer(Ls, 1).nrm + j) * innorm;
+                const float2 v = PROBS ? c_scale(lds_ld(Ust + 8u * (uint32_t)(j * m + mode_of(0))), 2.f * ((const float*)gin)[off + j] * c * c)
+                                       : c_scale(((const float2*)gin)[off + j], c);
+                lds_st(GUacc + 8u * j, v);
             }
             __syncthreads();
         } else if (n >= 2) {
@@ -807,7 +810,8 @@ __global__ __launch_bounds__(BLOCK) void fused_bwd_kernel(int m, const LayerDev*
             // ---- lower layers.  d_0..d_{n-2} stored after g_{n-1} (layer k at
             // Np + number of states with < k photons); g ping-pongs between 0 and R.
             const int R = Np + (int)Lp.cum;
-            if (tid == 0) lds_st(kXAddr + 8u * (uint32_t)Np, make_float2(1.f, 0.f));
+            // d_0 = 1 (the constant formed here, not kept in registers from the kernel entry)
+            if (tid == 0) lds_st(kXAddr + 8u * (uint32_t)Np, make_float2(__int_as_float(fresh_v(0x3f800000)), 0.f));
             __syncthreads();
             for (int k = 1; k <= n - 2; ++k) {
                 load_ucol(k);
@@ -853,7 +857,13 @@ __global__ __launch_bounds__(BLOCK) void fused_bwd_kernel(int m, const LayerDev*
                             if (tp < Nkm1) lds_st(gkm1 + 8u * (uint32_t)tp, acc[s]);
                         }
                     }
-                    lower_h<BLOCK, MMAX, RS>(m, Nkm1, rsk, gsk, gk, dkm1, GUacc + 8u * (uint32_t)((k - 1) * 32));
+                    if (!RS && k == 1) {
+                        // layer 1 is e_0 .. e_{m-1} in rank order and d_0 = 1:
+                        // G_U[j][i_1] = g_1[j]
+                        if (tid < m) lds_st(GUacc + 8u * (uint32_t)tid, lds_ld(gk + 8u * (uint32_t)tid));
+                    } else {
+                        lower_h<BLOCK, MMAX, RS>(m, Nkm1, rsk, gsk, gk, dkm1, GUacc + 8u * (uint32_t)((k - 1) * 32));
+                    }
                 }
                 __syncthreads();
             }
