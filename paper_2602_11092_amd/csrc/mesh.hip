@@ -230,13 +230,17 @@ __global__ __launch_bounds__(256) void mesh_bwd_reduce_kernel(int m, int B, cons
 }
 
 // Reverse column sweeps of both factors.  Thread layout as in mesh_factors_kernel.
+// Each step keeps its MZIs' reduced products G_T (four complex numbers per
+// MZI) in LDS; the gradients are formed from them after the sweep, one
+// thread per MZI, off the sequential path.
 __global__ __launch_bounds__(1024) void mesh_bwd_sweep_kernel(int m, const float* __restrict__ theta,
                                                               const float2* __restrict__ Wf,
                                                               const Mzi* __restrict__ Tm,
                                                               const float2* __restrict__ Gf,
                                                               float* __restrict__ gtheta) {
     __shared__ float2 X[2][32][33], G[2][32][33];
-    __shared__ Mzi Ts[496];  // every MZI record, staged once (the sweep's steps read them in order)
+    __shared__ Mzi Ts[496];    // every MZI record, staged once (the sweep's steps read them in order)
+    __shared__ float2 GT[496][4];  // each MZI's G_T
     const int tid = threadIdx.x;
     const int half = tid >> 9, pr = (tid >> 5) & 15, col = tid & 31;
     for (int q = tid; q < num_mzi(m); q += 1024) Ts[q] = Tm[q];
@@ -275,24 +279,8 @@ __global__ __launch_bounds__(1024) void mesh_bwd_sweep_kernel(int m, const float
                 p[e].y = sum32(p[e].y);
             }
             if (col == 31) {
-                const float2 eth = T.eth;
-                const float2 etp = T.etp;
-                // dT/dtheta = 1/2 [[ i e^{i(th+ph)}, -e^{i th} ], [ -e^{i(th+ph)}, -i e^{i th} ]]
-                const float2 d00 = make_float2(-0.5f * etp.y, 0.5f * etp.x);
-                const float2 d01 = make_float2(-0.5f * eth.x, -0.5f * eth.y);
-                const float2 d10 = make_float2(-0.5f * etp.x, -0.5f * etp.y);
-                const float2 d11 = make_float2(0.5f * eth.y, -0.5f * eth.x);
-                float gth = 0.f;
-                gth += p[0].x * d00.x + p[0].y * d00.y;
-                gth += p[1].x * d01.x + p[1].y * d01.y;
-                gth += p[2].x * d10.x + p[2].y * d10.y;
-                gth += p[3].x * d11.x + p[3].y * d11.y;
-                // dT/dphi = [[ i t00, 0 ], [ i t10, 0 ]]
-                const float2 e00 = make_float2(-T.t00.y, T.t00.x);
-                const float2 e10 = make_float2(-T.t10.y, T.t10.x);
-                const float gph = p[0].x * e00.x + p[0].y * e00.y + p[2].x * e10.x + p[2].y * e10.y;
-                gtheta[2 * q] = gth;
-                gtheta[2 * q + 1] = gph;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) GT[q][e] = p[e];
             }
             if (col < m) {
                 X[half][k][col] = r0;
@@ -307,6 +295,28 @@ __global__ __launch_bounds__(1024) void mesh_bwd_sweep_kernel(int m, const float
             }
         }
         __syncthreads();
+    }
+    for (int q = tid; q < num_mzi(m); q += 1024) {
+        const Mzi T = Ts[q];
+        const float2 p0 = GT[q][0], p1 = GT[q][1], p2 = GT[q][2], p3 = GT[q][3];
+        const float2 eth = T.eth;
+        const float2 etp = T.etp;
+        // dT/dtheta = 1/2 [[ i e^{i(th+ph)}, -e^{i th} ], [ -e^{i(th+ph)}, -i e^{i th} ]]
+        const float2 d00 = make_float2(-0.5f * etp.y, 0.5f * etp.x);
+        const float2 d01 = make_float2(-0.5f * eth.x, -0.5f * eth.y);
+        const float2 d10 = make_float2(-0.5f * etp.x, -0.5f * etp.y);
+        const float2 d11 = make_float2(0.5f * eth.y, -0.5f * eth.x);
+        float gth = 0.f;
+        gth += p0.x * d00.x + p0.y * d00.y;
+        gth += p1.x * d01.x + p1.y * d01.y;
+        gth += p2.x * d10.x + p2.y * d10.y;
+        gth += p3.x * d11.x + p3.y * d11.y;
+        // dT/dphi = [[ i t00, 0 ], [ i t10, 0 ]]
+        const float2 e00 = make_float2(-T.t00.y, T.t00.x);
+        const float2 e10 = make_float2(-T.t10.y, T.t10.x);
+        const float gph = p0.x * e00.x + p0.y * e00.y + p2.x * e10.x + p2.y * e10.y;
+        gtheta[2 * q] = gth;
+        gtheta[2 * q + 1] = gph;
     }
 }
 
