@@ -26,12 +26,14 @@
 // it gathers g_k[t' + e_j] from LDS.  The top layer is consumed in chunks of
 // consecutive "smallest occupied mode" blocks: for a chunk of smallest modes
 // [a, b) the pairs (t', j) whose successor falls in it are exactly
-// {min(t') in [a,b), j >= a} (whole groups of four modes per owned state,
-// G_U partials per lane in registers, one fixed-order DPP reduction per
-// layer) and {min(t') >= b, a <= j < b} (a few modes, one at a time, each
-// mode's G_U share reduced per wave), two contiguous ranges of t', so the
-// pull stays a plain gather from LDS.  The smaller lower layers take g_{k-1}
-// from the same pull and G_U from mode-per-wave dot products.
+// {min(t') in [a,b), j >= a} (whole groups of four modes per owned state)
+// and {min(t') >= b, a <= j < b} (a few modes, one at a time; there the
+// successor's rank is t' plus a per-mode constant, so no table is read),
+// two contiguous ranges of t', so the pull stays a plain gather from LDS.
+// Both keep the G_U partials per lane in registers, reduced in a fixed order
+// once per layer, and a wave skips the owned slots where none of its lanes is
+// in range.  The smaller lower layers take g_{k-1} from the same pull and
+// G_U from mode-per-wave dot products.
 #include <type_traits>
 
 #include "slos_internal.h"
