@@ -267,6 +267,34 @@ def test_fused_adjoint_every_workgroup_size(block):
         assert rel_err(G[b], ref) <= G_RTOL, (block, b, rel_err(G[b], ref))
 
 
+@pytest.mark.parametrize("m,n,block", [(20, 5, 512), (20, 5, 768), (20, 5, 1024), (16, 5, 1024),
+                                         (24, 4, 512), (32, 3, 256), (32, 3, 512)])
+def test_fused_adjoint_full_slots_and_wide_columns(m, n, block):
+    """The fused adjoint where layer n-1 fills most owned slots (18 per thread
+    at 512 threads for m=20, n=5) and for the 24- and 32-mode instances,
+    with bunched inputs, against the oracle: every chunk, the per-wave slot
+    skipping and the table-free narrow pull run over full ranges."""
+    rng = np.random.default_rng(7000 + 97 * m + n + block)
+    Bn = 3
+    U = W.haar_unitaries(rng, Bn, m).astype(np.complex64)
+    occ = np.zeros((Bn, m), dtype=np.int32)
+    for b in range(Bn):
+        for i in rng.choice(m, size=n, replace=True):
+            occ[b, i] += 1
+    say("fused adjoint m", m, "n", n, "block", block)
+    batch = B.Batch(B.Plan(m, n), occ)
+    batch.set_config(B.OP_PROBS_BACKWARD, B.VARIANT_FUSED, block)
+    assert batch.get_config(B.OP_PROBS_BACKWARD) == (B.VARIANT_FUSED, block)
+    gp = rng.random(batch.out_len).astype(np.float32)
+    G = B.fock_probs_backward(batch, to_dev_c64(U), torch.from_numpy(gp).to(DEV))
+    torch.cuda.synchronize()
+    G = G.cpu().numpy()
+    for b in range(Bn):
+        sl = slice(batch.offsets[b], batch.offsets[b + 1])
+        ref = O.probs_grad(widen(U[b]), occ[b], gp[sl].astype(np.float64))
+        assert rel_err(G[b], ref) <= G_RTOL, (m, n, block, b, rel_err(G[b], ref))
+
+
 def test_autograd_resolves_lazy_conjugate_gradients():
     # L = Re(sum conj(a) w) hands the amplitude adjoint a lazily conjugated
     # gradient view; the wrapper must pass its values, not its raw memory
