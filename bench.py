@@ -76,10 +76,11 @@ def replay_percentiles(run, stream, n=100):
             "p90_ms": round(float(np.percentile(t, 90)), 5)}
 
 
-def roofline_of(kernel, avg_ms, flops, nbytes):
+def roofline_of(kernel, avg_ms, flops, nbytes, workload, config=None):
     """Roofline entry of one kernel from its algorithmic flops and HBM bytes
     per launch: the bound is the resource it comes closer to saturating
-    (FP32 vector ALUs without packed math, or HBM)."""
+    (FP32 vector ALUs without packed math, or HBM).  `config` is the
+    autotuned configuration that was timed on `workload`, if any."""
     alu = flops / (avg_ms * 1e-3) / 1e12
     hbm = nbytes / (avg_ms * 1e-3) / 1e9
     fa, fh = alu / ALU_PEAK_TFLOPS, hbm / HBM_PEAK_GBS
@@ -90,7 +91,7 @@ def roofline_of(kernel, avg_ms, flops, nbytes):
                   "frac": round(fa, 4)})
     else:
         r.update({"bound": "hbm", "achieved": round(hbm, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(fh, 4)})
-    r["traffic"] = load_traffic(kernel)
+    r["traffic"] = load_traffic(kernel, workload, config)
     return r
 
 
@@ -242,7 +243,7 @@ def main():
         dur, flops, nbytes = k_bwd, flop_bwd, bwd_bytes
     else:
         dur, flops, nbytes = k_fwd, flop_fwd, fwd_bytes
-    roofline = roofline_of(dominant, dur, flops, nbytes)
+    roofline = roofline_of(dominant, dur, flops, nbytes, args.workload, tuned_cfg.get(dominant))
     hbm_frac_step = step_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS
 
     # ---- readout + cross-entropy + its backward, for the full training step
@@ -488,7 +489,9 @@ def bench_other(args, wl, dev):
     work = {"fock_probs": (8.0 * edges, u_bytes + 4 * amps),
             "fock_probs_backward": (8.0 * 3 * edges, 2 * u_bytes + 4 * amps)}
     dominant = max((k for k in kernels if k in work), key=lambda k: kernels[k])
-    roofline = roofline_of(dominant, kernels[dominant], *work[dominant])
+    dom_op = {"fock_probs": B.OP_PROBS, "fock_probs_backward": B.OP_PROBS_BACKWARD}[dominant]
+    roofline = roofline_of(dominant, kernels[dominant], *work[dominant], args.workload,
+                           config=cfg_name(tuned[dom_op]) if dom_op in tuned else None)
     torch.cuda.synchronize()
     cpu = None if args.no_cpu_baseline else cpu_baseline_other(wl, U, p, gU, gp)
     out = {"metric": "Fock amplitudes/sec, batched %s (%s)" % ("fwd+bwd" if wl.backward else "fwd", wl.name),
@@ -774,15 +777,18 @@ def bench_extension(args, dev):
     print(json.dumps(line), flush=True)
 
 
-def load_traffic(kernel):
+def load_traffic(kernel, workload, config=None):
     """HBM bytes per launch from the committed counter summary, if it was taken
-    on the current kernel sources (else None)."""
+    on the current kernel sources, on the same workload and (for an autotuned
+    op) on the configuration being timed (else None)."""
     path = os.path.join(ROOT, "profiles", "traffic_%s.json" % kernel)
     if not os.path.exists(path):
         return None
     try:
         d = json.load(open(path))
         if d.get("src_sha256") != sources_sha256():
+            return None
+        if d.get("workload") != workload or (config is not None and d.get("config") != config):
             return None
         return d.get("bytes_per_launch")
     except Exception:

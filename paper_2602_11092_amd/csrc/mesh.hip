@@ -4,9 +4,12 @@
 //
 // Rectangular mesh: column c holds MZIs on pairs (k, k+1), k = c mod 2 + 2p.
 // MZIs of one column touch disjoint pairs, so a column is applied to all
-// rows at once.  W1 = columns [0, m/2), W2 = the rest.  All 2x2 MZI matrices
-// are formed in parallel first; one workgroup then sweeps the columns of both
-// factors (one half each) and every sample forms U_b = W2 diag(e^{i enc x_b}) W1.
+// rows at once.  W1 = columns [0, m/2), W2 = the rest.  In the forward every
+// workgroup (one per sample) forms all 2x2 MZI matrices and sweeps the columns
+// of both factors in its own LDS, which keeps a separate single-workgroup
+// launch off the serial chain, then forms U_b = W2 diag(e^{i enc x_b}) W1.
+// The adjoint forms the factors once, in one workgroup, for its per-sample
+// kernel (there the per-workgroup sweep costs more than the launch).
 // The adjoint computes each sample's contribution to dL/dW1 and dL/dW2 (and
 // dL/dx_b) in its own workgroup, sums them over the batch in a fixed order,
 // then sweeps the columns backwards, recovering each column's input as
@@ -89,19 +92,21 @@ __host__ __device__ inline MeshWs mesh_ws_split(void* ws, int m) {
     return w;
 }
 
-// Builds W1 (half 0) and W2 (half 1) into Wout[2][m][m] and stores every
-// MZI matrix in Tout.  1024 threads: half = tid / 512, pair slot =
-// (tid % 512) / 32, column of W = tid % 32.
-__global__ __launch_bounds__(1024) void mesh_factors_kernel(int m, const float* __restrict__ theta,
-                                                            float2* __restrict__ Wout, Mzi* __restrict__ Tout) {
-    __shared__ float2 W[2][32][33];
-    __shared__ Mzi Ts[496];
+// Builds W1 (W[0]) and W2 (W[1]) in LDS and every MZI matrix in Ts.  Needs
+// a workgroup of 1024 threads: half = tid / 512, pair slot = (tid % 512) / 32,
+// column of W = tid % 32.  With Wout and Tout non-NULL, workgroup 0 also
+// stores the factors in Wout[2][m][m] and the MZI records in Tout (the
+// adjoint's per-sample kernel and sweep read them).
+__device__ __forceinline__ void factors_into_lds(int m, const float* __restrict__ theta, float2 (&W)[2][32][33],
+                                                 Mzi (&Ts)[496], float2* __restrict__ Wout,
+                                                 Mzi* __restrict__ Tout) {
     const int tid = threadIdx.x;
+    const bool store = Wout != nullptr && blockIdx.x == 0;
     const int nm = num_mzi(m);
     for (int q = tid; q < nm; q += 1024) {
         const Mzi T = mzi(theta[2 * q], theta[2 * q + 1]);
         Ts[q] = T;
-        Tout[q] = T;
+        if (store) Tout[q] = T;
     }
     const int half = tid >> 9, pr = (tid >> 5) & 15, col = tid & 31;
     for (int r = pr; r < 32; r += 16) W[half][r][col] = make_float2((r == col) ? 1.f : 0.f, 0.f);
@@ -123,19 +128,33 @@ __global__ __launch_bounds__(1024) void mesh_factors_kernel(int m, const float* 
         }
         __syncthreads();
     }
-    for (int r = pr; r < m; r += 16)
-        if (col < m) Wout[((size_t)half * m + r) * m + col] = W[half][r][col];
+    if (store)
+        for (int r = pr; r < m; r += 16)
+            if (col < m) Wout[((size_t)half * m + r) * m + col] = W[half][r][col];
 }
 
-// U_b = W2 diag(S_b) W1, one sample per block.
-__global__ __launch_bounds__(256) void mesh_apply_kernel(int m, const float2* __restrict__ Wf,
+// The factors alone (the adjoint's per-sample kernel reads them from the
+// workspace): one workgroup of 1024 threads.
+__global__ __launch_bounds__(1024) void mesh_factors_kernel(int m, const float* __restrict__ theta,
+                                                            float2* __restrict__ Wout, Mzi* __restrict__ Tout) {
+    __shared__ float2 W[2][32][33];
+    __shared__ Mzi Ts[496];
+    factors_into_lds(m, theta, W, Ts, Wout, Tout);
+}
+
+// U_b = W2 diag(S_b) W1, one sample per block (the factors formed in LDS).
+constexpr int kMeshNT = 1024;  // threads of mesh_apply_kernel: the layout factors_into_lds needs
+
+__global__ __launch_bounds__(kMeshNT) void mesh_apply_kernel(int m, const float* __restrict__ theta,
                                                          const float* __restrict__ x, float enc,
                                                          float2* __restrict__ U) {
-    __shared__ float2 W2[32][33];
+    __shared__ float2 W[2][32][33];
+    __shared__ Mzi Ts[496];
     __shared__ float2 A[32][33];  // diag(S) W1
     const int b = blockIdx.x;
     const int tid = threadIdx.x;
-    for (int q = tid; q < m * m; q += 256) {
+    factors_into_lds(m, theta, W, Ts, nullptr, nullptr);
+    for (int q = tid; q < m * m; q += kMeshNT) {
         const int r = q / m, c = q % m;
         float2 s = make_float2(1.f, 0.f);
         if (x) {
@@ -143,14 +162,13 @@ __global__ __launch_bounds__(256) void mesh_apply_kernel(int m, const float2* __
             sincosf(enc * x[(size_t)b * m + r], &sn, &cs);
             s = make_float2(cs, sn);
         }
-        A[r][c] = cmul(s, Wf[(size_t)r * m + c]);
-        W2[r][c] = Wf[(size_t)m * m + q];
+        A[r][c] = cmul(s, W[0][r][c]);
     }
     __syncthreads();
-    for (int q = tid; q < m * m; q += 256) {
+    for (int q = tid; q < m * m; q += kMeshNT) {
         const int j = q / m, i = q % m;
         float2 acc = c_zero();
-        for (int k = 0; k < m; ++k) c_fma(acc, W2[j][k], A[k][i]);
+        for (int k = 0; k < m; ++k) c_fma(acc, W[1][j][k], A[k][i]);
         U[(size_t)b * m * m + q] = acc;
     }
 }
@@ -229,7 +247,8 @@ __global__ __launch_bounds__(256) void mesh_bwd_reduce_kernel(int m, int B, cons
     if (r == 0 && e < E) G[e] = red[threadIdx.x];
 }
 
-// Reverse column sweeps of both factors.  Thread layout as in mesh_factors_kernel.
+// Reverse column sweeps of both factors.  1024 threads: half = tid / 512,
+// pair slot = (tid % 512) / 32, column of W = tid % 32.
 // Each step keeps its MZIs' reduced products G_T (four complex numbers per
 // MZI) in LDS; the gradients are formed from them after the sweep, one
 // thread per MZI, off the sequential path.
@@ -378,9 +397,7 @@ extern "C" int mesh_to_unitary(int m, int B, const float* theta, const float* x,
     if (!theta || !U) return fail(SLOS_EINVAL, "mesh_to_unitary: NULL pointer");
     if (!ws || ws_bytes < mesh_ws(m, B)) return fail(SLOS_EWORKSPACE, "mesh_to_unitary: workspace too small");
     hipStream_t s = (hipStream_t)stream;
-    MeshWs w = mesh_ws_split(ws, m);
-    hipLaunchKernelGGL(mesh_factors_kernel, dim3(1), dim3(1024), 0, s, m, theta, w.W, w.T);
-    hipLaunchKernelGGL(mesh_apply_kernel, dim3(B), dim3(256), 0, s, m, (const float2*)w.W, x, enc_scale, (float2*)U);
+    hipLaunchKernelGGL(mesh_apply_kernel, dim3(B), dim3(kMeshNT), 0, s, m, theta, x, enc_scale, (float2*)U);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(SLOS_EHIP, std::string("mesh_to_unitary launch: ") + hipGetErrorString(e));
     return SLOS_OK;

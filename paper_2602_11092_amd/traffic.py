@@ -3,14 +3,19 @@ runs of the benchmark (one with FETCH_SIZE, one with WRITE_SIZE, both with
 the benchmark's --copy-probe), scaled by what the same counters read for the
 probe's elementwise kernel of known size (1 GiB read, 1 GiB written).
 
-    python -m paper_2602_11092_amd.traffic FETCH_DB WRITE_DB OUT_DIR "<command>"
+    python -m paper_2602_11092_amd.traffic FETCH_DB WRITE_DB OUT_DIR WORKLOAD "<command>"
 
 writes OUT_DIR/traffic_<entry point>.json (read by bench.py while the kernel
-sources are unchanged) and OUT_DIR/traffic_<entry point>.txt.
+sources are unchanged and it times the same workload and configuration) and
+OUT_DIR/traffic_<entry point>.txt.  Both runs must time the same kernel
+instance (give them the same --autotune-cache, written by a plain benchmark
+run): counter collection serialises the launches, so an autotuner timing
+under it may pick another instance.
 """
 import hashlib
 import json
 import os
+import re
 import sqlite3
 import sys
 
@@ -18,11 +23,30 @@ import sys
 KERNELS = {
     "fock_probs": ("fused_fwd_kernel", "fused_pairs_fwd_kernel"),
     "fock_probs_backward": ("fused_bwd_kernel",),
-    "mesh_to_unitary": ("mesh_factors_kernel",),
+    "mesh_to_unitary": ("mesh_apply_kernel",),
     "mesh_to_unitary_backward": ("mesh_bwd_sweep_kernel",),
 }
 PROBE = "neg_kernel"
 PROBE_BYTES = float(1 << 30)
+
+
+def config_of(symbol):
+    """The autotuner's name of a SLOS kernel instance ('variant/block' or
+    'fused-pairs/block/tile'), read from its template arguments; None for
+    other kernels."""
+    mt = re.search(r"(fused_pairs_fwd_kernel|fused_fwd_kernel|fused_bwd_kernel)<(\d+), (\d+)(?:, (\d+))?", symbol)
+    if not mt:
+        return None
+    if mt.group(1) == "fused_pairs_fwd_kernel":
+        return "fused-pairs/%s/%s" % (mt.group(2), mt.group(4))
+    return "fused/%s" % mt.group(2)
+
+
+def dominant(counts, frags):
+    """(name, (mean KiB, dispatches)) of the instance with the most dispatches
+    among the kernels whose names hold one of `frags`, or None."""
+    cands = sorted(((k, v) for k, v in counts.items() if any(f in k for f in frags)), key=lambda kv: -kv[1][1])
+    return cands[0] if cands else None
 
 
 def per_dispatch_kib(db, counter):
@@ -44,7 +68,7 @@ def sources_sha256(root):
     return h.hexdigest()
 
 
-def main(fetch_db, write_db, out_dir, command):
+def main(fetch_db, write_db, out_dir, workload, command):
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     fetch = per_dispatch_kib(fetch_db, "FETCH_SIZE")
     write = per_dispatch_kib(write_db, "WRITE_SIZE")
@@ -58,21 +82,25 @@ def main(fetch_db, write_db, out_dir, command):
     for entry, frags in KERNELS.items():
         # the instance the timed step runs: the one with the most dispatches
         # (the autotuner launches the others a few times each)
-        fs = sorted(((k, v) for k, v in fetch.items() if any(f in k for f in frags)), key=lambda kv: -kv[1][1])
-        ws = [(k, v) for k, v in write.items() if fs and k == fs[0][0]]
+        fs, ws = dominant(fetch, frags), dominant(write, frags)
         if not fs or not ws:
             continue
-        f_kib, nf = fs[0][1]
-        w_kib, nw = ws[0][1]
+        if fs[0] != ws[0]:
+            raise SystemExit("%s: the counter runs timed different instances (%s / %s); give both the same "
+                             "--autotune-cache" % (entry, fs[0], ws[0]))
+        f_kib, nf = fs[1]
+        w_kib, nw = ws[1]
         rd = f_kib * 1024.0 * kf
         wr = w_kib * 1024.0 * kw
-        d = {"kernel": fs[0][0], "entry_point": entry, "fetch_kib_raw": f_kib, "write_kib_raw": w_kib,
+        d = {"kernel": fs[0], "config": config_of(fs[0]), "workload": workload, "entry_point": entry, "fetch_kib_raw": f_kib, "write_kib_raw": w_kib,
              "fetch_scale": kf, "write_scale": kw, "read_bytes_per_launch": rd, "write_bytes_per_launch": wr,
              "bytes_per_launch": rd + wr, "dispatches": [nf, nw], "src_sha256": sha, "command": command}
         with open(os.path.join(out_dir, "traffic_%s.json" % entry), "w") as f:
             json.dump(d, f, indent=1)
         with open(os.path.join(out_dir, "traffic_%s.txt" % entry), "w") as f:
-            f.write("HBM traffic of %s (%s), per launch\n" % (entry, fs[0][0][:90]))
+            f.write("HBM traffic of %s (%s), per launch, workload %s\n" % (entry, fs[0][:90], workload))
+            if d["config"]:
+                f.write("configuration: %s\n" % d["config"])
             f.write("command: %s\n" % command)
             f.write("FETCH_SIZE %.1f KiB raw x %.4f (probe calibration) = %.3f MB read\n" % (f_kib, kf, rd / 1e6))
             f.write("WRITE_SIZE %.1f KiB raw x %.4f (probe calibration) = %.3f MB written\n" % (w_kib, kw, wr / 1e6))
@@ -81,4 +109,4 @@ def main(fetch_db, write_db, out_dir, command):
 
 
 if __name__ == "__main__":
-    main(*sys.argv[1:5])
+    main(*sys.argv[1:6])
