@@ -356,6 +356,30 @@ def plain_path(B, wl, theta, x, gp, plan, N, dev, stream, ms_batched):
                        "mostly launch overhead"}
 
 
+def cpu_model():
+    """The host CPU's model name (first processor in /proc/cpuinfo), or None."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def omp_threads(n):
+    """Sets the OpenMP thread count of the calling thread's next parallel
+    regions (the oracle's C code runs in libgomp); False where libgomp
+    cannot be loaded."""
+    import ctypes
+    try:
+        ctypes.CDLL("libgomp.so.1").omp_set_num_threads(int(n))
+        return True
+    except (OSError, AttributeError):
+        return False
+
+
 def cpu_baseline(wl, U, p, gp, gU, N):
     """The FP64 oracle (Ryser permanents and minor permanents) timed on the
     host for a bounded sample of the workload's samples; also the largest
@@ -386,11 +410,22 @@ def cpu_baseline(wl, U, p, gp, gU, N):
     for b in range(1, 1 + S):
         worst = max(worst, one(b))
     dt = time.perf_counter() - t0
+    # the same work for one more sample on one thread
+    single = None
+    b1 = min(S + 1, wl.B - 1)
+    if omp_threads(1):
+        try:
+            t0 = time.perf_counter()
+            O.amplitudes(U64[b1], wl.occ[b1])
+            O.probs_grad(U64[b1], wl.occ[b1], gpn[b1 * N:(b1 + 1) * N])
+            single = N / (time.perf_counter() - t0)
+        finally:
+            omp_threads(threads)
     return {"value": S * N / dt, "unit": "Fock amplitudes/s", "cores": threads, "kind": "oracle",
             "sample": "%d of %d samples, forward amplitudes + minor-permanent gradient, FP64 Ryser, OpenMP" % (
                 S, wl.B),
-            "seconds": round(dt, 2), "max_abs_dp": worst,
-            "grad_rel_err": math.sqrt(gerr[0] / max(gerr[1], 1e-300)),
+            "seconds": round(dt, 2), "cpu_model": cpu_model(), "single_thread_value": single,
+            "max_abs_dp": worst, "grad_rel_err": math.sqrt(gerr[0] / max(gerr[1], 1e-300)),
             "grad_samples": S + 1}
 
 
@@ -544,7 +579,8 @@ def cpu_baseline_other(wl, U, p, gU, gp):
         units += ref.size
         done += 1
     dt = time.perf_counter() - t0
-    res = {"value": units / dt, "unit": "Fock amplitudes/s", "cores": threads, "kind": "oracle",
+    res = {"value": units / dt, "unit": "Fock amplitudes/s", "cores": threads, "cpu_model": cpu_model(),
+           "kind": "oracle",
            "sample": ("%d of %d samples, 300 seeded outputs each" if big else "%d of %d samples, every output") % (
                done, wl.B) + ", FP64 Ryser, OpenMP", "seconds": round(dt, 2), "max_abs_dp": worst}
     if gp is not None:
@@ -770,7 +806,8 @@ def bench_extension(args, dev):
             done += 1
         dt = time.perf_counter() - t0
         per = oracle_units or work / Bn
-        line["cpu_baseline"] = {"value": done * per / dt, "unit": unit, "cores": threads, "kind": "oracle",
+        line["cpu_baseline"] = {"value": done * per / dt, "unit": unit, "cores": threads, "cpu_model": cpu_model(),
+                                "kind": "oracle",
                                 "sample": "%d of %d samples (rows), %d %s each" % (done, Bn, per, unit.split("/")[0]),
                                 "seconds": round(dt, 2),
                                 "max_diff_vs_gpu": worst}
