@@ -654,12 +654,14 @@ template <int BLOCK, int OWN, int MMAX, bool RS>
 __global__ __launch_bounds__(BLOCK) void fused_bwd_kernel(int m, const LayerDev* __restrict__ Ls, BatchDev Bt,
                                                           const float2* __restrict__ U,
                                                           const void* __restrict__ gin,
-                                                          float2* __restrict__ gU, int S, int PROBS) {
+                                                          float2* __restrict__ gU, int S, int PROBS, int KR) {
     constexpr int NW = BLOCK / 64;
     // states per thread in the gathers (register budget: acc and h stay live)
     // (the layer recomputes run while acc and h are dead: the forward's width)
     constexpr int GU = kLU;
     constexpr int GM = BLOCK <= 512 ? 4 : BLOCK <= 768 ? 2 : 1;  // wider gathers where registers allow
+    // KR: layers d_0..d_KR stay in LDS from the first recompute to the lower
+    // layers' pulls, in the last slots of X (KR = -1: none)
     // LDS: ucol | X[S] layers and chunks | Hw[NW][32] | GUacc[16][32] | the
     // sample's U [m][m] | minoff of layers n and n-1 [2][m+1] | photon modes
     extern __shared__ float2 lds[];
@@ -721,22 +723,28 @@ __global__ __launch_bounds__(BLOCK) void fused_bwd_kernel(int m, const LayerDev*
             const LayerDev Ln = layer(Ls, n);
             const LayerDev Lp = layer(Ls, n - 1);
             const int Np = (int)Lp.N;
-            // ---- recompute layers 1..n-1; layer n-1 ends at the start of X
+            // the kept layers d_0..d_KRs sit at E + (states with fewer photons)
+            const int KRs = min(KR, n - 2);
+            const int E = S - (KR >= 0 ? (int)ldc(&Ls[KR + 1].cum) : 0);
+            if (KRs >= 0 && tid == 0) lds_st(kXAddr + 8u * (uint32_t)E, make_float2(__int_as_float(fresh_v(0x3f800000)), 0.f));
+            // ---- recompute layers 1..n-1; layer n-1 ends at the start of X,
+            // the others alternate ends of X[0, E) unless kept
             for (int k = 1; k <= n - 1; ++k) {
                 load_ucol(k);
                 __syncthreads();
                 const LayerDev Lk = layer(Ls, k);
                 const int Nk = (int)Lk.N;
                 const int Nkm1 = (int)ldc(&Ls[k - 1].N);
-                layer_into_lds<BLOCK, GU>(Lk, k, kXAddr + 8u * (uint32_t)((((n - k) & 1) == 0) ? 0 : S - Nkm1),
-                                          kXAddr + 8u * (uint32_t)((((n - 1 - k) & 1) == 0) ? 0 : S - Nk));
+                const int ps = (k - 1 <= KRs) ? E + (int)ldc(&Ls[k - 1].cum) : ((((n - k) & 1) == 0) ? 0 : E - Nkm1);
+                const int cs = (k <= KRs) ? E + (int)Lk.cum : ((((n - 1 - k) & 1) == 0) ? 0 : E - Nk);
+                layer_into_lds<BLOCK, GU>(Lk, k, kXAddr + 8u * (uint32_t)ps, kXAddr + 8u * (uint32_t)cs);
                 __syncthreads();
             }
             // ---- top layer, in chunks of smallest-mode blocks
             load_ucol(n);
             const uint32_t D = kXAddr;                     // d_{n-1}
             const uint32_t C = kXAddr + 8u * (uint32_t)Np;  // the chunk of g_n
-            const int cap = S - Np;
+            const int cap = E - Np;
             const uint32_t gstride = (uint32_t)Np * 16u;  // one group of four successor columns
             const __amdgpu_buffer_rsrc_t rs = buf_rsrc(Ln.succ, (uint32_t)((m + 3) / 4) * gstride);
             const __amdgpu_buffer_rsrc_t rn = buf_rsrc(Ln.nrm, (uint32_t)Ln.N * 4u);
@@ -809,18 +817,19 @@ __global__ __launch_bounds__(BLOCK) void fused_bwd_kernel(int m, const LayerDev*
                 if (tp < Np) lds_st(kXAddr + 8u * (uint32_t)tp, acc[s]);
             }
             reduce_columns<BLOCK, MMAX>(h, m, Hw, GUacc + 8u * (uint32_t)((n - 1) * 32));
-            // ---- lower layers.  d_0..d_{n-2} stored after g_{n-1} (layer k at
-            // Np + number of states with < k photons); g ping-pongs between 0 and R.
+            // ---- lower layers.  d_0..d_{n-2} not kept are recomputed after
+            // g_{n-1} (layer k at Np + number of states with < k photons); g
+            // ping-pongs between 0 and R.
             const int R = Np + (int)Lp.cum;
+            auto dslot = [&](int k) { return (k <= KRs ? E : Np) + (int)ldc(&Ls[k].cum); };
             // d_0 = 1 (the constant formed here, not kept in registers from the kernel entry)
-            if (tid == 0) lds_st(kXAddr + 8u * (uint32_t)Np, make_float2(__int_as_float(fresh_v(0x3f800000)), 0.f));
+            if (KRs < 0 && tid == 0) lds_st(kXAddr + 8u * (uint32_t)Np, make_float2(__int_as_float(fresh_v(0x3f800000)), 0.f));
             __syncthreads();
-            for (int k = 1; k <= n - 2; ++k) {
+            for (int k = max(1, KRs + 1); k <= n - 2; ++k) {
                 load_ucol(k);
                 __syncthreads();
                 const LayerDev Lk = layer(Ls, k);
-                layer_into_lds<BLOCK, GU>(Lk, k, kXAddr + 8u * (uint32_t)(Np + (int)ldc(&Ls[k - 1].cum)),
-                                          kXAddr + 8u * (uint32_t)(Np + (int)Lk.cum));
+                layer_into_lds<BLOCK, GU>(Lk, k, kXAddr + 8u * (uint32_t)dslot(k - 1), kXAddr + 8u * (uint32_t)dslot(k));
                 __syncthreads();
             }
             for (int k = n - 1; k >= 1; --k) {
@@ -828,7 +837,7 @@ __global__ __launch_bounds__(BLOCK) void fused_bwd_kernel(int m, const LayerDev*
                 const uint32_t gk = kXAddr + 8u * (uint32_t)((((n - 1 - k) & 1) == 0) ? 0 : R);
                 const uint32_t gkm1 = kXAddr + 8u * (uint32_t)((((n - k) & 1) == 0) ? 0 : R);
                 const LayerDev Lkm1 = layer(Ls, k - 1);
-                const uint32_t dkm1 = kXAddr + 8u * (uint32_t)(Np + (int)Lkm1.cum);
+                const uint32_t dkm1 = kXAddr + 8u * (uint32_t)dslot(k - 1);
                 const int Nkm1 = (int)Lkm1.N;
                 const uint32_t gsk = (uint32_t)Nkm1 * 16u;
                 const __amdgpu_buffer_rsrc_t rsk = buf_rsrc(ldc(&Ls[k].succ), (uint32_t)((m + 3) / 4) * gsk);
@@ -1131,13 +1140,35 @@ int launch_fused_bwd(const slos_batch_s& Bt, int block, const float2* U, const v
     const int64_t Np = Bt.n_max >= 2 ? P.N[Bt.n_max - 1] : 1;
     void* fn = pick_bwd(block, P.m, Np, restricted_plan(P));
     if (!fn) return fail(SLOS_EUNSUPPORTED, "fused backward: no kernel instance for this shape");
-    const size_t lds = bwd_lds_for_block(P, Bt.n_max, block);
-    hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const size_t base = bwd_lds_for_block(P, Bt.n_max, block);
+    hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)P.max_lds);
+    // keep the smallest layers d_0..d_KR in LDS between the first recompute and
+    // the lower layers' pulls, as far as the spare LDS allows without fewer
+    // workgroups per CU
+    int KR = -1;
+    int64_t kept = 0;
+    size_t lds = base;
+    if (Bt.n_max >= 2) {
+        int per_base = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_base, fn, block, base) != hipSuccess) per_base = 1 << 30;
+        int64_t r = 0;
+        for (int K = 0; K <= Bt.n_max - 2; ++K) {
+            r += P.N[K];
+            const size_t l = base + (size_t)r * sizeof(float2);
+            int pc = 0;
+            if (l > P.max_lds || hipOccupancyMaxActiveBlocksPerMultiprocessor(&pc, fn, block, l) != hipSuccess ||
+                pc < per_base)
+                break;
+            KR = K;
+            kept = r;
+            lds = l;
+        }
+    }
     const int grid = grid_for(P, fn, block, lds, Bt.B);
-    const int S = (int)lds_bwd_states(P, Bt.n_max);
+    const int S = (int)(lds_bwd_states(P, Bt.n_max) + kept);
     int pr = probs ? 1 : 0;
     void* args[] = {(void*)&P.m, (void*)&P.d_layers, (void*)&Bt.dev, (void*)&U, (void*)&gin, (void*)&gU,
-                    (void*)&S, (void*)&pr};
+                    (void*)&S, (void*)&pr, (void*)&KR};
     hipError_t e = hipLaunchKernel(fn, dim3(grid), dim3(block), args, lds, stream);
     if (e != hipSuccess) return fail(SLOS_EHIP, std::string("fused backward launch: ") + hipGetErrorString(e));
     return SLOS_OK;
