@@ -267,6 +267,37 @@ def test_fused_adjoint_every_workgroup_size(block):
         assert rel_err(G[b], ref) <= G_RTOL, (block, b, rel_err(G[b], ref))
 
 
+@pytest.mark.parametrize("block", [256, 512, 768, 1024])
+def test_fused_adjoint_mixed_photon_numbers(block):
+    """One batch with n_b from 0 to 5 photons at m = 10: the smallest layers
+    kept in LDS are sized for the largest n, and a sample with fewer photons
+    keeps fewer of them (at this size the spare LDS can hold all of d_0..d_3,
+    286 states, in which case the n = 5 samples recompute no lower layer)."""
+    rng = np.random.default_rng(777 + block)
+    m = 10
+    ns = [5, 4, 3, 2, 1, 0, 5, 3, 2]
+    occ = np.zeros((len(ns), m), dtype=np.int32)
+    for b, n in enumerate(ns):
+        for i in rng.choice(m, size=n, replace=True):
+            occ[b, i] += 1
+    U = W.haar_unitaries(rng, len(ns), m).astype(np.complex64)
+    say("fused adjoint, mixed photon numbers, block", block)
+    plan = B.Plan(m, 5)
+    batch = B.Batch(plan, occ)
+    batch.set_config(B.OP_PROBS_BACKWARD, B.VARIANT_FUSED, block)
+    gp = rng.random(batch.out_len).astype(np.float32)
+    G = B.fock_probs_backward(batch, to_dev_c64(U), torch.from_numpy(gp).to(DEV))
+    torch.cuda.synchronize()
+    G = G.cpu().numpy()
+    for b, n in enumerate(ns):
+        if n == 0:
+            assert np.abs(G[b]).max() == 0
+            continue
+        sl = slice(batch.offsets[b], batch.offsets[b + 1])
+        ref = O.probs_grad(widen(U[b]), occ[b], gp[sl].astype(np.float64))
+        assert rel_err(G[b], ref) <= G_RTOL, (block, b, n, rel_err(G[b], ref))
+
+
 @pytest.mark.parametrize("m,n,block", [(20, 5, 512), (20, 5, 768), (20, 5, 1024), (16, 5, 1024),
                                          (24, 4, 512), (32, 3, 256), (32, 3, 512)])
 def test_fused_adjoint_full_slots_and_wide_columns(m, n, block):
