@@ -726,7 +726,8 @@ __global__ __launch_bounds__(BLOCK) void fused_bwd_kernel(int m, const LayerDev*
             // the kept layers d_0..d_KRs sit at E + (states with fewer photons)
             const int KRs = min(KR, n - 2);
             const int E = S - (KR >= 0 ? (int)ldc(&Ls[KR + 1].cum) : 0);
-            if (KRs >= 0 && tid == 0) lds_st(kXAddr + 8u * (uint32_t)E, make_float2(__int_as_float(fresh_v(0x3f800000)), 0.f));
+            if (KRs >= 0 && tid == 0)
+                lds_st(kXAddr + 8u * (uint32_t)E, make_float2(__int_as_float(fresh_v(0x3f800000)), 0.f));
             // ---- recompute layers 1..n-1; layer n-1 ends at the start of X,
             // the others alternate ends of X[0, E) unless kept
             for (int k = 1; k <= n - 1; ++k) {
@@ -735,7 +736,8 @@ __global__ __launch_bounds__(BLOCK) void fused_bwd_kernel(int m, const LayerDev*
                 const LayerDev Lk = layer(Ls, k);
                 const int Nk = (int)Lk.N;
                 const int Nkm1 = (int)ldc(&Ls[k - 1].N);
-                const int ps = (k - 1 <= KRs) ? E + (int)ldc(&Ls[k - 1].cum) : ((((n - k) & 1) == 0) ? 0 : E - Nkm1);
+                const int ps =
+                    (k - 1 <= KRs) ? E + (int)ldc(&Ls[k - 1].cum) : ((((n - k) & 1) == 0) ? 0 : E - Nkm1);
                 const int cs = (k <= KRs) ? E + (int)Lk.cum : ((((n - 1 - k) & 1) == 0) ? 0 : E - Nk);
                 layer_into_lds<BLOCK, GU>(Lk, k, kXAddr + 8u * (uint32_t)ps, kXAddr + 8u * (uint32_t)cs);
                 __syncthreads();
@@ -823,13 +825,15 @@ __global__ __launch_bounds__(BLOCK) void fused_bwd_kernel(int m, const LayerDev*
             const int R = Np + (int)Lp.cum;
             auto dslot = [&](int k) { return (k <= KRs ? E : Np) + (int)ldc(&Ls[k].cum); };
             // d_0 = 1 (the constant formed here, not kept in registers from the kernel entry)
-            if (KRs < 0 && tid == 0) lds_st(kXAddr + 8u * (uint32_t)Np, make_float2(__int_as_float(fresh_v(0x3f800000)), 0.f));
+            if (KRs < 0 && tid == 0)
+                lds_st(kXAddr + 8u * (uint32_t)Np, make_float2(__int_as_float(fresh_v(0x3f800000)), 0.f));
             __syncthreads();
             for (int k = max(1, KRs + 1); k <= n - 2; ++k) {
                 load_ucol(k);
                 __syncthreads();
                 const LayerDev Lk = layer(Ls, k);
-                layer_into_lds<BLOCK, GU>(Lk, k, kXAddr + 8u * (uint32_t)dslot(k - 1), kXAddr + 8u * (uint32_t)dslot(k));
+                layer_into_lds<BLOCK, GU>(Lk, k, kXAddr + 8u * (uint32_t)dslot(k - 1),
+                                          kXAddr + 8u * (uint32_t)dslot(k));
                 __syncthreads();
             }
             for (int k = n - 1; k >= 1; --k) {
@@ -1150,7 +1154,8 @@ int launch_fused_bwd(const slos_batch_s& Bt, int block, const float2* U, const v
     size_t lds = base;
     if (Bt.n_max >= 2) {
         int per_base = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_base, fn, block, base) != hipSuccess) per_base = 1 << 30;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_base, fn, block, base) != hipSuccess)
+            per_base = 1 << 30;  // unknown: keep no layers
         int64_t r = 0;
         for (int K = 0; K <= Bt.n_max - 2; ++K) {
             r += P.N[K];

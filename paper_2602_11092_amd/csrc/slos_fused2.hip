@@ -94,6 +94,7 @@ template <int BLOCK, int SU, int SPR>
 __device__ __forceinline__ void gather2_states(const LayerDev& L, int k, int t0, int tlim, uint32_t pb,
                                                f4v (&acc)[SU]) {
     constexpr int SP = SPR < SU ? SPR : SU;
+    static_assert(SU % SP == 0, "states must split evenly into gather sets");
 #pragma unroll
     for (int u = 0; u < SU; ++u) acc[u] = f4v{0.f, 0.f, 0.f, 0.f};
     if (k == 1) {  // d_1[t] = U[t][i_1]
