@@ -626,20 +626,69 @@ __device__ __forceinline__ void lower_h(int m, int Nkm1, __amdgpu_buffer_rsrc_t 
     }
 }
 
-// Sums h[j] over the workgroup (per wave with DPP, then over the waves in a
-// fixed order) into the LDS column at GUcol, j < MMAX (h[j] = 0 for j >= m).
+// One halving exchange of a wave-wide sum of C values per lane: lanes with
+// bit D of the lane index set keep the upper C/2 values, the others the lower
+// C/2, and each adds its partner's (lane ^ D) copy of the half it keeps.
+template <int C, int D, int T>
+__device__ __forceinline__ void halve_across(float (&v)[T], int lane) {
+    const bool up = (lane & D) != 0;
+    const int from = (lane ^ D) << 2;
+#pragma unroll
+    for (int i = 0; i < C / 2; ++i) {
+        const float send = up ? v[i] : v[i + C / 2];
+        const float keep = up ? v[i + C / 2] : v[i];
+        float recv;
+        if constexpr (D >= 16) recv = __int_as_float(__builtin_amdgcn_ds_bpermute(from, __float_as_int(send)));
+        else recv = dpp<0x128>(send);  // row_ror:8: lane ^ 8 within the 16-lane row
+        v[i] = keep + recv;
+    }
+}
+
+// The sums over a wave's 64 lanes of the 2*MMAX floats of h (value 2j is
+// Re h[j], 2j+1 is Im h[j]), written to the wave's row of Hw (float2 per j).
+// Three halving exchanges, with the lanes 32, 16 and 8 away, leave each group
+// of eight lanes (g = lane / 8) with partial sums of the values
+// [g*T/8, (g+1)*T/8); three DPP steps finish them inside the group, and lane
+// 8g writes them.  A fixed order, in about a third of the VALU instructions of
+// one six-step DPP reduction per value.
+template <int MMAX>
+__device__ __forceinline__ void wave_sum_columns(const float2 (&h)[MMAX], uint32_t row) {
+    constexpr int T = 2 * MMAX;
+    static_assert(T % 8 == 0, "three halvings of the values");
+    const int lane = threadIdx.x & 63;
+    float v[T];
+#pragma unroll
+    for (int j = 0; j < MMAX; ++j) {
+        v[2 * j] = h[j].x;
+        v[2 * j + 1] = h[j].y;
+    }
+    halve_across<T, 32>(v, lane);
+    halve_across<T / 2, 16>(v, lane);
+    halve_across<T / 4, 8>(v, lane);
+#pragma unroll
+    for (int i = 0; i < T / 8; ++i) {
+        float x = v[i];
+        x += dpp<0xB1>(x);   // quad_perm [1,0,3,2]
+        x += dpp<0x4E>(x);   // quad_perm [2,3,0,1]
+        x += dpp<0x141>(x);  // row_half_mirror: every lane holds its group's sum
+        v[i] = x;
+    }
+    if ((lane & 7) == 0) {
+        const int g = lane >> 3;
+#pragma unroll
+        for (int i = 0; i < T / 8; ++i) lds_stf(row + 4u * (uint32_t)(g * (T / 8) + i), v[i]);
+    }
+}
+
+// Sums h[j] over the workgroup (per wave, then over the waves in a fixed
+// order) into the LDS column at GUcol, j < MMAX (h[j] = 0 for j >= m).
 // Hw: [NW][32] LDS scratch.
 template <int BLOCK, int MMAX>
 __device__ __forceinline__ void reduce_columns(const float2 (&h)[MMAX], int m, uint32_t Hw, uint32_t GUcol) {
     constexpr int NW = BLOCK / 64;
     const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
-#pragma unroll
-    for (int j = 0; j < MMAX; ++j) {
-        const float re = wave_sum63(h[j].x);
-        const float im = wave_sum63(h[j].y);
-        if (lane == 63) lds_st(Hw + 8u * (uint32_t)(wave * 32 + j), make_float2(re, im));
-    }
+    const int wave = tid >> 6;
+    wave_sum_columns<MMAX>(h, Hw + 8u * (uint32_t)(wave * 32));
     __syncthreads();
     if (tid < m) {
         float2 sum = c_zero();
@@ -1127,7 +1176,7 @@ int launch_fused_fwd(const slos_batch_s& Bt, int block, const float2* U, void* o
         return fail(SLOS_EUNSUPPORTED, "fused forward: click-pattern runs do not fit in LDS");
     void* fn = pick_fwd(block, epi);
     const size_t lds = fwd_lds_for(P, Bt.n_max, block, expect, thr);
-    hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     const int grid = grid_for(P, fn, block, lds, Bt.B);
     const int S = (int)lds_fwd_states(P, Bt.n_max);
     void* args[] = {(void*)&P.m, (void*)&P.d_layers, (void*)&Bt.dev, (void*)&U, (void*)&out, (void*)&S};
@@ -1145,7 +1194,7 @@ int launch_fused_bwd(const slos_batch_s& Bt, int block, const float2* U, const v
     void* fn = pick_bwd(block, P.m, Np, restricted_plan(P));
     if (!fn) return fail(SLOS_EUNSUPPORTED, "fused backward: no kernel instance for this shape");
     const size_t base = bwd_lds_for_block(P, Bt.n_max, block);
-    hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)P.max_lds);
+    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)P.max_lds);
     // keep the smallest layers d_0..d_KR in LDS between the first recompute and
     // the lower layers' pulls, as far as the spare LDS allows without fewer
     // workgroups per CU
