@@ -480,8 +480,16 @@ __device__ __forceinline__ void pull(int lo, int hi, int jlo, int jhi, __amdgpu_
         uint4 sv[NG];
 #pragma unroll
         for (int g = 0; g < NG; ++g) sv[g] = buf_ld4(rs, vo, (uint32_t)g * gstride);
-        const float2 dv = lds_ld(Db + 8u * (uint32_t)tc);
+        float2 dv = lds_ld(Db + 8u * (uint32_t)tc);
         float2 a = elem_get<OWN>(acc, s);
+        // Standard spaces: a lane out of range works on state tc instead, which
+        // is in range, so its successors in [jlo, jhi) lie in the source range
+        // too (finite values); its products are dropped once per slot (d set to
+        // zero for the G_U shares, its accumulator kept) rather than by a select
+        // per gather.  Restricted spaces select per gather, as their tables
+        // mark successors outside the space.
+        const float2 a0 = a;
+        if constexpr (!RS) dv = act ? dv : c_zero();
 #pragma unroll
         for (int g = 0; g < NG; ++g) {
             if (!has(gbits, g)) continue;  // no mode of this group in range (uniform)
@@ -496,10 +504,13 @@ __device__ __forceinline__ void pull(int lo, int hi, int jlo, int jhi, __amdgpu_
             float2 gv[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                bool ok = act;
-                // restricted spaces: a successor outside the space was never formed
-                if constexpr (RS) ok = ok && c[q] != kNoSuccessor;
-                gv[q] = lds_ld(srcb + (ok ? c[q] : zoff));
+                if constexpr (RS) {
+                    // a successor outside the space was never formed
+                    const bool ok = act && c[q] != kNoSuccessor;
+                    gv[q] = lds_ld(srcb + (ok ? c[q] : zoff));
+                } else {
+                    gv[q] = lds_ld(srcb + c[q]);
+                }
             }
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
@@ -508,6 +519,7 @@ __device__ __forceinline__ void pull(int lo, int hi, int jlo, int jhi, __amdgpu_
                 if (WITH_H) c_fma_conj(h[j], dv, gv[q]);
             }
         }
+        if constexpr (!RS) a = act ? a : a0;
         elem_set<OWN>(acc, s, a);
     }
 }
