@@ -551,7 +551,7 @@ __device__ __forceinline__ void pull_narrow(int lo, int hi, int jlo, int jhi, __
     float2 dv[OWN];  // conj(d_{k-1}) of the owned states, read once
 #pragma unroll
     for (int s = 0; s < OWN; ++s) {
-        if (s < s_first) continue;
+        if (s < fresh(s_first)) continue;
         const int tp = fresh_v(tid) + s * BLOCK;
         dv[s] = lds_ld(Db + 8u * (uint32_t)min(max(tp, lo), hi - 1));
     }
@@ -564,7 +564,7 @@ __device__ __forceinline__ void pull_narrow(int lo, int hi, int jlo, int jhi, __
             const uint32_t soff = (uint32_t)(j >> 2) * gstride + 4u * (uint32_t)(j & 3);
 #pragma unroll
             for (int s = 0; s < OWN; ++s) {
-                if (s < s_first) continue;
+                if (s < fresh(s_first)) continue;
                 const int tp = fresh_v(tid) + s * BLOCK;
                 const bool act = tp >= lo && tp < hi;
                 const uint32_t sv = buf_ld1(rs, (uint32_t)min(max(tp, lo), hi - 1) * 16u, soff);
@@ -575,7 +575,7 @@ __device__ __forceinline__ void pull_narrow(int lo, int hi, int jlo, int jhi, __
             const uint32_t dj = srcb + 8u * (uint32_t)(__builtin_amdgcn_readfirstlane(lds_ldi(MOk + 4u * (uint32_t)(j + 1))) - Nkm1);
 #pragma unroll
             for (int s = 0; s < OWN; ++s) {
-                if (s < s_first) continue;
+                if (s < fresh(s_first)) continue;
                 const int tp = fresh_v(tid) + s * BLOCK;
                 const bool act = tp >= lo && tp < hi;
                 g[s] = lds_ld(act ? dj + 8u * (uint32_t)tp : zaddr);
@@ -583,7 +583,7 @@ __device__ __forceinline__ void pull_narrow(int lo, int hi, int jlo, int jhi, __
         }
 #pragma unroll
         for (int s = 0; s < OWN; ++s) {
-            if (s < s_first) continue;
+            if (s < fresh(s_first)) continue;
             c_fma_conj(acc[s], uj, g[s]);
             c_fma_conj(h[j], dv[s], g[s]);
         }
