@@ -19,6 +19,8 @@
 // once the workgroup has finished reading layer k-1.  No atomics: results are
 // bitwise reproducible, and equal to the single-sample kernel's (the same
 // operations in the same order).
+#include <type_traits>
+
 #include "slos_internal.h"
 
 namespace slos {
@@ -90,14 +92,16 @@ __device__ __forceinline__ void gather2_loaded(const uint4 (&e)[SU][NGX], int g0
 
 // acc[u] = the pair's d_k[t0 + u*BLOCK] (u < SU), pulled from layer k-1 at
 // LDS address pb.  Lanes past tlim compute state tlim-1 (callers do not store it).
-template <int BLOCK, int SU, int SPR>
+// KC > 0: k is KC, known when compiling, so every predecessor group's entry
+// count is a constant and no branch on it remains.
+template <int BLOCK, int SU, int SPR, int KC = 0>
 __device__ __forceinline__ void gather2_states(const LayerDev& L, int k, int t0, int tlim, uint32_t pb,
                                                f4v (&acc)[SU]) {
     constexpr int SP = SPR < SU ? SPR : SU;
     static_assert(SU % SP == 0, "states must split evenly into gather sets");
 #pragma unroll
     for (int u = 0; u < SU; ++u) acc[u] = f4v{0.f, 0.f, 0.f, 0.f};
-    if (k == 1) {  // d_1[t] = U[t][i_1]
+    if ((KC > 0 ? KC : k) == 1) {  // d_1[t] = U[t][i_1]
 #pragma unroll
         for (int u = 0; u < SU; ++u) acc[u] = lds_ld4(kCol2Addr + 16u * (uint32_t)min(t0 + u * BLOCK, tlim - 1));
         return;
@@ -107,20 +111,39 @@ __device__ __forceinline__ void gather2_states(const LayerDev& L, int k, int t0,
     uint32_t vo[SU];
 #pragma unroll
     for (int u = 0; u < SU; ++u) vo[u] = (uint32_t)min(t0 + u * BLOCK, tlim - 1) * 16u;
-    int g0 = 0;
-    for (; g0 + 2 <= L.ngrp; g0 += 2) {
-        uint4 e[SU][2];
+    if constexpr (KC > 0) {
+        constexpr int NGRP = (KC + 3) / 4;  // the table's predecessor groups for layer KC
 #pragma unroll
-        for (int u = 0; u < SU; ++u)
+        for (int g0 = 0; g0 + 2 <= NGRP; g0 += 2) {
+            uint4 e[SU][2];
 #pragma unroll
-            for (int h = 0; h < 2; ++h) e[u][h] = buf_ld4(r, vo[u], (uint32_t)(g0 + h) * gstride);
-        gather2_loaded<SU, SP, 2>(e, g0, k, pb, acc);
-    }
-    for (; g0 < L.ngrp; ++g0) {
-        uint4 e[SU][1];
+            for (int u = 0; u < SU; ++u)
 #pragma unroll
-        for (int u = 0; u < SU; ++u) e[u][0] = buf_ld4(r, vo[u], (uint32_t)g0 * gstride);
-        gather2_loaded<SU, SP, 1>(e, g0, k, pb, acc);
+                for (int h = 0; h < 2; ++h) e[u][h] = buf_ld4(r, vo[u], (uint32_t)(g0 + h) * gstride);
+            gather2_loaded<SU, SP, 2>(e, g0, KC, pb, acc);
+        }
+        if constexpr (NGRP % 2 == 1) {
+            uint4 e[SU][1];
+#pragma unroll
+            for (int u = 0; u < SU; ++u) e[u][0] = buf_ld4(r, vo[u], (uint32_t)(NGRP - 1) * gstride);
+            gather2_loaded<SU, SP, 1>(e, NGRP - 1, KC, pb, acc);
+        }
+    } else {
+        int g0 = 0;
+        for (; g0 + 2 <= L.ngrp; g0 += 2) {
+            uint4 e[SU][2];
+#pragma unroll
+            for (int u = 0; u < SU; ++u)
+#pragma unroll
+                for (int h = 0; h < 2; ++h) e[u][h] = buf_ld4(r, vo[u], (uint32_t)(g0 + h) * gstride);
+            gather2_loaded<SU, SP, 2>(e, g0, k, pb, acc);
+        }
+        for (; g0 < L.ngrp; ++g0) {
+            uint4 e[SU][1];
+#pragma unroll
+            for (int u = 0; u < SU; ++u) e[u][0] = buf_ld4(r, vo[u], (uint32_t)g0 * gstride);
+            gather2_loaded<SU, SP, 1>(e, g0, k, pb, acc);
+        }
     }
 }
 
@@ -233,30 +256,52 @@ __global__ __launch_bounds__(BLOCK) void fused_pairs_fwd_kernel(int m, const Lay
                 const __amdgpu_buffer_rsrc_t rb =
                     buf_rsrc(PROBS ? (const void*)((float*)out + offb) : (const void*)((float2*)out + offb),
                              two ? (uint32_t)N * (PROBS ? 4u : 8u) : 0u);
-                for (int t0 = tid; t0 < N; t0 += BLOCK * TU) {
-                    float c[TU];
+                // the last layer, with the photon count as a compile-time constant
+                // where it is small (no branch on a group's entry count)
+                auto last_layer = [&](auto KCc) {
+                    constexpr int KC = decltype(KCc)::value;
+                    for (int t0 = tid; t0 < N; t0 += BLOCK * TU) {
+                        float c[TU];
 #pragma unroll
-                    for (int u = 0; u < TU; ++u) c[u] = buf_ldf(rn, (uint32_t)min(t0 + u * BLOCK, N - 1) * 4u, 0);
-                    f4v acc[TU];
-                    gather2_states<BLOCK, TU, kLP2>(L, k, t0, N, kX2Addr, acc);
+                        for (int u = 0; u < TU; ++u)
+                            c[u] = buf_ldf(rn, (uint32_t)min(t0 + u * BLOCK, N - 1) * 4u, 0);
+                        f4v acc[TU];
+                        gather2_states<BLOCK, TU, kLP2, KC>(L, k, t0, N, kX2Addr, acc);
 #pragma unroll
-                    for (int u = 0; u < TU; ++u) {
-                        const int t = t0 + u * BLOCK;
-                        if (t >= N) continue;
-                        const float cA = c[u] * ina, cB = c[u] * inb;
-                        if (PROBS) {
-                            const float pA = cA * cA * (acc[u].x * acc[u].x + acc[u].y * acc[u].y);
-                            const float pB = cB * cB * (acc[u].z * acc[u].z + acc[u].w * acc[u].w);
-                            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(pA), ra, t * 4, 0, kCpolStream);
-                            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(pB), rb, t * 4, 0, kCpolStream);
-                        } else {
-                            typedef __attribute__((ext_vector_type(2))) unsigned int u2;
-                            const float2 aA = make_float2(acc[u].x * cA, acc[u].y * cA);
-                            const float2 aB = make_float2(acc[u].z * cB, acc[u].w * cB);
-                            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, aA), ra, t * 8, 0, kCpolStream);
-                            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, aB), rb, t * 8, 0, kCpolStream);
+                        for (int u = 0; u < TU; ++u) {
+                            const int t = t0 + u * BLOCK;
+                            if (t >= N) continue;
+                            const float cA = c[u] * ina, cB = c[u] * inb;
+                            if (PROBS) {
+                                const float pA = cA * cA * (acc[u].x * acc[u].x + acc[u].y * acc[u].y);
+                                const float pB = cB * cB * (acc[u].z * acc[u].z + acc[u].w * acc[u].w);
+                                __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(pA), ra, t * 4, 0,
+                                                                      kCpolStream);
+                                __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(pB), rb, t * 4, 0,
+                                                                      kCpolStream);
+                            } else {
+                                typedef __attribute__((ext_vector_type(2))) unsigned int u2;
+                                const float2 aA = make_float2(acc[u].x * cA, acc[u].y * cA);
+                                const float2 aB = make_float2(acc[u].z * cB, acc[u].w * cB);
+                                __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, aA), ra, t * 8, 0,
+                                                                      kCpolStream);
+                                __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, aB), rb, t * 8, 0,
+                                                                      kCpolStream);
+                            }
                         }
                     }
+                };
+                // (two states per thread only: with more, the unrolled gathers
+                // of all their groups exceed the register budget)
+                switch (TU == 2 ? k : 0) {
+                    case 2: last_layer(std::integral_constant<int, 2>{}); break;
+                    case 3: last_layer(std::integral_constant<int, 3>{}); break;
+                    case 4: last_layer(std::integral_constant<int, 4>{}); break;
+                    case 5: last_layer(std::integral_constant<int, 5>{}); break;
+                    case 6: last_layer(std::integral_constant<int, 6>{}); break;
+                    case 7: last_layer(std::integral_constant<int, 7>{}); break;
+                    case 8: last_layer(std::integral_constant<int, 8>{}); break;
+                    default: last_layer(std::integral_constant<int, 0>{}); break;
                 }
             }
             __syncthreads();
