@@ -186,35 +186,46 @@ __device__ __forceinline__ void gather_groups(__amdgpu_buffer_rsrc_t r, const ui
 // acc[u] = d_k of the state whose table row starts at byte vo[u] (row * 16),
 // pulled from layer k-1 at LDS address pb with coefficients U[j][i_k] from
 // the coefficient column.  With k = 1 the row is the state itself.
-template <int SU, int SPR, int NG>
+// KC > 0: k is KC, known when compiling, so every predecessor group's entry
+// count is a constant and no branch on it remains.
+template <int SU, int SPR, int NG, int KC = 0>
 __device__ __forceinline__ void gather_rows(const LayerDev& L, int k, const uint32_t (&vo)[SU], uint32_t pb,
                                             float2 (&acc)[SU]) {
     constexpr int SP = SPR < SU ? SPR : SU;
     static_assert(SU % SP == 0, "states must split evenly into gather sets");
 #pragma unroll
     for (int u = 0; u < SU; ++u) acc[u] = c_zero();
-    if (k == 1) {  // d_1[t] = U[t][i_1]
+    if ((KC > 0 ? KC : k) == 1) {  // d_1[t] = U[t][i_1]
 #pragma unroll
         for (int u = 0; u < SU; ++u) acc[u] = lds_ld(kUcolAddr + (vo[u] >> 1));
         return;
     }
     const uint32_t gstride = (uint32_t)L.N * 16u;
     const __amdgpu_buffer_rsrc_t r = buf_rsrc(L.predv, (uint32_t)L.ngrp * gstride);
-    int g0 = 0;
-    if (NG >= 2)
-        for (; g0 + 2 <= L.ngrp; g0 += 2) gather_groups<SU, SP, 2>(r, vo, gstride, g0, k, pb, acc);
-    for (; g0 < L.ngrp; ++g0) gather_groups<SU, SP, 1>(r, vo, gstride, g0, k, pb, acc);
+    if constexpr (KC > 0) {
+        constexpr int NGRP = (KC + 3) / 4;  // the table's predecessor groups for layer KC
+        constexpr int NPAIR = NG >= 2 ? NGRP / 2 : 0;
+#pragma unroll
+        for (int p = 0; p < NPAIR; ++p) gather_groups<SU, SP, 2>(r, vo, gstride, 2 * p, KC, pb, acc);
+#pragma unroll
+        for (int g = 2 * NPAIR; g < NGRP; ++g) gather_groups<SU, SP, 1>(r, vo, gstride, g, KC, pb, acc);
+    } else {
+        int g0 = 0;
+        if (NG >= 2)
+            for (; g0 + 2 <= L.ngrp; g0 += 2) gather_groups<SU, SP, 2>(r, vo, gstride, g0, k, pb, acc);
+        for (; g0 < L.ngrp; ++g0) gather_groups<SU, SP, 1>(r, vo, gstride, g0, k, pb, acc);
+    }
 }
 
 // acc[u] = d_k of table row t0 + u*BLOCK for u < SU.  Lanes past tlim
 // compute the value of row tlim-1 (callers do not store it).
-template <int BLOCK, int SU, int SPR, int NG>
+template <int BLOCK, int SU, int SPR, int NG, int KC = 0>
 __device__ __forceinline__ void gather_states(const LayerDev& L, int k, int t0, int tlim, uint32_t pb,
                                               float2 (&acc)[SU]) {
     uint32_t vo[SU];
 #pragma unroll
     for (int u = 0; u < SU; ++u) vo[u] = (uint32_t)min(t0 + u * BLOCK, tlim - 1) * 16u;
-    gather_rows<SU, SPR, NG>(L, k, vo, pb, acc);
+    gather_rows<SU, SPR, NG, KC>(L, k, vo, pb, acc);
 }
 
 // One layer of the recursion, LDS to LDS, SU states per thread per iteration.
@@ -378,34 +389,49 @@ __global__ __launch_bounds__(BLOCK) void fused_fwd_kernel(int m, const LayerDev*
                 const __amdgpu_buffer_rsrc_t ro =
                     buf_rsrc(PROBS ? (const void*)((float*)out + off) : (const void*)((float2*)out + off),
                              EXPECT ? 0u : (uint32_t)N * (PROBS ? 4u : 8u));
-                for (int t0 = tid; t0 < N; t0 += BLOCK * kLU) {
-                    float c[kLU];
+                // the last layer with the photon count as a compile-time constant
+                // where it is small (no branch on a group's entry count)
+                auto last_layer = [&](auto KCc) {
+                    constexpr int KC = decltype(KCc)::value;
+                    for (int t0 = tid; t0 < N; t0 += BLOCK * kLU) {
+                        float c[kLU];
 #pragma unroll
-                    for (int u = 0; u < kLU; ++u)
-                        c[u] = buf_ldf(rn, (uint32_t)min(t0 + u * BLOCK, N - 1) * 4u, 0) * innorm;
-                    float2 acc[kLU];
-                    gather_states<BLOCK, kLU, kLP, 2>(L, k, t0, N, kXAddr, acc);
+                        for (int u = 0; u < kLU; ++u)
+                            c[u] = buf_ldf(rn, (uint32_t)min(t0 + u * BLOCK, N - 1) * 4u, 0) * innorm;
+                        float2 acc[kLU];
+                        gather_states<BLOCK, kLU, kLP, 2, KC>(L, k, t0, N, kXAddr, acc);
 #pragma unroll
-                    for (int u = 0; u < kLU; ++u) {
-                        const int t = t0 + u * BLOCK;
-                        if (!EXPECT && t < N) {
-                            if (PROBS) {
-                                const float p = c[u] * c[u] * (acc[u].x * acc[u].x + acc[u].y * acc[u].y);
-                                __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(p), ro, t * 4, 0, kCpolStream);
-                            } else {
-                                const float2 a = c_scale(acc[u], c[u]);
-                                __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(
-                                    __attribute__((ext_vector_type(2))) unsigned int, a), ro, t * 8, 0, kCpolStream);
+                        for (int u = 0; u < kLU; ++u) {
+                            const int t = t0 + u * BLOCK;
+                            if (!EXPECT && t < N) {
+                                if (PROBS) {
+                                    const float p = c[u] * c[u] * (acc[u].x * acc[u].x + acc[u].y * acc[u].y);
+                                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(p), ro, t * 4, 0, kCpolStream);
+                                } else {
+                                    const float2 a = c_scale(acc[u], c[u]);
+                                    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(
+                                        __attribute__((ext_vector_type(2))) unsigned int, a), ro, t * 8, 0, kCpolStream);
+                                }
                             }
                         }
-                    }
-                    if (EXPECT) {
-                        float pv[kLU];
+                        if (EXPECT) {
+                            float pv[kLU];
 #pragma unroll
-                        for (int u = 0; u < kLU; ++u)  // lanes past N add zero
-                            pv[u] = t0 + u * BLOCK < N ? c[u] * c[u] * (acc[u].x * acc[u].x + acc[u].y * acc[u].y) : 0.f;
-                        photons_into_lds<BLOCK, kLU, EPI == 3>(L, k, t0, N, pv, accb);
+                            for (int u = 0; u < kLU; ++u)  // lanes past N add zero
+                                pv[u] = t0 + u * BLOCK < N ? c[u] * c[u] * (acc[u].x * acc[u].x + acc[u].y * acc[u].y) : 0.f;
+                            photons_into_lds<BLOCK, kLU, EPI == 3>(L, k, t0, N, pv, accb);
+                        }
                     }
+                };
+                switch (k) {
+                    case 2: last_layer(std::integral_constant<int, 2>{}); break;
+                    case 3: last_layer(std::integral_constant<int, 3>{}); break;
+                    case 4: last_layer(std::integral_constant<int, 4>{}); break;
+                    case 5: last_layer(std::integral_constant<int, 5>{}); break;
+                    case 6: last_layer(std::integral_constant<int, 6>{}); break;
+                    case 7: last_layer(std::integral_constant<int, 7>{}); break;
+                    case 8: last_layer(std::integral_constant<int, 8>{}); break;
+                    default: last_layer(std::integral_constant<int, 0>{}); break;
                 }
             }
             __syncthreads();
