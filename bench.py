@@ -154,7 +154,7 @@ def main():
     mws = B.mesh_workspace(m, Bn, dev)
     B.mesh_to_unitary(theta, x, wl.enc_scale, out=U, ws=mws)
     # kernel variant and workgroup size per op, picked by timing on this batch
-    tuned = autotune(batch, U, ops=(B.OP_PROBS, B.OP_PROBS_BACKWARD), warmup=2, iters=3, cache=args.autotune_cache)
+    tuned = autotune(batch, U, ops=(B.OP_PROBS, B.OP_PROBS_BACKWARD), warmup=3, iters=10, cache=args.autotune_cache)
     names = VARIANT_NAMES
     tuned_cfg = {op_name: cfg_name(tuned[op])
                  for op, op_name in ((B.OP_PROBS, "fock_probs"), (B.OP_PROBS_BACKWARD, "fock_probs_backward"))}
