@@ -4,12 +4,12 @@
 //
 // Rectangular mesh: column c holds MZIs on pairs (k, k+1), k = c mod 2 + 2p.
 // MZIs of one column touch disjoint pairs, so a column is applied to all
-// rows at once.  W1 = columns [0, m/2), W2 = the rest.  In the forward every
-// workgroup (one per sample) forms all 2x2 MZI matrices and sweeps the columns
-// of both factors in its own LDS, which keeps a separate single-workgroup
-// launch off the serial chain, then forms U_b = W2 diag(e^{i enc x_b}) W1.
-// The adjoint forms the factors once, in one workgroup, for its per-sample
-// kernel (there the per-workgroup sweep costs more than the launch).
+// rows at once.  W1 = columns [0, m/2), W2 = the rest.  For batches that fit
+// one resident round of workgroups, every workgroup of the forward (one per
+// sample) forms all 2x2 MZI matrices and sweeps the columns of both factors
+// in its own LDS, which keeps a separate single-workgroup launch off the
+// serial chain; larger batches form the factors once, in one workgroup, as
+// the adjoint does.  The forward then forms U_b = W2 diag(e^{i enc x_b}) W1.
 // The adjoint computes each sample's contribution to dL/dW1 and dL/dW2 (and
 // dL/dx_b) in its own workgroup, sums them over the batch in a fixed order,
 // then sweeps the columns backwards, recovering each column's input as
@@ -169,6 +169,37 @@ __global__ __launch_bounds__(kMeshNT) void mesh_apply_kernel(int m, const float*
         const int j = q / m, i = q % m;
         float2 acc = c_zero();
         for (int k = 0; k < m; ++k) c_fma(acc, W[1][j][k], A[k][i]);
+        U[(size_t)b * m * m + q] = acc;
+    }
+}
+
+// U_b = W2 diag(S_b) W1, one sample per block, from factors formed once by
+// mesh_factors_kernel (the forward's path for batches beyond one resident
+// round of mesh_apply_kernel workgroups, where sweeping the factors in every
+// workgroup would cost more than the shared launch).
+__global__ __launch_bounds__(256) void mesh_apply_shared_kernel(int m, const float2* __restrict__ Wf,
+                                                                const float* __restrict__ x, float enc,
+                                                                float2* __restrict__ U) {
+    __shared__ float2 W2[32][33];
+    __shared__ float2 A[32][33];  // diag(S) W1
+    const int b = blockIdx.x;
+    const int tid = threadIdx.x;
+    for (int q = tid; q < m * m; q += 256) {
+        const int r = q / m, c = q % m;
+        float2 s = make_float2(1.f, 0.f);
+        if (x) {
+            float sn, cs;
+            sincosf(enc * x[(size_t)b * m + r], &sn, &cs);
+            s = make_float2(cs, sn);
+        }
+        A[r][c] = cmul(s, Wf[(size_t)r * m + c]);
+        W2[r][c] = Wf[(size_t)m * m + q];
+    }
+    __syncthreads();
+    for (int q = tid; q < m * m; q += 256) {
+        const int j = q / m, i = q % m;
+        float2 acc = c_zero();
+        for (int k = 0; k < m; ++k) c_fma(acc, W2[j][k], A[k][i]);
         U[(size_t)b * m * m + q] = acc;
     }
 }
@@ -397,7 +428,19 @@ extern "C" int mesh_to_unitary(int m, int B, const float* theta, const float* x,
     if (!theta || !U) return fail(SLOS_EINVAL, "mesh_to_unitary: NULL pointer");
     if (!ws || ws_bytes < mesh_ws(m, B)) return fail(SLOS_EWORKSPACE, "mesh_to_unitary: workspace too small");
     hipStream_t s = (hipStream_t)stream;
-    hipLaunchKernelGGL(mesh_apply_kernel, dim3(B), dim3(kMeshNT), 0, s, m, theta, x, enc_scale, (float2*)U);
+    // up to one resident round of workgroups (two of 1024 threads per CU),
+    // every workgroup forms the factors itself; beyond that, once, shared
+    int dev = 0, cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(SLOS_EHIP, "mesh_to_unitary: no HIP device");
+    (void)hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (B <= 2 * std::max(cu, 1)) {
+        hipLaunchKernelGGL(mesh_apply_kernel, dim3(B), dim3(kMeshNT), 0, s, m, theta, x, enc_scale, (float2*)U);
+    } else {
+        MeshWs w = mesh_ws_split(ws, m);
+        hipLaunchKernelGGL(mesh_factors_kernel, dim3(1), dim3(1024), 0, s, m, theta, w.W, w.T);
+        hipLaunchKernelGGL(mesh_apply_shared_kernel, dim3(B), dim3(256), 0, s, m, (const float2*)w.W, x, enc_scale,
+                           (float2*)U);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(SLOS_EHIP, std::string("mesh_to_unitary launch: ") + hipGetErrorString(e));
     return SLOS_OK;

@@ -23,7 +23,7 @@ import sys
 KERNELS = {
     "fock_probs": ("fused_fwd_kernel", "fused_pairs_fwd_kernel"),
     "fock_probs_backward": ("fused_bwd_kernel",),
-    "mesh_to_unitary": ("mesh_apply_kernel",),
+    "mesh_to_unitary": ("mesh_apply_kernel", "mesh_apply_shared_kernel"),
     "mesh_to_unitary_backward": ("mesh_bwd_sweep_kernel",),
 }
 PROBE = "neg_kernel"

@@ -17,7 +17,9 @@ pytestmark = pytest.mark.gpu
 U_TOL = 2e-6  # max |U_gpu - U_oracle| entrywise (FP32 mesh of up to 190 MZIs)
 
 
-@pytest.mark.parametrize("m,Bn", [(12, 64), (20, 32), (5, 7), (2, 3), (32, 4)])
+# (12, 4096) and (20, 1100): more samples than one resident round of
+# workgroups, so the factors are formed once and shared
+@pytest.mark.parametrize("m,Bn", [(12, 64), (20, 32), (5, 7), (2, 3), (32, 4), (12, 4096), (20, 1100)])
 def test_mesh_forward(m, Bn):
     rng = np.random.default_rng(m)
     theta = rng.uniform(0, 2 * np.pi, m * (m - 1)).astype(np.float32)
