@@ -446,8 +446,9 @@ SLOS_API int fock_fidelity_kernel(int m, const int32_t* occ, const float* U1, in
 SLOS_API int mesh_workspace_bytes(int m, int B, size_t* bytes);
 
 /* U (device, complex, [B][m][m]) <- U(x_b, theta).  x: device [B][m] or NULL.
- * ws: at least mesh_workspace_bytes(m, B) bytes (checked; the forward forms
- * its factors on chip and leaves the workspace untouched). */
+ * ws: at least mesh_workspace_bytes(m, B) bytes (checked).  Batches of up to
+ * two samples per compute unit form the mesh factors on chip and leave the
+ * workspace untouched; larger ones form them once into the workspace. */
 SLOS_API int mesh_to_unitary(int m, int B, const float* theta, const float* x, float enc_scale,
                     float* U, void* ws, size_t ws_bytes, void* stream);
 
